@@ -1,0 +1,182 @@
+/*
+ * sap.h -- C ABI of the MI355X (gfx950) split-and-parallelize (SaP) solver
+ * for dense banded linear systems A x = b.
+ *
+ * Method: Li, Serban and Negrut, "Analysis of a splitting approach for the
+ * parallel solution of linear systems on GPU cards", arXiv:1509.07919.
+ *   - Sec. 2.1 (eq:LeftRightSpikes, eq:diag-sys, eq:spike-sys,
+ *     eq:SPIKE_reduced_system, eq:solveTopBottom and the purification
+ *     equations): partition A into P diagonal blocks A_i, factor each, and
+ *     couple neighbouring blocks through the truncated spike tips.
+ *   - Sec. 2.1.1: decoupled (SaP-D, M = diag(A_i)) and coupled (SaP-C,
+ *     truncated reduced system + purification) preconditioners inside an
+ *     outer left-preconditioned BiCGStab(2).
+ *   - Sec. 2.2, pivot-boosting paragraph: block LU/UL without pivoting; a
+ *     pivot whose magnitude falls below a threshold is boosted.
+ *   - Sec. 3.1: partition sizes, band storage, LU/UL factorizations and the
+ *     mixed-precision strategy (single-precision preconditioner, double-
+ *     precision Krylov loop).
+ *
+ * Conventions for every entry point
+ *   - All vector and matrix pointers are DEVICE pointers (HIP device memory
+ *     of the current device) unless marked "host".
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Work is enqueued on it in order; entry points that must read a device
+ *     scalar (sap_solve, sap_solve_adjoint, sap_handle_status) synchronise
+ *     on that stream only.
+ *   - Return value: SAP_OK (0), SAP_NOT_CONVERGED (1, a warning) or a
+ *     negative error code.  On error, sap_last_error() gives a message for
+ *     the calling thread.  No C++ exception ever crosses this boundary.
+ *
+ * Band layout of A (Sec. 3.1, "Matrix storage"): the N x (2K+1) "tall and
+ * thin" array stored column-major.  As a flat array of (2K+1)*N doubles,
+ * storage column q (0..2K) is contiguous and holds a[c+q-K][c] at index
+ * q*N + c; the diagonal is storage column K.  Slots whose row c+q-K lies
+ * outside [0, N) are padding: never read, may hold any value (even NaN).
+ */
+#ifndef SAP_H_
+#define SAP_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define SAP_OK              0
+#define SAP_NOT_CONVERGED   1   /* warning: x holds the last iterate      */
+#define SAP_ERR_INVALID    -1   /* bad argument (see sap_last_error)       */
+#define SAP_ERR_NOSPACE    -2   /* workspace smaller than required         */
+#define SAP_ERR_HIP        -3   /* a HIP runtime call failed               */
+#define SAP_ERR_BREAKDOWN  -4   /* BiCGStab(2): rho0, gamma or sigma = 0   */
+#define SAP_ERR_SINGULAR   -5   /* zero pivot (boosting off) / singular    */
+                                /* reduced matrix                          */
+#define SAP_ERR_STATE      -6   /* call out of order (e.g. solve before    */
+                                /* factor)                                 */
+
+/* preconditioner mode, Sec. 2.1.1 */
+#define SAP_DECOUPLED 0         /* SaP-D: M^{-1} = D^{-1}                    */
+#define SAP_COUPLED   1         /* SaP-C: truncated spikes + purification    */
+
+/* precision of factors, spike tips, reduced matrices and sweeps (Sec. 3.1,
+ * "Mixed Precision Strategy").  The Krylov loop is always FP64. */
+#define SAP_PREC_FP64 0
+#define SAP_PREC_FP32 1
+
+typedef struct sap_options {
+    int64_t n;            /* matrix order N >= 1                            */
+    int32_t k;            /* half-bandwidth K, 0 <= K < N, K <= 255         */
+    int32_t p;            /* partitions P, 1 <= P <= N (SaP-C: N/P >= 2K)   */
+    int32_t mode;         /* SAP_DECOUPLED or SAP_COUPLED                   */
+    int32_t factor_prec;  /* SAP_PREC_FP64 or SAP_PREC_FP32                 */
+    double  boost_eps;    /* pivot boost: tau_i = boost_eps * max|A_i|.      */
+                          /*  0 -> unit roundoff of factor_prec (2^-52 or    */
+                          /*  2^-23); < 0 disables boosting.                 */
+    int32_t adjoint;      /* nonzero: also keep the transposed factor copies */
+                          /*  needed by sap_solve_adjoint                    */
+    int32_t reserved;     /* must be 0                                      */
+} sap_options;
+
+typedef struct sap_stats {
+    double  iters;             /* Krylov-operator applications / 4: BiCGStab(2)
+                                  iterations in quarters (Sec. 4.1.1)          */
+    double  rel_resid_true;    /* ||b - A x||_2 / ||b||_2 at exit             */
+    double  rel_resid_precond; /* recursive ||M^{-1} r|| / ||M^{-1} b||        */
+    int32_t converged;         /* 1 if rel_resid_true <= tol                  */
+    int32_t n_boosted;         /* pivots boosted during sap_factor            */
+    int32_t restarts;          /* restarts after a failed true-residual check */
+    int32_t n_apply;           /* Krylov-operator applications                */
+    float   t_factor_ms;       /* device time of the last sap_factor          */
+    float   t_lu_ms;           /*   of which block LU/UL (T_LU)               */
+    float   t_tips_ms;         /*   of which B/C, spike tips and reduced      */
+                               /*   factorization (T_BC + T_SPK + T_LUrdcd)   */
+    float   t_solve_ms;        /* device time of this solve (T_Kry)           */
+} sap_stats;
+
+typedef struct sap_handle_ *sap_handle;
+
+/* Bytes of device workspace sap_create needs for these options.  Returns
+ * SAP_ERR_INVALID for invalid options. */
+int sap_workspace_bytes(const sap_options *opt, size_t *bytes /* host */);
+
+/* Validate options, compute the partition (Sec. 3.1: the first
+ * P_r = N - P*floor(N/P) blocks get floor(N/P)+1 rows, the rest floor(N/P))
+ * and carve the caller's workspace.  `workspace` is device memory of at
+ * least sap_workspace_bytes() bytes, 256-byte aligned, owned by the caller
+ * and borrowed by the handle until sap_destroy.  The handle itself and a
+ * small pinned host buffer are owned by the library.  No device work. */
+int sap_create(const sap_options *opt, void *workspace, size_t ws_bytes,
+               sap_handle *out /* host */);
+
+/* Numeric factorization (Sec. 2.1 and 3.1): per-block max-norm, LU of every
+ * A_i without pivoting but with pivot boosting, and for SaP-C the UL of
+ * every A_i, the coupling blocks B_i, C_{i+1}, the spike tips
+ *   V_i^(b)     = U_bb^{-1} L_bb^{-1} B_i        (bottom corners of LU(A_i))
+ *   W_{i+1}^(t) = L'_tt^{-1} U'_tt^{-1} C_{i+1}  (top corners of UL(A_{i+1}))
+ * and Rbar_i = I - W_{i+1}^(t) V_i^(b) with its inverse (LU with partial
+ * pivoting).  `a_band` (N*(2K+1) doubles, band layout) is BORROWED: it is
+ * read again by every solve and must stay unchanged until the next
+ * sap_factor or sap_destroy.  May be called again with new values.
+ * Enqueue-only: device-side failures (zero pivot with boosting off,
+ * singular Rbar) are reported by the next solve or by sap_handle_status. */
+int sap_factor(sap_handle h, const double *a_band, void *stream);
+
+/* Solve A x = b with left-preconditioned BiCGStab(2) (Sleijpen-Fokkema),
+ * x0 = 0, preconditioner from the last sap_factor.  Exit tests at the three
+ * exit points per iteration; a candidate exit is accepted only when the true
+ * relative residual ||b - A x||/||b|| <= tol, otherwise the iteration
+ * restarts from the current x with the recomputed residual.  maxit bounds
+ * the BiCGStab(2) iterations.  b and x: N doubles each, must not overlap.
+ * b = 0 gives x = 0 at once.  Returns SAP_OK, SAP_NOT_CONVERGED (x = last
+ * iterate), SAP_ERR_BREAKDOWN, SAP_ERR_SINGULAR or SAP_ERR_STATE.
+ * `st` (host, nullable) receives the statistics. */
+int sap_solve(sap_handle h, const double *b, double *x, double tol,
+              int32_t maxit, void *stream, sap_stats *st);
+
+/* Adjoint solve A^T lambda = g with the same Krylov method, the transposed
+ * banded SpMV and the exact transpose M^{-T} of the preconditioner built by
+ * sap_factor (its factors and tips, no refactorization).  Needs
+ * opt.adjoint != 0 at sap_create.  Same conventions as sap_solve. */
+int sap_solve_adjoint(sap_handle h, const double *g, double *lambda,
+                      double tol, int32_t maxit, void *stream, sap_stats *st);
+
+/* Band of dL/dA = -lambda x^T: writes g_band[(K+r-c)*N + c] = -lambda_r x_c
+ * for every band slot inside the matrix and 0 into padding slots.  With
+ * lambda = A^{-T} dL/dx this is the gradient of L(x(A)) restricted to the
+ * band; dL/db is lambda itself.  g_band: (2K+1)*N doubles. */
+int sap_band_grad(sap_handle h, const double *lambda, const double *x,
+                  double *g_band, void *stream);
+
+/* Device-side status of the last factorization, synchronising `stream`:
+ * SAP_OK or SAP_ERR_SINGULAR; n_boosted (host, nullable) gets the number of
+ * boosted pivots. */
+int sap_handle_status(sap_handle h, void *stream, int32_t *n_boosted);
+
+/* Single steps of the hot path, for parity testing and benchmarking.
+ *   sap_spmv:          y = A v (trans = 0) or A^T v (trans = 1), FP64.
+ *   sap_precond_apply: z = M^{-1} r (trans = 0) or M^{-T} r (trans = 1),
+ *                      r and z FP64, arithmetic in the factor precision.
+ * Both need a completed sap_factor; v/y and r/z must not overlap. */
+int sap_spmv(sap_handle h, const double *v, double *y, int32_t trans,
+             void *stream);
+int sap_precond_apply(sap_handle h, const double *r, double *z,
+                      int32_t trans, void *stream);
+
+/* Copy the SaP-C interface matrices of interface i (0 <= i < P-1, between
+ * blocks i and i+1) into host arrays of K*K doubles, row-major: V_i^(b),
+ * W_{i+1}^(t) and Rbar_i.  Any pointer may be NULL.  Synchronises. */
+int sap_get_tips(sap_handle h, int32_t i, double *v, double *w, double *rbar,
+                 void *stream);
+
+/* Release the handle (not the caller's workspace or matrix). */
+int sap_destroy(sap_handle h);
+
+/* Message for the last error status returned on this thread. */
+const char *sap_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SAP_H_ */

@@ -1,0 +1,399 @@
+// Bandwidth-bound kernels of the solve: banded SpMV (and A^T), the band of
+// the gradient -lambda x^T, the SaP-C interface correction, and the fused
+// vector updates + dot products of BiCGStab(2).
+#include "sap_internal.h"
+
+namespace sap {
+
+// --------------------------------------------------------------- SpMV
+// y_r = sum_q band[q*n + c] v_c with c = r + K - q (A v), or
+// y_c = sum_q band[q*n + c] v_{c+q-K} (A^T v).  One thread per output; for a
+// fixed q consecutive threads read consecutive band entries, and the v tile
+// [r0-K, r0+256+K) is staged once in LDS.  Optional residual form b - A v.
+__global__ __launch_bounds__(256) void k_spmv(const double *__restrict__ band, int64_t n,
+                                              int k, const double *__restrict__ v,
+                                              const double *__restrict__ b,
+                                              double *__restrict__ y, int trans)
+{
+    __shared__ double vt[256 + 2 * kMaxK];
+    const int64_t r0 = (int64_t)blockIdx.x * 256;
+    const int tid = threadIdx.x;
+    for (int i = tid; i < 256 + 2 * k; i += 256) {
+        const int64_t g = r0 - k + i;
+        vt[i] = (g >= 0 && g < n) ? v[g] : 0.0;
+    }
+    __syncthreads();
+    const int64_t r = r0 + tid;
+    if (r >= n) return;
+    double acc0 = 0.0, acc1 = 0.0;
+    const int w = 2 * k + 1;
+    if (!trans) {
+        // a[r][c] at band[(k + r - c)*n + c]; c = r + k - q in [0, n)
+        const int qlo = (int)max((int64_t)0, r + k - (n - 1));
+        const int qhi = (int)min((int64_t)(w - 1), r + k);
+        int q = qlo;
+        for (; q + 1 <= qhi; q += 2) {
+            acc0 = fma(band[(int64_t)q * n + (r + k - q)], vt[tid + 2 * k - q], acc0);
+            acc1 = fma(band[(int64_t)(q + 1) * n + (r + k - q - 1)], vt[tid + 2 * k - q - 1], acc1);
+        }
+        if (q <= qhi) acc0 = fma(band[(int64_t)q * n + (r + k - q)], vt[tid + 2 * k - q], acc0);
+    } else {
+        // a[rr][r] at band[q*n + r] with rr = r + q - k in [0, n)
+        const int qlo = (int)max((int64_t)0, (int64_t)k - r);
+        const int qhi = (int)min((int64_t)(w - 1), n - 1 - r + k);
+        int q = qlo;
+        for (; q + 1 <= qhi; q += 2) {
+            acc0 = fma(band[(int64_t)q * n + r], vt[tid + q], acc0);
+            acc1 = fma(band[(int64_t)(q + 1) * n + r], vt[tid + q + 1], acc1);
+        }
+        if (q <= qhi) acc0 = fma(band[(int64_t)q * n + r], vt[tid + q], acc0);
+    }
+    const double acc = acc0 + acc1;
+    y[r] = b ? b[r] - acc : acc;
+}
+
+hipError_t launch_spmv(const double *band, int64_t n, int k, const double *v,
+                       const double *b, double *y, int trans, hipStream_t s)
+{
+    const int64_t nblk = (n + 255) / 256;
+    hipLaunchKernelGGL(k_spmv, dim3((unsigned)nblk), dim3(256), 0, s, band, n, k, v, b, y, trans);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------ band gradient
+__global__ __launch_bounds__(256) void k_band_grad(int64_t n, int k,
+                                                   const double *__restrict__ lam,
+                                                   const double *__restrict__ x,
+                                                   double *__restrict__ g)
+{
+    const int64_t total = (int64_t)(2 * k + 1) * n;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * 256) {
+        const int64_t q = e / n, c = e - q * n;
+        const int64_t r = c + q - k;
+        g[e] = (r >= 0 && r < n) ? -lam[r] * x[c] : 0.0;
+    }
+}
+
+hipError_t launch_band_grad(int64_t n, int k, const double *lam, const double *x, double *g,
+                            hipStream_t s)
+{
+    const int64_t total = (int64_t)(2 * k + 1) * n;
+    const int64_t nblk = min((total + 255) / 256, (int64_t)65536);
+    hipLaunchKernelGGL(k_band_grad, dim3((unsigned)nblk), dim3(256), 0, s, n, k, lam, x, g);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------ SaP-C correction
+// Interface i couples blocks i and i+1 (s1 = first row of block i+1).
+// Forward (eq:solveTopBottom and purification), from g = D^{-1} r:
+//   y = Rbar^{-1}(g^(t)_{i+1} - W g^(b)_i),  z = g^(b)_i - V y
+//   dbot_i = -B_i y,  dtop_{i+1} = -C_{i+1} z     (added to r before D^{-1})
+// Transposed, from h = D^{-T} s:
+//   ybar = -B^T h^(b)_i,  zbar = -C^T h^(t)_{i+1},  tbar = Rbar^{-T}(ybar - V^T zbar)
+//   dtop_{i+1} = tbar,    dbot_i = zbar - W^T tbar  (added to s before D^{-T})
+template <typename T>
+__global__ __launch_bounds__(256) void k_correction(CorrArgs<T> a)
+{
+    const int i = blockIdx.x;
+    const int k = a.pt.k;
+    const int64_t s1 = a.pt.starts[i + 1];
+    const int64_t kk = (int64_t)k * k;
+    const T *B = a.B + i * kk, *C = a.C + i * kk, *V = a.V + i * kk, *W = a.W + i * kk;
+    const T *RI = a.Rinv + i * kk;
+    __shared__ T vb[kMaxK], vt[kMaxK], w1[kMaxK], w2[kMaxK], w3[kMaxK];
+    const int t = threadIdx.x;
+    if (t < k) {
+        vb[t] = a.g[s1 - k + t];
+        vt[t] = a.g[s1 + t];
+    }
+    __syncthreads();
+    T *dbot = a.dbot + (int64_t)i * k;          // bottom rows of block i
+    T *dtop = a.dtop + (int64_t)(i + 1) * k;    // top rows of block i+1
+    if (!a.trans) {
+        if (t < k) {
+            T s = vt[t];
+            for (int c = 0; c < k; ++c) s = fma(-W[t * k + c], vb[c], s);
+            w1[t] = s;
+        }
+        __syncthreads();
+        if (t < k) {
+            T s = T(0);
+            for (int c = 0; c < k; ++c) s = fma(RI[t * k + c], w1[c], s);
+            w2[t] = s;                                   // y
+        }
+        __syncthreads();
+        if (t < k) {
+            T s = vb[t];
+            for (int c = 0; c < k; ++c) s = fma(-V[t * k + c], w2[c], s);
+            w3[t] = s;                                   // z
+        }
+        __syncthreads();
+        if (t < k) {
+            T sb = T(0), st = T(0);
+            for (int c = 0; c < k; ++c) {
+                sb = fma(B[t * k + c], w2[c], sb);
+                st = fma(C[t * k + c], w3[c], st);
+            }
+            dbot[t] = -sb;
+            dtop[t] = -st;
+        }
+    } else {
+        if (t < k) {
+            T sy = T(0), sz = T(0);
+            for (int c = 0; c < k; ++c) {
+                sy = fma(B[c * k + t], vb[c], sy);
+                sz = fma(C[c * k + t], vt[c], sz);
+            }
+            w1[t] = -sy;                                 // ybar
+            w2[t] = -sz;                                 // zbar
+        }
+        __syncthreads();
+        if (t < k) {
+            T s = w1[t];
+            for (int c = 0; c < k; ++c) s = fma(-V[c * k + t], w2[c], s);
+            w3[t] = s;                                   // ybar - V^T zbar
+        }
+        __syncthreads();
+        if (t < k) {
+            T s = T(0);
+            for (int c = 0; c < k; ++c) s = fma(RI[c * k + t], w3[c], s);
+            w1[t] = s;                                   // tbar
+        }
+        __syncthreads();
+        if (t < k) {
+            T s = w2[t];
+            for (int c = 0; c < k; ++c) s = fma(-W[c * k + t], w1[c], s);
+            dbot[t] = s;
+            dtop[t] = w1[t];
+        }
+    }
+}
+
+template <typename T>
+hipError_t launch_correction(const CorrArgs<T> &a, hipStream_t s)
+{
+    if (a.pt.p < 2 || a.pt.k == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_correction<T>, dim3(a.pt.p - 1), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+template hipError_t launch_correction<float>(const CorrArgs<float> &, hipStream_t);
+template hipError_t launch_correction<double>(const CorrArgs<double> &, hipStream_t);
+
+// ------------------------------------------------------------ reductions
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    return v;
+}
+
+// Scalar recurrences of BiCGStab(2) (Sleijpen-Fokkema), run by one thread
+// once the dots d[] of a launch are complete.
+__device__ void scalar_op(int op, const double *d, double *sc, double *host)
+{
+    auto brk = [&](double code) {
+        if (sc[S_BREAK] == 0.0) sc[S_BREAK] = code;
+    };
+    auto prep_j0 = [&](double rho1) {     // rho0 = -omega rho0; beta; rho0 = rho1
+        sc[S_RHO0] = -sc[S_OMEGA] * sc[S_RHO0];
+        if (sc[S_RHO0] == 0.0) brk(1.0);
+        sc[S_BETA] = sc[S_ALPHA] * rho1 / sc[S_RHO0];
+        sc[S_RHO0] = rho1;
+    };
+    bool publish = false;
+    switch (op) {
+    case OP_INIT:
+        sc[S_RHO0] = 1.0; sc[S_ALPHA] = 0.0; sc[S_OMEGA] = 1.0; sc[S_BREAK] = 0.0;
+        sc[S_NRM2] = d[1]; publish = true;
+        prep_j0(d[0]);
+        break;
+    case OP_GAMMA:
+        sc[S_GAMMA] = d[0];
+        if (d[0] == 0.0) brk(2.0);
+        sc[S_ALPHA] = sc[S_RHO0] / d[0];
+        break;
+    case OP_EXIT:
+    case OP_NORM:
+        sc[S_NRM2] = d[0]; publish = true;
+        break;
+    case OP_RHO:
+        if (sc[S_RHO0] == 0.0) brk(1.0);
+        sc[S_BETA] = sc[S_ALPHA] * d[0] / sc[S_RHO0];
+        sc[S_RHO0] = d[0];
+        break;
+    case OP_MR1:
+        sc[S_SIGMA1] = d[0];
+        if (d[0] == 0.0) brk(3.0);
+        sc[S_GP1] = d[1] / d[0];
+        sc[S_TAU12] = d[2] / d[0];
+        break;
+    case OP_MR2: {
+        sc[S_SIGMA2] = d[0];
+        if (d[0] == 0.0) brk(3.0);
+        const double gp2 = d[1] / d[0];
+        sc[S_GP2] = gp2;
+        sc[S_G2] = gp2;
+        sc[S_OMEGA] = gp2;
+        sc[S_G1] = sc[S_GP1] - sc[S_TAU12] * gp2;
+        sc[S_GPP1] = gp2;
+        break;
+    }
+    case OP_FINAL:
+        sc[S_NRM2] = d[0]; publish = true;
+        prep_j0(d[1]);
+        break;
+    default:
+        break;
+    }
+    if (host) {
+        if (publish) host[H_NRM2] = sc[S_NRM2];
+        host[H_BREAK] = sc[S_BREAK];
+    }
+}
+
+// Block-reduce up to three per-thread sums, store this block's partials and
+// let the last block to finish combine all partials in a fixed order (so the
+// result is bitwise reproducible) and run the scalar recurrence.
+__device__ void finish_dots(const DotArgs &a, double l0, double l1, double l2)
+{
+    __shared__ double red[3][4];
+    __shared__ bool last;
+    const int tid = threadIdx.x, wid = tid >> 6, lane = tid & 63;
+    const double s0 = wave_sum(l0), s1 = wave_sum(l1), s2 = wave_sum(l2);
+    if (lane == 0) { red[0][wid] = s0; red[1][wid] = s1; red[2][wid] = s2; }
+    __syncthreads();
+    if (tid == 0) {
+        for (int d = 0; d < 3; ++d)
+            a.partial[blockIdx.x * 3 + d] = (red[d][0] + red[d][1]) + (red[d][2] + red[d][3]);
+        __threadfence();
+        const unsigned ticket = atomicAdd(a.counter, 1u);
+        last = ticket == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    __shared__ double tot[3][256];
+    for (int d = 0; d < 3; ++d) {
+        double s = 0.0;
+        for (int b = tid; b < (int)gridDim.x; b += 256) s += a.partial[b * 3 + d];
+        tot[d][tid] = s;
+    }
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (tid < w)
+            for (int d = 0; d < 3; ++d) tot[d][tid] += tot[d][tid + w];
+        __syncthreads();
+    }
+    if (tid == 0) {
+        const double dd[3] = {tot[0][0], tot[1][0], tot[2][0]};
+        scalar_op(a.op, dd, a.sc, a.host);
+        *a.counter = 0u;
+        __threadfence_system();
+    }
+}
+
+__global__ __launch_bounds__(256) void k_dots(DotArgs a)
+{
+    double l[3] = {0.0, 0.0, 0.0};
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < a.n;
+         i += (int64_t)gridDim.x * 256) {
+        for (int d = 0; d < 3; ++d)
+            if (d < a.nd) l[d] = fma(a.x[d][i], a.y[d][i], l[d]);
+    }
+    finish_dots(a, l[0], l[1], l[2]);
+}
+
+hipError_t launch_dots(const DotArgs &a, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_dots, dim3(kDotBlocks), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_update(UpdArgs a)
+{
+    const double *sc = a.dots.sc;
+    const double beta = sc[S_BETA], alpha = sc[S_ALPHA], tau12 = sc[S_TAU12];
+    const double g1 = sc[S_G1], g2 = sc[S_G2], gp1 = sc[S_GP1], gp2 = sc[S_GP2],
+                 gpp1 = sc[S_GPP1];
+    double l0 = 0.0, l1 = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < a.n;
+         i += (int64_t)gridDim.x * 256) {
+        switch (a.kind) {
+        case UPD_U0:
+            a.u0[i] = a.r0[i] - beta * a.u0[i];
+            break;
+        case UPD_J0: {
+            const double r = a.r0[i] - alpha * a.u1[i];
+            a.r0[i] = r;
+            a.x[i] += alpha * a.u0[i];
+            l0 = fma(r, r, l0);
+            break;
+        }
+        case UPD_U01:
+            a.u0[i] = a.r0[i] - beta * a.u0[i];
+            a.u1[i] = a.r1[i] - beta * a.u1[i];
+            break;
+        case UPD_J1: {
+            const double r = a.r0[i] - alpha * a.u1[i];
+            a.r0[i] = r;
+            a.r1[i] -= alpha * a.u2[i];
+            a.x[i] += alpha * a.u0[i];
+            l0 = fma(r, r, l0);
+            break;
+        }
+        case UPD_MR2: {
+            const double r2 = a.r2[i] - tau12 * a.r1[i];
+            a.r2[i] = r2;
+            l0 = fma(r2, r2, l0);
+            l1 = fma(a.r0[i], r2, l1);
+            break;
+        }
+        case UPD_FINAL: {
+            const double r0 = a.r0[i], r1 = a.r1[i];
+            a.x[i] += g1 * r0 + gpp1 * r1;
+            const double rn = r0 - gp2 * a.r2[i] - gp1 * r1;
+            a.r0[i] = rn;
+            a.u0[i] = a.u0[i] - g2 * a.u2[i] - g1 * a.u1[i];
+            l0 = fma(rn, rn, l0);
+            l1 = fma(rn, a.rt[i], l1);
+            break;
+        }
+        case UPD_RESTART: {
+            const double r = a.r0[i];
+            a.rt[i] = r;
+            a.u0[i] = 0.0;
+            l0 = fma(r, r, l0);        // (r0, rt) = (r0, r0)
+            break;
+        }
+        default:
+            break;
+        }
+    }
+    if (a.dots.nd == 0) return;
+    if (a.kind == UPD_RESTART) l1 = l0;
+    // dot order per kind: J0/J1 -> (r0,r0); MR2 -> (r2,r2),(r0,r2);
+    // FINAL -> (r0,r0),(r0,rt); RESTART -> (r0,rt),(r0,r0)
+    finish_dots(a.dots, l0, l1, 0.0);
+}
+
+hipError_t launch_update(const UpdArgs &a, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_update, dim3(kDotBlocks), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+__global__ void k_fill(double *v, double val, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * 256)
+        v[i] = val;
+}
+
+hipError_t launch_fill(double *v, double val, int64_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_fill, dim3(kDotBlocks), dim3(256), 0, s, v, val, n);
+    return hipGetLastError();
+}
+
+}  // namespace sap

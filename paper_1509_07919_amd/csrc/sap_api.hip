@@ -1,0 +1,622 @@
+// C ABI of libsap: argument validation, workspace layout, the factorization
+// sequence and the BiCGStab(2) driver.  The host only sequences kernels and
+// reads one device scalar per exit point; all arithmetic runs on the GPU.
+#include "sap.h"
+#include "sap_internal.h"
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+using namespace sap;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg)
+{
+    g_err = msg;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                               \
+    do {                                                                            \
+        hipError_t e_ = (expr);                                                     \
+        if (e_ != hipSuccess)                                                       \
+            return fail(SAP_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+struct Layout {
+    size_t starts, partial, status, Lc, Uc, Lr, Ur, corner, B, C, V, W, Rbar, Rlu, Rinv, piv,
+        gT, yT, dtop, dbot, kv, dpart, counter, sc, total;
+};
+
+bool coupled_active(const sap_options &o) { return o.mode == SAP_COUPLED && o.p > 1 && o.k > 0; }
+
+int validate(const sap_options *o)
+{
+    if (!o) return fail(SAP_ERR_INVALID, "options pointer is null");
+    if (o->n < 1) return fail(SAP_ERR_INVALID, "N must be >= 1");
+    if (o->k < 0 || o->k > kMaxK) return fail(SAP_ERR_INVALID, "K must be in [0, 255]");
+    if (o->k >= o->n && !(o->n == 1 && o->k == 0))
+        return fail(SAP_ERR_INVALID, "K must be < N");
+    if (o->p < 1 || (int64_t)o->p > o->n) return fail(SAP_ERR_INVALID, "P must be in [1, N]");
+    if (o->mode != SAP_DECOUPLED && o->mode != SAP_COUPLED)
+        return fail(SAP_ERR_INVALID, "mode must be SAP_DECOUPLED or SAP_COUPLED");
+    if (o->factor_prec != SAP_PREC_FP64 && o->factor_prec != SAP_PREC_FP32)
+        return fail(SAP_ERR_INVALID, "factor_prec must be SAP_PREC_FP64 or SAP_PREC_FP32");
+    if (o->reserved != 0) return fail(SAP_ERR_INVALID, "reserved field must be 0");
+    if (o->factor_prec == SAP_PREC_FP64 && o->k >= 128)
+        return fail(SAP_ERR_INVALID, "FP64 factors support K <= 127");
+    if (o->mode == SAP_COUPLED && o->p > 1 && o->n / o->p < 2 * (int64_t)o->k)
+        return fail(SAP_ERR_INVALID, "coupled mode needs floor(N/P) >= 2K");
+    if (std::isnan(o->boost_eps)) return fail(SAP_ERR_INVALID, "boost_eps is NaN");
+    return SAP_OK;
+}
+
+Layout layout_for(const sap_options &o)
+{
+    Layout L{};
+    const int64_t n = o.n;
+    const int k = o.k, p = o.p;
+    const size_t sf = o.factor_prec == SAP_PREC_FP32 ? 4 : 8;
+    const int64_t maxnb = n / p + (n % p ? 1 : 0);
+    const int nchunk = (int)((maxnb + 255) / 256);
+    const bool cpl = coupled_active(o);
+    const size_t kk = (size_t)k * k;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = off;
+        off = align_up(off + bytes);
+        return at;
+    };
+    L.starts = take(sizeof(int64_t) * (p + 1));
+    L.partial = take(sizeof(double) * (size_t)p * nchunk);
+    L.status = take(64);
+    L.Lc = take(sf * n * (k + 1));
+    L.Uc = take(sf * n * (k + 1));
+    L.Lr = o.adjoint ? take(sf * n * (k + 1)) : 0;
+    L.Ur = o.adjoint ? take(sf * n * (k + 1)) : 0;
+    const size_t ni = cpl ? (size_t)(p - 1) : 0;
+    L.corner = cpl ? take(sf * p * kk) : 0;
+    L.B = cpl ? take(sf * ni * kk) : 0;
+    L.C = cpl ? take(sf * ni * kk) : 0;
+    L.V = cpl ? take(sf * ni * kk) : 0;
+    L.W = cpl ? take(sf * ni * kk) : 0;
+    L.Rbar = cpl ? take(sf * ni * kk) : 0;
+    L.Rlu = cpl ? take(sf * ni * kk) : 0;
+    L.Rinv = cpl ? take(sf * ni * kk) : 0;
+    L.piv = cpl ? take(sizeof(int) * ni * k) : 0;
+    L.gT = take(sf * n);
+    L.yT = take(sf * n);
+    L.dtop = cpl ? take(sf * (size_t)p * k) : 0;
+    L.dbot = cpl ? take(sf * (size_t)p * k) : 0;
+    L.kv = take(sizeof(double) * 8 * (size_t)n);
+    L.dpart = take(sizeof(double) * 3 * kDotBlocks);
+    L.counter = take(64);
+    L.sc = take(sizeof(double) * kScalars);
+    L.total = off;
+    return L;
+}
+
+}  // namespace
+
+struct sap_handle_ {
+    sap_options opt;
+    bool coupled, fp32;
+    Partition pt;
+    int nchunk;
+    unsigned char *ws;
+    Layout L;
+    int64_t *h_starts;       // pinned copy of the partition
+    double *h_slots;         // pinned, mapped: written by reduction kernels
+    double *d_slots;         // device alias of h_slots
+    int32_t *h_status;       // pinned
+    const double *a_band;
+    bool factored, starts_uploaded;
+    hipEvent_t ev[5];        // factor start / after LU / end, solve start / end
+    float t_factor, t_lu, t_tips;
+
+    template <typename T> T *ptr(size_t off) { return reinterpret_cast<T *>(ws + off); }
+    double *kvec(int i) { return ptr<double>(L.kv) + (size_t)i * opt.n; }
+};
+
+namespace {
+
+enum KVec { KV_R0 = 0, KV_R1, KV_R2, KV_U0, KV_U1, KV_U2, KV_RT, KV_T };
+
+// ------------------------------------------------------------------ sweeps
+template <typename T>
+int dinv(sap_handle h, int trans, const double *xin, const T *dtop, const T *dbot,
+         double *dout, T *tout, hipStream_t s)
+{
+    SweepArgs<T> a1{};
+    a1.pt = h->pt;
+    a1.xin = xin;
+    a1.dtop = dtop;
+    a1.dbot = dbot;
+    a1.tout = h->ptr<T>(h->L.yT);
+    SweepArgs<T> a2{};
+    a2.pt = h->pt;
+    a2.tin = h->ptr<T>(h->L.yT);
+    a2.dout = dout;
+    a2.tout = tout;
+    if (!trans) {            // L (forward, unit) then U (backward)
+        a1.F = h->ptr<T>(h->L.Lc); a1.fwd = 1; a1.diag = 0;
+        a2.F = h->ptr<T>(h->L.Uc); a2.fwd = 0; a2.diag = 1;
+    } else {                 // U^T (forward) then L^T (backward, unit)
+        a1.F = h->ptr<T>(h->L.Ur); a1.fwd = 1; a1.diag = 1;
+        a2.F = h->ptr<T>(h->L.Lr); a2.fwd = 0; a2.diag = 0;
+    }
+    HIP_TRY(launch_sweep<T>(a1, s));
+    HIP_TRY(launch_sweep<T>(a2, s));
+    return SAP_OK;
+}
+
+template <typename T>
+int precond_t(sap_handle h, int trans, const double *r, double *z, hipStream_t s)
+{
+    if (!h->coupled) return dinv<T>(h, trans, r, nullptr, nullptr, z, nullptr, s);
+    T *g = h->ptr<T>(h->L.gT);
+    T *dtop = h->ptr<T>(h->L.dtop), *dbot = h->ptr<T>(h->L.dbot);
+    int rc = dinv<T>(h, trans, r, nullptr, nullptr, nullptr, g, s);
+    if (rc) return rc;
+    CorrArgs<T> c{};
+    c.pt = h->pt;
+    c.g = g;
+    c.B = h->ptr<T>(h->L.B); c.C = h->ptr<T>(h->L.C);
+    c.V = h->ptr<T>(h->L.V); c.W = h->ptr<T>(h->L.W);
+    c.Rinv = h->ptr<T>(h->L.Rinv);
+    c.dtop = dtop; c.dbot = dbot;
+    c.trans = trans;
+    HIP_TRY(launch_correction<T>(c, s));
+    return dinv<T>(h, trans, r, dtop, dbot, z, nullptr, s);
+}
+
+int precond(sap_handle h, int trans, const double *r, double *z, hipStream_t s)
+{
+    return h->fp32 ? precond_t<float>(h, trans, r, z, s) : precond_t<double>(h, trans, r, z, s);
+}
+
+// Krylov operator  v -> M^{-1} A v  (or M^{-T} A^T v)
+int apply_op(sap_handle h, int trans, const double *v, double *out, hipStream_t s)
+{
+    double *t = h->kvec(KV_T);
+    HIP_TRY(launch_spmv(h->a_band, h->opt.n, h->opt.k, v, nullptr, t, trans, s));
+    return precond(h, trans, t, out, s);
+}
+
+DotArgs dot_args(sap_handle h, int op)
+{
+    DotArgs d{};
+    d.n = h->opt.n;
+    d.partial = h->ptr<double>(h->L.dpart);
+    d.counter = h->ptr<unsigned>(h->L.counter);
+    d.sc = h->ptr<double>(h->L.sc);
+    d.host = h->d_slots;
+    d.op = op;
+    return d;
+}
+
+int dots(sap_handle h, int op, std::initializer_list<std::pair<const double *, const double *>> pr,
+         hipStream_t s)
+{
+    DotArgs d = dot_args(h, op);
+    int i = 0;
+    for (auto &p : pr) { d.x[i] = p.first; d.y[i] = p.second; ++i; }
+    d.nd = i;
+    HIP_TRY(launch_dots(d, s));
+    return SAP_OK;
+}
+
+int update(sap_handle h, int kind, double *x, int op, int nd, hipStream_t s)
+{
+    UpdArgs u{};
+    u.kind = kind;
+    u.n = h->opt.n;
+    u.x = x;
+    u.r0 = h->kvec(KV_R0); u.r1 = h->kvec(KV_R1); u.r2 = h->kvec(KV_R2);
+    u.u0 = h->kvec(KV_U0); u.u1 = h->kvec(KV_U1); u.u2 = h->kvec(KV_U2);
+    u.rt = h->kvec(KV_RT);
+    u.dots = dot_args(h, op);
+    u.dots.nd = nd;
+    HIP_TRY(launch_update(u, s));
+    return SAP_OK;
+}
+
+int sync_read(sap_handle h, hipStream_t s, double *nrm2, double *brk)
+{
+    HIP_TRY(hipStreamSynchronize(s));
+    *nrm2 = h->h_slots[H_NRM2];
+    *brk = h->h_slots[H_BREAK];
+    return SAP_OK;
+}
+
+int read_factor_status(sap_handle h, hipStream_t s, int32_t *nboost, int32_t *singular)
+{
+    HIP_TRY(hipMemcpyAsync(h->h_status, h->ptr<int>(h->L.status), 2 * sizeof(int32_t),
+                           hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    *nboost = h->h_status[0];
+    *singular = h->h_status[1];
+    return SAP_OK;
+}
+
+#define TRY(expr)                 \
+    do {                          \
+        int rc_ = (expr);         \
+        if (rc_ < 0) return rc_;  \
+    } while (0)
+
+// Left-preconditioned BiCGStab(2), x0 = 0.
+int krylov(sap_handle h, int trans, const double *b, double *x, double tol, int32_t maxit,
+           hipStream_t s, sap_stats *st)
+{
+    if (!h->factored) return fail(SAP_ERR_STATE, "sap_factor has not been called");
+    if (!b || !x) return fail(SAP_ERR_INVALID, "null vector pointer");
+    if (!(tol > 0.0)) return fail(SAP_ERR_INVALID, "tol must be > 0");
+    if (maxit < 1) return fail(SAP_ERR_INVALID, "maxit must be >= 1");
+    if (trans && !h->opt.adjoint)
+        return fail(SAP_ERR_STATE, "handle was created without adjoint = 1");
+    const int64_t n = h->opt.n;
+    if ((const void *)b < (const void *)(x + n) && (const void *)x < (const void *)(b + n))
+        return fail(SAP_ERR_INVALID, "b and x overlap");
+
+    sap_stats loc{};
+    HIP_TRY(hipEventRecord(h->ev[3], s));
+    int32_t nboost = 0, singular = 0;
+    TRY(read_factor_status(h, s, &nboost, &singular));
+    loc.n_boosted = nboost;
+    if (singular) {
+        if (st) *st = loc;
+        return fail(SAP_ERR_SINGULAR, singular == 1 ? "zero pivot in a diagonal block (boosting disabled)"
+                                                    : "singular reduced matrix Rbar");
+    }
+    double *r0 = h->kvec(KV_R0), *r1 = h->kvec(KV_R1), *r2 = h->kvec(KV_R2);
+    double *u0 = h->kvec(KV_U0), *u1 = h->kvec(KV_U1), *u2 = h->kvec(KV_U2);
+    double *rt = h->kvec(KV_RT), *t = h->kvec(KV_T);
+    const double *A = h->a_band;
+    const int k = h->opt.k;
+    double nrm2 = 0, brk = 0;
+
+    TRY(dots(h, OP_NORM, {{b, b}}, s));
+    TRY(sync_read(h, s, &nrm2, &brk));
+    const double bnorm = std::sqrt(nrm2);
+    HIP_TRY(launch_fill(x, 0.0, n, s));
+    auto finish = [&](int code, const char *msg) {
+        HIP_TRY(hipEventRecord(h->ev[4], s));
+        HIP_TRY(hipEventSynchronize(h->ev[4]));
+        HIP_TRY(hipEventElapsedTime(&loc.t_solve_ms, h->ev[3], h->ev[4]));
+        loc.t_factor_ms = h->t_factor;
+        loc.t_lu_ms = h->t_lu;
+        loc.t_tips_ms = h->t_tips;
+        loc.iters = loc.n_apply / 4.0;
+        if (st) *st = loc;
+        if (code != SAP_OK && code != SAP_NOT_CONVERGED) return fail(code, msg);
+        if (code == SAP_NOT_CONVERGED) g_err = msg;
+        return code;
+    };
+    if (bnorm == 0.0) {
+        loc.converged = 1;
+        return finish(SAP_OK, "");
+    }
+
+    // r0 = M^{-1} b, rt = r0, u0 = 0, scalars reset
+    TRY(precond(h, trans, b, r0, s));
+    TRY(update(h, UPD_RESTART, x, OP_INIT, 2, s));
+    TRY(sync_read(h, s, &nrm2, &brk));
+    const double pnorm0 = std::sqrt(nrm2);
+    double thr = tol * pnorm0;
+    int napply = 0;
+
+    // exit test: returns 1 = converged, 2 = restarted, 0 = continue, < 0 error
+    auto exit_test = [&]() -> int {
+        TRY(sync_read(h, s, &nrm2, &brk));
+        if (brk != 0.0) return SAP_ERR_BREAKDOWN;
+        if (!std::isfinite(nrm2)) return SAP_ERR_BREAKDOWN;
+        loc.rel_resid_precond = std::sqrt(nrm2) / pnorm0;
+        if (std::sqrt(nrm2) > thr) return 0;
+        HIP_TRY(launch_spmv(A, n, k, x, b, t, trans, s));        // t = b - A x
+        TRY(dots(h, OP_NORM, {{t, t}}, s));
+        double tn2 = 0, b2 = 0;
+        TRY(sync_read(h, s, &tn2, &b2));
+        const double tn = std::sqrt(tn2);
+        loc.rel_resid_true = tn / bnorm;
+        if (loc.rel_resid_true <= tol) return 1;
+        TRY(precond(h, trans, t, r0, s));                        // restart
+        ++napply;
+        ++loc.restarts;
+        TRY(update(h, UPD_RESTART, x, OP_INIT, 2, s));
+        TRY(sync_read(h, s, &nrm2, &brk));
+        thr = tol * bnorm * std::sqrt(nrm2) / tn;
+        return 2;
+    };
+
+    int code = SAP_NOT_CONVERGED;
+    for (int32_t it = 0; it < maxit; ++it) {
+        int e;
+        // j = 0
+        TRY(update(h, UPD_U0, x, 0, 0, s));
+        TRY(apply_op(h, trans, u0, u1, s)); ++napply;
+        TRY(dots(h, OP_GAMMA, {{u1, rt}}, s));
+        TRY(update(h, UPD_J0, x, OP_EXIT, 1, s));
+        loc.n_apply = napply;
+        e = exit_test(); loc.n_apply = napply;
+        if (e < 0) return finish(e, "breakdown in BiCGStab(2)");
+        if (e == 1) { code = SAP_OK; break; }
+        if (e == 2) continue;
+        TRY(apply_op(h, trans, r0, r1, s)); ++napply;
+        // j = 1
+        TRY(dots(h, OP_RHO, {{r1, rt}}, s));
+        TRY(update(h, UPD_U01, x, 0, 0, s));
+        TRY(apply_op(h, trans, u1, u2, s)); ++napply;
+        TRY(dots(h, OP_GAMMA, {{u2, rt}}, s));
+        TRY(update(h, UPD_J1, x, OP_EXIT, 1, s));
+        loc.n_apply = napply;
+        e = exit_test(); loc.n_apply = napply;
+        if (e < 0) return finish(e, "breakdown in BiCGStab(2)");
+        if (e == 1) { code = SAP_OK; break; }
+        if (e == 2) continue;
+        TRY(apply_op(h, trans, r1, r2, s)); ++napply;
+        // minimal-residual part
+        TRY(dots(h, OP_MR1, {{r1, r1}, {r0, r1}, {r2, r1}}, s));
+        TRY(update(h, UPD_MR2, x, OP_MR2, 2, s));
+        TRY(update(h, UPD_FINAL, x, OP_FINAL, 2, s));
+        loc.n_apply = napply;
+        e = exit_test(); loc.n_apply = napply;
+        if (e < 0) return finish(e, "breakdown in BiCGStab(2)");
+        if (e == 1) { code = SAP_OK; break; }
+    }
+    loc.n_apply = napply;
+    if (code == SAP_OK) {
+        loc.converged = 1;
+        return finish(SAP_OK, "");
+    }
+    HIP_TRY(launch_spmv(A, n, k, x, b, t, trans, s));
+    TRY(dots(h, OP_NORM, {{t, t}}, s));
+    double tn2 = 0;
+    TRY(sync_read(h, s, &tn2, &brk));
+    loc.rel_resid_true = std::sqrt(tn2) / bnorm;
+    return finish(SAP_NOT_CONVERGED, "maximum number of iterations reached");
+}
+
+template <typename T>
+int factor_t(sap_handle h, const double *a_band, hipStream_t s)
+{
+    LuArgs<T> lu{};
+    lu.band = a_band;
+    lu.pt = h->pt;
+    lu.partial = h->ptr<double>(h->L.partial);
+    lu.nchunk = h->nchunk;
+    double eps = h->opt.boost_eps;
+    if (eps == 0.0) eps = h->fp32 ? std::ldexp(1.0, -23) : std::ldexp(1.0, -52);
+    lu.boost_eps = eps;
+    lu.Lc = h->ptr<T>(h->L.Lc);
+    lu.Uc = h->ptr<T>(h->L.Uc);
+    lu.Lr = h->opt.adjoint ? h->ptr<T>(h->L.Lr) : nullptr;
+    lu.Ur = h->opt.adjoint ? h->ptr<T>(h->L.Ur) : nullptr;
+    lu.corner = h->coupled ? h->ptr<T>(h->L.corner) : nullptr;
+    lu.status = h->ptr<int>(h->L.status);
+    lu.with_ul = h->coupled ? 1 : 0;
+    HIP_TRY(launch_banded_lu<T>(lu, s));
+    HIP_TRY(hipEventRecord(h->ev[1], s));
+    if (h->coupled) {
+        TipsArgs<T> ta{};
+        ta.band = a_band;
+        ta.pt = h->pt;
+        ta.Lc = lu.Lc; ta.Uc = lu.Uc; ta.corner = lu.corner;
+        ta.B = h->ptr<T>(h->L.B); ta.C = h->ptr<T>(h->L.C);
+        ta.V = h->ptr<T>(h->L.V); ta.W = h->ptr<T>(h->L.W);
+        ta.Rbar = h->ptr<T>(h->L.Rbar); ta.Rlu = h->ptr<T>(h->L.Rlu);
+        ta.Rinv = h->ptr<T>(h->L.Rinv);
+        ta.piv = h->ptr<int>(h->L.piv);
+        ta.status = lu.status;
+        HIP_TRY(launch_tips<T>(ta, s));
+    }
+    return SAP_OK;
+}
+
+}  // namespace
+
+// ======================================================================= ABI
+
+extern "C" {
+
+const char *sap_last_error(void) { return g_err.c_str(); }
+
+int sap_workspace_bytes(const sap_options *opt, size_t *bytes)
+{
+    int rc = validate(opt);
+    if (rc) return rc;
+    if (!bytes) return fail(SAP_ERR_INVALID, "bytes pointer is null");
+    *bytes = layout_for(*opt).total;
+    return SAP_OK;
+}
+
+int sap_create(const sap_options *opt, void *workspace, size_t ws_bytes, sap_handle *out)
+{
+    int rc = validate(opt);
+    if (rc) return rc;
+    if (!out) return fail(SAP_ERR_INVALID, "output handle pointer is null");
+    *out = nullptr;
+    if (!workspace) return fail(SAP_ERR_INVALID, "workspace is null");
+    if (reinterpret_cast<uintptr_t>(workspace) % kAlign)
+        return fail(SAP_ERR_INVALID, "workspace must be 256-byte aligned");
+    Layout L = layout_for(*opt);
+    if (ws_bytes < L.total)
+        return fail(SAP_ERR_NOSPACE, "workspace too small: need " + std::to_string(L.total) +
+                                         " bytes, got " + std::to_string(ws_bytes));
+    sap_handle h = new (std::nothrow) sap_handle_();
+    if (!h) return fail(SAP_ERR_INVALID, "out of host memory");
+    h->opt = *opt;
+    h->coupled = coupled_active(*opt);
+    h->fp32 = opt->factor_prec == SAP_PREC_FP32;
+    h->ws = static_cast<unsigned char *>(workspace);
+    h->L = L;
+    const int64_t n = opt->n;
+    const int p = opt->p;
+    h->pt.n = n;
+    h->pt.k = opt->k;
+    h->pt.p = p;
+    h->pt.maxnb = n / p + (n % p ? 1 : 0);
+    h->pt.starts = h->ptr<int64_t>(L.starts);
+    h->nchunk = (int)((h->pt.maxnb + 255) / 256);
+    auto cleanup = [&](int code, const std::string &m) {
+        if (h->h_starts) (void)hipHostFree(h->h_starts);
+        if (h->h_slots) (void)hipHostFree(h->h_slots);
+        if (h->h_status) (void)hipHostFree(h->h_status);
+        for (auto &e : h->ev)
+            if (e) (void)hipEventDestroy(e);
+        delete h;
+        return fail(code, m);
+    };
+    if (hipHostMalloc((void **)&h->h_starts, sizeof(int64_t) * (p + 1), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void **)&h->h_slots, sizeof(double) * kHostSlots, hipHostMallocMapped) != hipSuccess ||
+        hipHostMalloc((void **)&h->h_status, 64, hipHostMallocDefault) != hipSuccess)
+        return cleanup(SAP_ERR_HIP, "hipHostMalloc failed");
+    if (hipHostGetDevicePointer((void **)&h->d_slots, h->h_slots, 0) != hipSuccess)
+        return cleanup(SAP_ERR_HIP, "hipHostGetDevicePointer failed");
+    for (auto &e : h->ev)
+        if (hipEventCreate(&e) != hipSuccess) return cleanup(SAP_ERR_HIP, "hipEventCreate failed");
+    // Sec. 3.1: first P_r = N - P*floor(N/P) blocks get floor(N/P) + 1 rows
+    const int64_t q = n / p, pr = n - (int64_t)p * q;
+    h->h_starts[0] = 0;
+    for (int i = 0; i < p; ++i) h->h_starts[i + 1] = h->h_starts[i] + q + (i < pr ? 1 : 0);
+    *out = h;
+    return SAP_OK;
+}
+
+int sap_factor(sap_handle h, const double *a_band, void *stream)
+{
+    if (!h) return fail(SAP_ERR_INVALID, "null handle");
+    if (!a_band) return fail(SAP_ERR_INVALID, "a_band is null");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (!h->starts_uploaded) {
+        HIP_TRY(hipMemcpyAsync(h->ptr<int64_t>(h->L.starts), h->h_starts,
+                               sizeof(int64_t) * (h->opt.p + 1), hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemsetAsync(h->ptr<unsigned>(h->L.counter), 0, 64, s));
+        h->starts_uploaded = true;
+    }
+    HIP_TRY(hipMemsetAsync(h->ptr<int>(h->L.status), 0, 64, s));
+    HIP_TRY(hipEventRecord(h->ev[0], s));
+    HIP_TRY(launch_block_norm(a_band, h->pt, h->ptr<double>(h->L.partial), h->nchunk, s));
+    int rc = h->fp32 ? factor_t<float>(h, a_band, s) : factor_t<double>(h, a_band, s);
+    if (rc) return rc;
+    HIP_TRY(hipEventRecord(h->ev[2], s));
+    h->a_band = a_band;
+    h->factored = true;
+    h->t_factor = h->t_lu = h->t_tips = -1.0f;
+    return SAP_OK;
+}
+
+static void collect_factor_times(sap_handle h)
+{
+    if (h->t_factor >= 0.0f) return;
+    if (hipEventSynchronize(h->ev[2]) != hipSuccess) return;
+    (void)hipEventElapsedTime(&h->t_factor, h->ev[0], h->ev[2]);
+    (void)hipEventElapsedTime(&h->t_lu, h->ev[0], h->ev[1]);
+    (void)hipEventElapsedTime(&h->t_tips, h->ev[1], h->ev[2]);
+}
+
+int sap_solve(sap_handle h, const double *b, double *x, double tol, int32_t maxit, void *stream,
+              sap_stats *st)
+{
+    if (!h) return fail(SAP_ERR_INVALID, "null handle");
+    if (h->factored) collect_factor_times(h);
+    return krylov(h, 0, b, x, tol, maxit, static_cast<hipStream_t>(stream), st);
+}
+
+int sap_solve_adjoint(sap_handle h, const double *g, double *lambda, double tol, int32_t maxit,
+                      void *stream, sap_stats *st)
+{
+    if (!h) return fail(SAP_ERR_INVALID, "null handle");
+    if (h->factored) collect_factor_times(h);
+    return krylov(h, 1, g, lambda, tol, maxit, static_cast<hipStream_t>(stream), st);
+}
+
+int sap_band_grad(sap_handle h, const double *lambda, const double *x, double *g_band,
+                  void *stream)
+{
+    if (!h) return fail(SAP_ERR_INVALID, "null handle");
+    if (!lambda || !x || !g_band) return fail(SAP_ERR_INVALID, "null vector pointer");
+    HIP_TRY(launch_band_grad(h->opt.n, h->opt.k, lambda, x, g_band,
+                             static_cast<hipStream_t>(stream)));
+    return SAP_OK;
+}
+
+int sap_handle_status(sap_handle h, void *stream, int32_t *n_boosted)
+{
+    if (!h) return fail(SAP_ERR_INVALID, "null handle");
+    if (!h->factored) return fail(SAP_ERR_STATE, "sap_factor has not been called");
+    int32_t nb = 0, sing = 0;
+    TRY(read_factor_status(h, static_cast<hipStream_t>(stream), &nb, &sing));
+    if (n_boosted) *n_boosted = nb;
+    if (sing) return fail(SAP_ERR_SINGULAR, sing == 1 ? "zero pivot in a diagonal block"
+                                                      : "singular reduced matrix Rbar");
+    return SAP_OK;
+}
+
+int sap_spmv(sap_handle h, const double *v, double *y, int32_t trans, void *stream)
+{
+    if (!h) return fail(SAP_ERR_INVALID, "null handle");
+    if (!h->factored) return fail(SAP_ERR_STATE, "sap_factor has not been called");
+    if (!v || !y) return fail(SAP_ERR_INVALID, "null vector pointer");
+    HIP_TRY(launch_spmv(h->a_band, h->opt.n, h->opt.k, v, nullptr, y, trans ? 1 : 0,
+                        static_cast<hipStream_t>(stream)));
+    return SAP_OK;
+}
+
+int sap_precond_apply(sap_handle h, const double *r, double *z, int32_t trans, void *stream)
+{
+    if (!h) return fail(SAP_ERR_INVALID, "null handle");
+    if (!h->factored) return fail(SAP_ERR_STATE, "sap_factor has not been called");
+    if (!r || !z) return fail(SAP_ERR_INVALID, "null vector pointer");
+    if (trans && !h->opt.adjoint)
+        return fail(SAP_ERR_STATE, "handle was created without adjoint = 1");
+    return precond(h, trans ? 1 : 0, r, z, static_cast<hipStream_t>(stream));
+}
+
+int sap_get_tips(sap_handle h, int32_t i, double *v, double *w, double *rbar, void *stream)
+{
+    if (!h) return fail(SAP_ERR_INVALID, "null handle");
+    if (!h->factored) return fail(SAP_ERR_STATE, "sap_factor has not been called");
+    if (!h->coupled) return fail(SAP_ERR_STATE, "no interface matrices in this mode");
+    if (i < 0 || i >= h->opt.p - 1) return fail(SAP_ERR_INVALID, "interface index out of range");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const size_t kk = (size_t)h->opt.k * h->opt.k;
+    const size_t sf = h->fp32 ? 4 : 8;
+    std::vector<unsigned char> tmp(kk * sf);
+    const size_t offs[3] = {h->L.V, h->L.W, h->L.Rbar};
+    double *dst[3] = {v, w, rbar};
+    for (int m = 0; m < 3; ++m) {
+        if (!dst[m]) continue;
+        HIP_TRY(hipMemcpyAsync(tmp.data(), h->ws + offs[m] + (size_t)i * kk * sf, kk * sf,
+                               hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        for (size_t e = 0; e < kk; ++e)
+            dst[m][e] = h->fp32 ? (double)reinterpret_cast<float *>(tmp.data())[e]
+                                : reinterpret_cast<double *>(tmp.data())[e];
+    }
+    return SAP_OK;
+}
+
+int sap_destroy(sap_handle h)
+{
+    if (!h) return SAP_OK;
+    (void)hipHostFree(h->h_starts);
+    (void)hipHostFree(h->h_slots);
+    (void)hipHostFree(h->h_status);
+    for (auto &e : h->ev)
+        if (e) (void)hipEventDestroy(e);
+    delete h;
+    return SAP_OK;
+}
+
+}  // extern "C"

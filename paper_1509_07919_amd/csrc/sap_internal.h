@@ -1,0 +1,169 @@
+// Internal declarations shared by the HIP translation units of libsap.
+//
+// Device data layout (all arrays live in the caller's workspace):
+//
+//   factor coefficient arrays, one row of CS = K+1 entries per matrix
+//   column/row j (global index), type T = float or double:
+//     Lc[j*CS + 0] = 1,        Lc[j*CS + m] = l(j+m, j)   (column j of L)
+//     Uc[j*CS + 0] = 1/u(j,j), Uc[j*CS + m] = u(j-m, j)   (column j of U)
+//     Ur[j*CS + 0] = 1/u(j,j), Ur[j*CS + m] = u(j, j+m)   (row j of U)
+//     Lr[j*CS + 0] = 1,        Lr[j*CS + m] = l(j, j-m)   (row j of L)
+//   for m = 1..K, with 0 wherever j+m or j-m leaves the diagonal block.
+//   Each row holds exactly the coefficients one step of a forward or
+//   backward sweep pushes to its K successors, so every sweep streams one
+//   contiguous row per step.  Ur/Lr exist only when the handle keeps the
+//   transposed factors for the adjoint solve.
+//
+//   ULcorner[i*K*K + a*K + b]: bottom-right K x K corner of LU(J A_i J)
+//   (unit-lower part below the diagonal, upper part with the pivots on and
+//   above it); J reverses the order of the block's rows and columns, so this
+//   is the top-left corner of the UL factorization of A_i read backwards.
+//
+//   interface arrays for SaP-C, i = 0..P-2, each K x K row-major, type T:
+//   B, C (coupling blocks), V (= V_i^(b)), W (= W_{i+1}^(t)), Rbar, Rinv.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sap {
+
+constexpr int kMaxK = 255;
+constexpr int kDotBlocks = 512;   // fixed grid of the reduction kernels
+
+enum KrylovOp : int {
+    OP_INIT = 0,   // d0=(r0,rt) d1=(r0,r0): rho=1,alpha=0,omega=1 then j=0 prep
+    OP_GAMMA,      // d0=(u_{j+1},rt): alpha = rho0/gamma
+    OP_EXIT,       // d0=(r0,r0): publish ||r0||^2
+    OP_RHO,        // d0=(r_j,rt): beta = alpha*rho1/rho0, rho0 = rho1
+    OP_MR1,        // d0=(r1,r1) d1=(r0,r1) d2=(r2,r1)
+    OP_MR2,        // d0=(r2,r2) d1=(r0,r2)
+    OP_FINAL,      // d0=(r0,r0) d1=(r0,rt): publish, then next j=0 prep
+    OP_NORM,       // d0=(v,v): publish only
+};
+
+// device scalar slots of the BiCGStab(2) recurrences (double sc[kScalars])
+enum ScalarSlot : int {
+    S_RHO0 = 0, S_ALPHA, S_OMEGA, S_BETA, S_GAMMA, S_SIGMA1, S_SIGMA2,
+    S_GP1, S_GP2, S_TAU12, S_G1, S_G2, S_GPP1, S_NRM2, S_BREAK, kScalars = 32
+};
+
+// host-visible (pinned, mapped) result slots written by reduction kernels
+enum HostSlot : int { H_NRM2 = 0, H_BREAK = 1, H_SPARE = 2, kHostSlots = 8 };
+
+struct Partition {
+    const int64_t *starts;   // P+1 block boundaries (device)
+    int64_t n;
+    int k;
+    int p;
+    int64_t maxnb;
+};
+
+// ------------------------------------------------------------- factorization
+hipError_t launch_block_norm(const double *band, const Partition &pt,
+                             double *partial, int nchunk, hipStream_t s);
+
+template <typename T>
+struct LuArgs {
+    const double *band;
+    Partition pt;
+    const double *partial;   // per-block norm partials [p][nchunk]
+    int nchunk;
+    double boost_eps;        // < 0: no boosting
+    T *Lc, *Uc, *Lr, *Ur;    // Lr/Ur may be null
+    T *corner;               // [p][K*K], UL direction only (may be null)
+    int *status;             // [0] boosted pivots, [1] singular flag
+    int with_ul;             // grid = 2P: blocks >= P run the UL direction
+};
+template <typename T>
+hipError_t launch_banded_lu(const LuArgs<T> &a, hipStream_t s);
+
+template <typename T>
+struct TipsArgs {
+    const double *band;
+    Partition pt;
+    const T *Lc, *Uc, *corner;
+    T *B, *C, *V, *W, *Rbar, *Rlu, *Rinv;
+    int *piv;
+    int *status;
+};
+template <typename T>
+hipError_t launch_tips(const TipsArgs<T> &a, hipStream_t s);
+
+// ------------------------------------------------------------------ sweeps
+// One triangular sweep per diagonal block.  fwd: steps j = 0..nb-1 pushing
+// to j+m; otherwise j = nb-1..0 pushing to j-m.  diag: multiply by F[j][0].
+// Input: xin (double) or tin (T), plus optional boundary deltas (T) added to
+// the top/bottom K rows of each block.  Output: dout (double) or tout (T).
+template <typename T>
+struct SweepArgs {
+    const T *F;
+    Partition pt;
+    int fwd, diag;
+    const double *xin;
+    const T *tin;
+    const T *dtop, *dbot;    // [p][K] or null
+    double *dout;
+    T *tout;
+};
+template <typename T>
+hipError_t launch_sweep(const SweepArgs<T> &a, hipStream_t s);
+
+// SaP-C interface correction: from g (T, full vector) compute the deltas
+// added to the top (dtop) and bottom (dbot) K rows of each block before the
+// purification sweep.  trans selects the exact transpose.
+template <typename T>
+struct CorrArgs {
+    Partition pt;
+    const T *g;
+    const T *B, *C, *V, *W, *Rinv;
+    T *dtop, *dbot;
+    int trans;
+};
+template <typename T>
+hipError_t launch_correction(const CorrArgs<T> &a, hipStream_t s);
+
+// ------------------------------------------------------------- SpMV / misc
+// y = A v (trans 0) or A^T v; if b != null: y = b - A v (residual form).
+hipError_t launch_spmv(const double *band, int64_t n, int k, const double *v,
+                       const double *b, double *y, int trans, hipStream_t s);
+hipError_t launch_band_grad(int64_t n, int k, const double *lam,
+                            const double *x, double *g, hipStream_t s);
+
+// ---------------------------------------------------------------- Krylov
+struct DotArgs {
+    const double *x[3];
+    const double *y[3];
+    int nd;
+    int64_t n;
+    double *partial;         // [kDotBlocks][3]
+    unsigned *counter;       // zero before the first launch; reset by kernel
+    double *sc;              // device scalars
+    double *host;            // mapped pinned host slots (may be null)
+    int op;
+};
+hipError_t launch_dots(const DotArgs &a, hipStream_t s);
+
+// Fused vector updates of BiCGStab(2) (l = 2), each optionally followed by
+// dots handled as in launch_dots.
+enum UpdKind : int {
+    UPD_U0 = 0,      // u0 = r0 - beta u0
+    UPD_J0,          // r0 -= alpha u1; x += alpha u0
+    UPD_U01,         // u0 = r0 - beta u0; u1 = r1 - beta u1
+    UPD_J1,          // r0 -= alpha u1; r1 -= alpha u2; x += alpha u0
+    UPD_MR2,         // r2 -= tau12 r1
+    UPD_FINAL,       // x += g1 r0 + gpp1 r1; r0 -= gp2 r2 + gp1 r1;
+                     // u0 -= g2 u2 + g1 u1
+    UPD_RESTART,     // rt = r0; u0 = 0
+};
+struct UpdArgs {
+    int kind;
+    int64_t n;
+    double *x, *r0, *r1, *r2, *u0, *u1, *u2, *rt;
+    DotArgs dots;            // dots.nd == 0: none
+};
+hipError_t launch_update(const UpdArgs &a, hipStream_t s);
+
+hipError_t launch_fill(double *v, double val, int64_t n, hipStream_t s);
+
+}  // namespace sap
