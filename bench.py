@@ -1,0 +1,225 @@
+"""Benchmark: time to solution of the coupled SaP solver on one MI355X.
+
+One step = sap_factor + sap_solve (factorization, spike tips, reduced
+systems and BiCGStab(2) to a 1e-10 true relative residual) on the resident
+N=200000, K=50, P=64, d=1 system.  The FP64 run is the headline value; the
+same steps with FP32 factors/tips/sweeps (FP64 Krylov) are timed beside it.
+
+Prints ONE JSON line.  `--gpus N` with N > 1 exits: this build runs on one
+GPU only.
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "solve ms & HBM GB/s, N=200k K=50; FP32-factor vs FP64 SaP at 1e-10 resid"
+HBM_PEAK_GBS = 8000.0           # MI355X HBM3E
+PROFILE_DIR = os.path.join(ROOT, "profiles")
+
+
+def sweep_bytes(n, k, sf, coupled):
+    """Algorithmic bytes of one sweep launch: the K+1 coefficients of every
+    row plus input and output vectors, averaged over the sweeps of one
+    preconditioner application (SaP-C: in/out = (8,s) (s,s) (8,s) (s,8);
+    SaP-D: (8,s) (s,8))."""
+    io = (24 + 5 * sf) / 4.0 if coupled else 8.0 + sf
+    return n * (k + 1) * sf + n * io
+
+
+def spmv_bytes(n, k):
+    return 8.0 * (2 * k + 1) * n + 16.0 * n
+
+
+def lu_bytes(n, k, sf, coupled):
+    dirs = 2 if coupled else 1
+    return dirs * 8.0 * (2 * k + 1) * n + 2.0 * n * (k + 1) * sf
+
+
+def kernel_source_hash(name: str) -> str:
+    path = os.path.join(ROOT, "paper_1509_07919_amd", "csrc", name)
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def traffic_from_profiles(kernel_file: str, tag: str):
+    """HBM bytes per launch measured with rocprofv3 counters, from a committed
+    summary that records the hash of the kernel source it was taken on; None
+    if absent or if the kernel changed since."""
+    path = os.path.join(PROFILE_DIR, "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        data = json.load(f)
+    ent = data.get(tag)
+    if not ent or ent.get("source_sha256_16") != kernel_source_hash(kernel_file):
+        return None
+    return ent.get("bytes_per_launch")
+
+
+def run_gpu(args, prec, pb, a, b):
+    import torch
+    from paper_1509_07919_amd import SapSolver
+
+    cfg = args.cfg
+    s = SapSolver(cfg["n"], cfg["k"], cfg["p"], mode=cfg["mode"], factor_prec=prec)
+    x = torch.empty_like(b)
+    for _ in range(args.warmup):
+        s.factor(a)
+        s.solve(b, x, tol=cfg["tol"], maxit=args.maxit)
+    torch.cuda.synchronize()
+    s.profile(True)
+    stats = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        s.factor(a)
+        _, st = s.solve(b, x, tol=cfg["tol"], maxit=args.maxit)
+        stats.append(st)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kt = s.kernel_times()
+    s.profile(False)
+    xs = x.cpu().numpy()
+    s.close()
+    return (t1 - t0) * 1e3 / args.steps, stats, kt, xs
+
+
+def cpu_baseline(cfg, pb, reps):
+    """The CPU oracle (plain FP64 SaP-C + BiCGStab(2)) on the same workload,
+    single thread, median of `reps` full solves."""
+    from threadpoolctl import threadpool_limits
+
+    import oracle
+    times, x = [], None
+    with threadpool_limits(1):
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            x, res, _ = oracle.sap_solve(pb.band, cfg["n"], cfg["k"], pb.b, cfg["p"],
+                                         cfg["mode"] == "coupled", tol=cfg["tol"])
+            times.append((time.perf_counter() - t0) * 1e3)
+    return statistics.median(times), x, res
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="sapc_n200k_k50")
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--maxit", type=int, default=100)
+    ap.add_argument("--cpu-reps", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--precs", default="fp64,fp32")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only; --gpus %d is not supported"
+              % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import sapgen
+    cfg = dict(sapgen.WORKLOADS[args.workload])
+    args.cfg = cfg
+    n, k = cfg["n"], cfg["k"]
+    pb = sapgen.make_problem(n, k, d=cfg["d"], seed=args.seed,
+                             row_scale_decades=cfg["row_scale_decades"])
+    dev = torch.device("cuda:0")
+    a = torch.from_numpy(pb.band).to(dev)
+    b = torch.from_numpy(pb.b).to(dev)
+    coupled = cfg["mode"] == "coupled"
+
+    runs = {}
+    for prec in args.precs.split(","):
+        ms, stats, kt, xs = run_gpu(args, prec, pb, a, b)
+        runs[prec] = dict(ms=ms, stats=stats, kt=kt, x=xs)
+
+    head = "fp64" if "fp64" in runs else next(iter(runs))
+    sf = 8 if head == "fp64" else 4
+    r = runs[head]
+    steps = args.steps
+    per_launch = {
+        "sweep": sweep_bytes(n, k, sf, coupled),
+        "spmv": spmv_bytes(n, k),
+        "lu": lu_bytes(n, k, sf, coupled),
+    }
+    kernels = {}
+    for name, (tms, cnt) in r["kt"].items():
+        if cnt == 0:
+            continue
+        ent = {"ms_per_step": tms / steps, "launches_per_step": cnt / steps,
+               "avg_us": 1e3 * tms / cnt}
+        if name in per_launch:
+            ent["bytes_per_launch"] = per_launch[name]
+            ent["algorithmic_GBps"] = per_launch[name] / (1e-3 * tms / cnt) / 1e9
+        kernels[name] = ent
+    dom = max(kernels, key=lambda q: kernels[q]["ms_per_step"])
+    if dom in per_launch:
+        src = {"sweep": "k_sweep.hip", "spmv": "k_vec.hip", "lu": "k_factor.hip"}[dom]
+        avg_s = 1e-3 * r["kt"][dom][0] / r["kt"][dom][1]
+        ach = per_launch[dom] / avg_s / 1e9
+        roof = {"kernel": dom, "bound": "hbm", "achieved": round(ach, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+                "traffic": traffic_from_profiles(src, "%s_%s_%s" % (dom, head, args.workload)),
+                "avg_us": round(avg_s * 1e6, 2),
+                "bytes_per_launch": per_launch[dom]}
+    else:
+        roof = {"kernel": dom, "bound": None, "note": "no byte model for this kernel class"}
+
+    def summary(prec):
+        q = runs[prec]
+        st = q["stats"][-1]
+        err_true = float(np.linalg.norm(q["x"] - pb.x_true) / np.linalg.norm(pb.x_true))
+        return {"ms": round(q["ms"], 4), "iters": st.iters, "restarts": st.restarts,
+                "rel_resid_true": st.rel_resid_true, "converged": bool(st.converged),
+                "t_factor_ms": round(st.t_factor_ms, 4), "t_lu_ms": round(st.t_lu_ms, 4),
+                "t_tips_ms": round(st.t_tips_ms, 4), "t_solve_ms": round(st.t_solve_ms, 4),
+                "rel_err_vs_xtrue": err_true}
+
+    out = {
+        "metric": METRIC, "value": round(r["ms"], 4), "unit": "ms", "n_gpus": 1,
+        "steps": steps, "warmup": args.warmup, "ms_per_step": round(r["ms"], 4),
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if head == "fp64" else "f32-factor/f64-krylov", "data": "synthetic",
+        "config": {"workload": args.workload, "n": n, "k": k, "p": cfg["p"],
+                   "mode": cfg["mode"], "d": cfg["d"], "tol": cfg["tol"], "seed": args.seed,
+                   "factor_prec": head},
+        "roofline": roof,
+        "runs": {p_: summary(p_) for p_ in runs},
+        "kernels": kernels,
+        "paper_context": {"sap_c_ms": 186.756, "sap_d_ms": 187.717, "mkl_ms": 367.638,
+                          "hardware": "Tesla K20X (paper Table t:denseBandedSweep, P=50)"},
+    }
+    if "fp64" in runs and "fp32" in runs:
+        out["race"] = {"fp64_ms": round(runs["fp64"]["ms"], 4),
+                       "fp32_factor_ms": round(runs["fp32"]["ms"], 4),
+                       "fp32_speedup": round(runs["fp64"]["ms"] / runs["fp32"]["ms"], 3)}
+    if not args.no_cpu:
+        cms, xo, res = cpu_baseline(cfg, pb, args.cpu_reps)
+        out["cpu_baseline"] = {
+            "value": round(cms, 2), "unit": "ms", "cores": 1, "kind": "oracle",
+            "sample": "full workload, median of %d oracle solves (FP64 SaP-%s, P=%d, "
+                      "BiCGStab(2) to %g), 1 thread" % (args.cpu_reps,
+                                                        "C" if coupled else "D",
+                                                        cfg["p"], cfg["tol"]),
+            "host_cpus": os.cpu_count()}
+        for p_ in runs:
+            out["runs"][p_]["rel_err_vs_oracle"] = float(
+                np.linalg.norm(runs[p_]["x"] - xo) / np.linalg.norm(xo))
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

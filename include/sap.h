@@ -170,6 +170,25 @@ int sap_precond_apply(sap_handle h, const double *r, double *z,
 int sap_get_tips(sap_handle h, int32_t i, double *v, double *w, double *rbar,
                  void *stream);
 
+/* Per-kernel device timing, for benchmarking.  sap_profile(h, 1) resets the
+ * counters and starts bracketing every kernel launch of the handle with a
+ * pair of HIP events on the launch stream; sap_profile(h, 0) stops.
+ * sap_kernel_time synchronises on the recorded events and returns the
+ * summed device milliseconds and the number of launches of one kernel class
+ * since the reset.  Recording adds event records between launches but does
+ * not change the kernels. */
+#define SAP_KERNEL_NORM    0   /* per-block max-norm                         */
+#define SAP_KERNEL_LU      1   /* banded LU (and UL) of the diagonal blocks  */
+#define SAP_KERNEL_TIPS    2   /* coupling blocks, spike tips, Rbar inverse  */
+#define SAP_KERNEL_SWEEP   3   /* one triangular sweep over all blocks       */
+#define SAP_KERNEL_CORR    4   /* SaP-C interface correction                 */
+#define SAP_KERNEL_SPMV    5   /* banded SpMV (A or A^T, plain or residual)  */
+#define SAP_KERNEL_KRYLOV  6   /* BiCGStab(2) dots and fused vector updates  */
+#define SAP_KERNEL_COUNT   7
+int sap_profile(sap_handle h, int32_t enable);
+int sap_kernel_time(sap_handle h, int32_t kernel, double *ms /* host */,
+                    int64_t *launches /* host */);
+
 /* Release the handle (not the caller's workspace or matrix). */
 int sap_destroy(sap_handle h);
 

@@ -204,7 +204,9 @@ class SapPrecond:
         self.band = _f64(self.band)
         n, k, p = self.n, self.k, self.p
         self.sizes, self.starts = partition(n, p)
-        if self.coupled and p > 1 and int(self.sizes.min()) < 2 * k:
+        # with K = 0 there are no coupling blocks: SaP-C reduces to SaP-D
+        self.cpl = self.coupled and p > 1 and k > 0
+        if self.cpl and int(self.sizes.min()) < 2 * k:
             raise ValueError("coupled mode needs every block to have >= 2K rows")
         lib = _load()
         w = 2 * k + 1
@@ -217,7 +219,7 @@ class SapPrecond:
             tau = (self.boost_eps * lib.orc_block_maxabs(nb, k, _p(f))
                    if self.boost_eps >= 0 else -1.0)
             self.tau.append(tau)
-            fu = f.copy() if (self.coupled and p > 1) else None
+            fu = f.copy() if self.cpl else None
             info = lib.orc_block_lu(nb, k, _p(f), tau, ctypes.byref(nb_tot))
             if info:
                 raise np.linalg.LinAlgError("zero pivot %d in block %d" % (info - 1, i))
@@ -229,7 +231,7 @@ class SapPrecond:
                     raise np.linalg.LinAlgError("zero UL pivot %d in block %d" % (info - 1, i))
                 self.n_boosted += nb_tot.value
                 self.ul.append(fu)
-        if self.coupled and p > 1:
+        if self.cpl:
             self._tips()
 
     # -- factor-corner helpers (row window R(r,c) = f[r*w + c - r + k]) --
@@ -311,7 +313,7 @@ class SapPrecond:
         g = D^{-1} r, truncated reduced solves, then the purification solve
         A_i x_i = b_i - [C_i x~^(b)_{i-1}; 0; 0] - [0; 0; B_i x~^(t)_{i+1}]."""
         g = self.dinv(r)
-        if not (self.coupled and self.p > 1):
+        if not self.cpl:
             return g
         k = self.k
         xt_all, xb_all = self.reduced(g)
@@ -328,7 +330,7 @@ class SapPrecond:
         Gamma the coupling-block products, M^{-T} s = D^{-T}(s + Psi^T Gamma^T
         D^{-T} s)."""
         h = self.dinv(s, trans=True)
-        if not (self.coupled and self.p > 1):
+        if not self.cpl:
             return h
         k = self.k
         gbar = np.zeros(self.n)

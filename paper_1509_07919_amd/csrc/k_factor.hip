@@ -92,6 +92,7 @@ __global__ __launch_bounds__(NT) void k_banded_lu(LuArgs<T> a)
 
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *stage = reinterpret_cast<T *>(smem_raw);               // [2][(2K+1)*S]
+    T *obuf = stage + 2 * (2 * a.pt.k + 1) * S;               // [S][2][K+1]
     __shared__ __align__(16) T lcol[2][WC];                   // perm: [rs*RPT+i]
     __shared__ __align__(16) T urow[2][WC];
     __shared__ double tau_sh;
@@ -164,8 +165,30 @@ __global__ __launch_bounds__(NT) void k_banded_lu(LuArgs<T> a)
             if (f < stage_sz) dst[f] = pre[i];
         }
     };
+    // Outputs of one chunk of S steps (L column and U row of each step) are
+    // kept in LDS and written out by all threads at the next chunk boundary,
+    // so no global access is pending between boundaries.
+    auto flush = [&](int64_t j0) {
+        if (ul) return;
+        const int tot = S * CS;
+        for (int idx = tid; idx < tot; idx += NT) {
+            const int jj = idx / CS, m = idx - jj * CS;
+            const int64_t j = j0 + jj;
+            if (j >= nb) continue;
+            const T lv = obuf[jj * 2 * CS + m];
+            const T uv = obuf[jj * 2 * CS + CS + m];
+            const bool in = j + m < nb;
+            a.Lc[(s0 + j) * CS + m] = lv;
+            if (in) a.Uc[(s0 + j + m) * CS + m] = uv;
+            if (a.Ur) a.Ur[(s0 + j) * CS + m] = in ? uv : T(0);
+            if (a.Lr && in) a.Lr[(s0 + j + m) * CS + m] = lv;
+        }
+    };
     prefetch(0);
     __syncthreads();
+    // Drain the ring-fill loads here: otherwise the wait for them is placed
+    // inside the step loop, where it also waits for every pending store.
+    __builtin_amdgcn_s_waitcnt(0);
     const double tau_d = tau_sh;
     const T tau = (T)tau_d;
     const bool do_boost = tau_d >= 0.0;
@@ -182,7 +205,10 @@ __global__ __launch_bounds__(NT) void k_banded_lu(LuArgs<T> a)
         T *ur = urow[u & 1];
         T *lc = lcol[u & 1];
         const int lbase = rs * RPT;
-        if ((j & (S - 1)) == 0) commit(j / S);        // chunk of entering data
+        if ((j & (S - 1)) == 0) {                     // chunk boundary
+            commit(j / S);                            // entering data of this chunk
+            if (j > 0) flush(j - S);                  // outputs of the last chunk
+        }
         // phase A: publish pivot row (by ring column) and pivot column
         if (own_row) ur[sc] = w[0];
         if (sc == u) {
@@ -215,10 +241,9 @@ __global__ __launch_bounds__(NT) void k_banded_lu(LuArgs<T> a)
             const T uv = m == 0 ? inv : ur[sl];
             const bool in = j + m < nb;
             if (!ul) {
-                a.Lc[(s0 + j) * CS + m] = lv;
-                if (in) a.Uc[(s0 + j + m) * CS + m] = uv;
-                if (a.Ur) a.Ur[(s0 + j) * CS + m] = in ? uv : T(0);
-                if (a.Lr && in) a.Lr[(s0 + j + m) * CS + m] = lv;
+                T *ob = obuf + (j & (S - 1)) * 2 * CS;
+                ob[m] = lv;
+                ob[CS + m] = uv;
             } else if (a.corner && j >= nb - k && in) {
                 const int64_t b0 = j - (nb - k);
                 T *cn = a.corner + (int64_t)blk * k * k;
@@ -253,13 +278,15 @@ __global__ __launch_bounds__(NT) void k_banded_lu(LuArgs<T> a)
         }
         if ((j & (S - 1)) == 0) prefetch(j / S + 1);
     }
+    __syncthreads();
+    flush((nb - 1) & ~(int64_t)(S - 1));              // last (partial) chunk
     if (tid == 0 && nboost) atomicAdd(&a.status[0], nboost);
 }
 
 template <typename T, int WC, int S, int NT>
 static hipError_t launch_lu_cfg(const LuArgs<T> &a, hipStream_t s)
 {
-    const size_t lds = 2 * (size_t)(2 * a.pt.k + 1) * S * sizeof(T);
+    const size_t lds = (2 * (size_t)(2 * a.pt.k + 1) * S + (size_t)S * 2 * (a.pt.k + 1)) * sizeof(T);
     auto kern = k_banded_lu<T, WC, S, NT>;
     hipError_t e = hipFuncSetAttribute((const void *)kern,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -276,7 +303,7 @@ hipError_t launch_banded_lu<double>(const LuArgs<double> &a, hipStream_t s)
     if (k < 16) return launch_lu_cfg<double, 16, 16, 256>(a, s);
     if (k < 32) return launch_lu_cfg<double, 32, 32, 256>(a, s);
     if (k < 64) return launch_lu_cfg<double, 64, 32, 256>(a, s);
-    if (k < 128) return launch_lu_cfg<double, 128, 32, 1024>(a, s);
+    if (k < 128) return launch_lu_cfg<double, 128, 16, 1024>(a, s);
     return hipErrorInvalidValue;   // FP64 window for K >= 128 exceeds the VGPR budget
 }
 
@@ -288,7 +315,7 @@ hipError_t launch_banded_lu<float>(const LuArgs<float> &a, hipStream_t s)
     if (k < 32) return launch_lu_cfg<float, 32, 32, 256>(a, s);
     if (k < 64) return launch_lu_cfg<float, 64, 32, 256>(a, s);
     if (k < 128) return launch_lu_cfg<float, 128, 32, 1024>(a, s);
-    return launch_lu_cfg<float, 256, 32, 1024>(a, s);
+    return launch_lu_cfg<float, 256, 16, 1024>(a, s);
 }
 
 }  // namespace sap

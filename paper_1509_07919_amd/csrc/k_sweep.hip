@@ -36,7 +36,7 @@ __device__ __forceinline__ float lane_bcast(float x, int l)
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
 }
 
-template <typename T, int KR, int S>
+template <typename T, int KR, int S, bool FWD, bool DIAG>
 __global__ __launch_bounds__(256) void k_sweep(SweepArgs<T> a)
 {
     static_assert(S % 64 == 0, "chunk must hold whole 64-step blocks");
@@ -55,13 +55,12 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs<T> a)
     const int tid = threadIdx.x;
     const int wave = tid >> 6;
     const int lane = tid & 63;
-    const bool fwd = a.fwd != 0;
     const int64_t nchunks = (nb + S - 1) / S;
     const T *dtop = (a.dtop && blk > 0) ? a.dtop + (int64_t)blk * k : nullptr;
     const T *dbot = (a.dbot && blk < a.pt.p - 1) ? a.dbot + (int64_t)blk * k : nullptr;
 
     // row of the block handled at step t
-    auto row_of = [&](int64_t t) -> int64_t { return fwd ? t : nb - 1 - t; };
+    auto row_of = [&](int64_t t) -> int64_t { return FWD ? t : nb - 1 - t; };
 
     if (wave != 0) {
         // ------------------------------------------------------ loaders
@@ -132,11 +131,17 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs<T> a)
     }
 
     // ------------------------------------------------------- compute wave
+    // Steps run in groups of G; the LDS operands of group g+1 (diagonal
+    // factor, input, and the KR coefficients each lane pushes) are read while
+    // the dependent chain of group g runs.
+    constexpr int G = 8;
+    struct Grp {
+        T d[G], vd[G], cf[G][KR];
+    };
     __syncthreads();
     T acc[KR];
 #pragma unroll
     for (int s = 0; s < KR; ++s) acc[s] = T(0);
-    const bool diag = a.diag != 0;
 
     for (int64_t t = 0; t < nchunks; ++t) {
         const T *c = cst + (t & 1) * S * PITCH;
@@ -145,21 +150,43 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs<T> a)
             const int64_t jb = t * S + 64 * g;        // first step of this 64-block
             if (jb >= nb) break;
             const int ulim = (int)min((int64_t)64, nb - jb);
-            T ov = T(0);
-#pragma unroll 4
-            for (int u = 0; u < ulim; ++u) {
-                const T *crow = c + (64 * g + u) * PITCH;
-                const T d = diag ? crow[0] : T(1);
-                const T vd = vv[64 * g + u] * d;
-                const T x = fma(acc[0], d, vd);       // acc = -pending; valid in lane u
-                const T xb = lane_bcast(x, u);
+            auto load = [&](int u0, Grp &q) {
 #pragma unroll
-                for (int s = 0; s < KR; ++s) {
-                    const int m = 64 * s + lane - u;  // step offset of slot (s, lane)
-                    const T cf = (m >= 1 && m <= k) ? crow[m] : T(0);
-                    acc[s] = fma(-cf, xb, acc[s]);
+                for (int e = 0; e < G; ++e) {
+                    const int u = min(u0 + e, 63);
+                    const T *crow = c + (64 * g + u) * PITCH;
+                    q.d[e] = DIAG ? crow[0] : T(1);
+                    q.vd[e] = vv[64 * g + u] * q.d[e];
+#pragma unroll
+                    for (int s = 0; s < KR; ++s) {
+                        const int m = 64 * s + lane - u;     // step offset of slot (s, lane)
+                        const int mc = min(max(m, 0), PITCH - 1);
+                        const T raw = crow[mc];
+                        q.cf[e][s] = (m >= 1 && m <= k) ? raw : T(0);
+                    }
                 }
-                ov = lane == u ? xb : ov;
+            };
+            T ov = T(0);
+            auto run = [&](int u0, const Grp &q) {
+#pragma unroll
+                for (int e = 0; e < G; ++e) {
+                    const int u = u0 + e;
+                    if (u < ulim) {
+                        const T x = fma(acc[0], q.d[e], q.vd[e]);   // acc = -pending
+                        const T xb = lane_bcast(x, u);
+#pragma unroll
+                        for (int s = 0; s < KR; ++s) acc[s] = fma(-q.cf[e][s], xb, acc[s]);
+                        ov = lane == u ? xb : ov;
+                    }
+                }
+            };
+            Grp ga, gb;
+            load(0, ga);
+            for (int u0 = 0; u0 < ulim; u0 += 2 * G) {
+                load(u0 + G, gb);
+                run(u0, ga);
+                load(u0 + 2 * G, ga);
+                run(u0 + G, gb);
             }
             const int64_t st = jb + lane;
             if (st < nb) {
@@ -175,11 +202,11 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs<T> a)
     }
 }
 
-template <typename T, int KR, int S>
+template <typename T, int KR, int S, bool FWD, bool DIAG>
 static hipError_t launch_sweep_cfg(const SweepArgs<T> &a, hipStream_t s)
 {
     const size_t lds = (2 * (size_t)S * 64 * (KR - 1) + 2 * S) * sizeof(T);
-    auto kern = k_sweep<T, KR, S>;
+    auto kern = k_sweep<T, KR, S, FWD, DIAG>;
     hipError_t e = hipFuncSetAttribute((const void *)kern,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
@@ -191,7 +218,12 @@ static hipError_t launch_sweep_cfg(const SweepArgs<T> &a, hipStream_t s)
 template <typename T, int KR>
 static hipError_t launch_sweep_kr(const SweepArgs<T> &a, hipStream_t s)
 {
-    return launch_sweep_cfg<T, KR, 64>(a, s);
+    if (a.fwd) {
+        if (a.diag) return launch_sweep_cfg<T, KR, 64, true, true>(a, s);
+        return launch_sweep_cfg<T, KR, 64, true, false>(a, s);
+    }
+    if (a.diag) return launch_sweep_cfg<T, KR, 64, false, true>(a, s);
+    return launch_sweep_cfg<T, KR, 64, false, false>(a, s);
 }
 
 template <typename T>

@@ -123,12 +123,44 @@ struct sap_handle_ {
     bool factored, starts_uploaded;
     hipEvent_t ev[5];        // factor start / after LU / end, solve start / end
     float t_factor, t_lu, t_tips;
+    // per-kernel timing (sap_profile): event pairs recorded around launches
+    bool prof;
+    std::vector<hipEvent_t> pev;                 // pool, 2 per record
+    std::vector<std::pair<int, size_t>> precs;   // (kernel class, pool index)
+    double prof_ms[SAP_KERNEL_COUNT];
+    int64_t prof_n[SAP_KERNEL_COUNT];
 
     template <typename T> T *ptr(size_t off) { return reinterpret_cast<T *>(ws + off); }
     double *kvec(int i) { return ptr<double>(L.kv) + (size_t)i * opt.n; }
 };
 
 namespace {
+
+// Brackets one kernel launch with events when profiling is on.
+struct ProfScope {
+    sap_handle h;
+    int kid;
+    hipStream_t s;
+    size_t idx = 0;
+    bool on = false;
+    ProfScope(sap_handle h_, int kid_, hipStream_t s_) : h(h_), kid(kid_), s(s_)
+    {
+        if (!h->prof) return;
+        idx = h->precs.size() * 2;
+        while (h->pev.size() < idx + 2) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return;
+            h->pev.push_back(e);
+        }
+        if (hipEventRecord(h->pev[idx], s) != hipSuccess) return;
+        on = true;
+    }
+    ~ProfScope()
+    {
+        if (!on) return;
+        if (hipEventRecord(h->pev[idx + 1], s) == hipSuccess) h->precs.push_back({kid, idx});
+    }
+};
 
 enum KVec { KV_R0 = 0, KV_R1, KV_R2, KV_U0, KV_U1, KV_U2, KV_RT, KV_T };
 
@@ -155,8 +187,14 @@ int dinv(sap_handle h, int trans, const double *xin, const T *dtop, const T *dbo
         a1.F = h->ptr<T>(h->L.Ur); a1.fwd = 1; a1.diag = 1;
         a2.F = h->ptr<T>(h->L.Lr); a2.fwd = 0; a2.diag = 0;
     }
-    HIP_TRY(launch_sweep<T>(a1, s));
-    HIP_TRY(launch_sweep<T>(a2, s));
+    {
+        ProfScope ps(h, SAP_KERNEL_SWEEP, s);
+        HIP_TRY(launch_sweep<T>(a1, s));
+    }
+    {
+        ProfScope ps(h, SAP_KERNEL_SWEEP, s);
+        HIP_TRY(launch_sweep<T>(a2, s));
+    }
     return SAP_OK;
 }
 
@@ -176,7 +214,10 @@ int precond_t(sap_handle h, int trans, const double *r, double *z, hipStream_t s
     c.Rinv = h->ptr<T>(h->L.Rinv);
     c.dtop = dtop; c.dbot = dbot;
     c.trans = trans;
-    HIP_TRY(launch_correction<T>(c, s));
+    {
+        ProfScope ps(h, SAP_KERNEL_CORR, s);
+        HIP_TRY(launch_correction<T>(c, s));
+    }
     return dinv<T>(h, trans, r, dtop, dbot, z, nullptr, s);
 }
 
@@ -189,7 +230,10 @@ int precond(sap_handle h, int trans, const double *r, double *z, hipStream_t s)
 int apply_op(sap_handle h, int trans, const double *v, double *out, hipStream_t s)
 {
     double *t = h->kvec(KV_T);
-    HIP_TRY(launch_spmv(h->a_band, h->opt.n, h->opt.k, v, nullptr, t, trans, s));
+    {
+        ProfScope ps(h, SAP_KERNEL_SPMV, s);
+        HIP_TRY(launch_spmv(h->a_band, h->opt.n, h->opt.k, v, nullptr, t, trans, s));
+    }
     return precond(h, trans, t, out, s);
 }
 
@@ -212,6 +256,7 @@ int dots(sap_handle h, int op, std::initializer_list<std::pair<const double *, c
     int i = 0;
     for (auto &p : pr) { d.x[i] = p.first; d.y[i] = p.second; ++i; }
     d.nd = i;
+    ProfScope ps(h, SAP_KERNEL_KRYLOV, s);
     HIP_TRY(launch_dots(d, s));
     return SAP_OK;
 }
@@ -227,6 +272,7 @@ int update(sap_handle h, int kind, double *x, int op, int nd, hipStream_t s)
     u.rt = h->kvec(KV_RT);
     u.dots = dot_args(h, op);
     u.dots.nd = nd;
+    ProfScope ps(h, SAP_KERNEL_KRYLOV, s);
     HIP_TRY(launch_update(u, s));
     return SAP_OK;
 }
@@ -323,7 +369,10 @@ int krylov(sap_handle h, int trans, const double *b, double *x, double tol, int3
         if (!std::isfinite(nrm2)) return SAP_ERR_BREAKDOWN;
         loc.rel_resid_precond = std::sqrt(nrm2) / pnorm0;
         if (std::sqrt(nrm2) > thr) return 0;
-        HIP_TRY(launch_spmv(A, n, k, x, b, t, trans, s));        // t = b - A x
+        {
+            ProfScope ps(h, SAP_KERNEL_SPMV, s);
+            HIP_TRY(launch_spmv(A, n, k, x, b, t, trans, s));    // t = b - A x
+        }
         TRY(dots(h, OP_NORM, {{t, t}}, s));
         double tn2 = 0, b2 = 0;
         TRY(sync_read(h, s, &tn2, &b2));
@@ -379,7 +428,10 @@ int krylov(sap_handle h, int trans, const double *b, double *x, double tol, int3
         loc.converged = 1;
         return finish(SAP_OK, "");
     }
-    HIP_TRY(launch_spmv(A, n, k, x, b, t, trans, s));
+    {
+        ProfScope ps(h, SAP_KERNEL_SPMV, s);
+        HIP_TRY(launch_spmv(A, n, k, x, b, t, trans, s));
+    }
     TRY(dots(h, OP_NORM, {{t, t}}, s));
     double tn2 = 0;
     TRY(sync_read(h, s, &tn2, &brk));
@@ -405,7 +457,10 @@ int factor_t(sap_handle h, const double *a_band, hipStream_t s)
     lu.corner = h->coupled ? h->ptr<T>(h->L.corner) : nullptr;
     lu.status = h->ptr<int>(h->L.status);
     lu.with_ul = h->coupled ? 1 : 0;
-    HIP_TRY(launch_banded_lu<T>(lu, s));
+    {
+        ProfScope ps(h, SAP_KERNEL_LU, s);
+        HIP_TRY(launch_banded_lu<T>(lu, s));
+    }
     HIP_TRY(hipEventRecord(h->ev[1], s));
     if (h->coupled) {
         TipsArgs<T> ta{};
@@ -418,6 +473,7 @@ int factor_t(sap_handle h, const double *a_band, hipStream_t s)
         ta.Rinv = h->ptr<T>(h->L.Rinv);
         ta.piv = h->ptr<int>(h->L.piv);
         ta.status = lu.status;
+        ProfScope ps(h, SAP_KERNEL_TIPS, s);
         HIP_TRY(launch_tips<T>(ta, s));
     }
     return SAP_OK;
@@ -506,7 +562,10 @@ int sap_factor(sap_handle h, const double *a_band, void *stream)
     }
     HIP_TRY(hipMemsetAsync(h->ptr<int>(h->L.status), 0, 64, s));
     HIP_TRY(hipEventRecord(h->ev[0], s));
-    HIP_TRY(launch_block_norm(a_band, h->pt, h->ptr<double>(h->L.partial), h->nchunk, s));
+    {
+        ProfScope ps(h, SAP_KERNEL_NORM, s);
+        HIP_TRY(launch_block_norm(a_band, h->pt, h->ptr<double>(h->L.partial), h->nchunk, s));
+    }
     int rc = h->fp32 ? factor_t<float>(h, a_band, s) : factor_t<double>(h, a_band, s);
     if (rc) return rc;
     HIP_TRY(hipEventRecord(h->ev[2], s));
@@ -607,9 +666,43 @@ int sap_get_tips(sap_handle h, int32_t i, double *v, double *w, double *rbar, vo
     return SAP_OK;
 }
 
+int sap_profile(sap_handle h, int32_t enable)
+{
+    if (!h) return fail(SAP_ERR_INVALID, "null handle");
+    if (enable) {
+        h->precs.clear();
+        for (int i = 0; i < SAP_KERNEL_COUNT; ++i) {
+            h->prof_ms[i] = 0.0;
+            h->prof_n[i] = 0;
+        }
+    }
+    h->prof = enable != 0;
+    return SAP_OK;
+}
+
+int sap_kernel_time(sap_handle h, int32_t kernel, double *ms, int64_t *launches)
+{
+    if (!h) return fail(SAP_ERR_INVALID, "null handle");
+    if (kernel < 0 || kernel >= SAP_KERNEL_COUNT) return fail(SAP_ERR_INVALID, "bad kernel id");
+    if (!h->precs.empty()) {
+        HIP_TRY(hipEventSynchronize(h->pev[h->precs.back().second + 1]));
+        for (auto &r : h->precs) {
+            float t = 0.0f;
+            HIP_TRY(hipEventElapsedTime(&t, h->pev[r.second], h->pev[r.second + 1]));
+            h->prof_ms[r.first] += t;
+            h->prof_n[r.first] += 1;
+        }
+        h->precs.clear();
+    }
+    if (ms) *ms = h->prof_ms[kernel];
+    if (launches) *launches = h->prof_n[kernel];
+    return SAP_OK;
+}
+
 int sap_destroy(sap_handle h)
 {
     if (!h) return SAP_OK;
+    for (auto &e : h->pev) (void)hipEventDestroy(e);
     (void)hipHostFree(h->h_starts);
     (void)hipHostFree(h->h_slots);
     (void)hipHostFree(h->h_status);

@@ -33,7 +33,10 @@ SAP_PREC_FP32 = 1
 
 EXPORTED = ("sap_workspace_bytes", "sap_create", "sap_factor", "sap_solve",
             "sap_solve_adjoint", "sap_band_grad", "sap_handle_status", "sap_spmv",
-            "sap_precond_apply", "sap_get_tips", "sap_destroy", "sap_last_error")
+            "sap_precond_apply", "sap_get_tips", "sap_profile", "sap_kernel_time",
+            "sap_destroy", "sap_last_error")
+
+KERNELS = ("norm", "lu", "tips", "sweep", "corr", "spmv", "krylov")
 
 
 class SapLibraryMissing(RuntimeError):
@@ -89,6 +92,8 @@ def load_library(path: str = LIB_PATH):
     lib.sap_spmv.argtypes = [vp, vp, vp, i32, vp]
     lib.sap_precond_apply.argtypes = [vp, vp, vp, i32, vp]
     lib.sap_get_tips.argtypes = [vp, i32, vp, vp, vp, vp]
+    lib.sap_profile.argtypes = [vp, i32]
+    lib.sap_kernel_time.argtypes = [vp, i32, P(dbl), P(i64)]
     lib.sap_destroy.argtypes = [vp]
     lib.sap_last_error.restype = ctypes.c_char_p
     for name in EXPORTED:
@@ -226,6 +231,20 @@ class SapSolver:
         out = torch.empty_like(r) if out is None else out
         _check(load_library().sap_precond_apply(self.handle, _dptr(r, self.n, "r"),
                                                 _dptr(out, self.n, "z"), int(trans), _stream()))
+        return out
+
+    def profile(self, enable: bool):
+        """Bracket every kernel launch with HIP events (resets the counters)."""
+        _check(load_library().sap_profile(self.handle, 1 if enable else 0))
+
+    def kernel_times(self) -> dict:
+        """{kernel class: (total device ms, launches)} since profile(True)."""
+        out = {}
+        for i, name in enumerate(KERNELS):
+            ms, cnt = ctypes.c_double(0), ctypes.c_int64(0)
+            _check(load_library().sap_kernel_time(self.handle, i, ctypes.byref(ms),
+                                                  ctypes.byref(cnt)))
+            out[name] = (ms.value, cnt.value)
         return out
 
     def tips(self, i: int):

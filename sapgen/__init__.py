@@ -18,7 +18,8 @@ and Sec. 4.1):
 * off-diagonal a[r, c], 0 < |r - c| <= K, inside the matrix: U[-1, 1)
   from stream 0 at index r*(2K+1) + (c - r + K);
 * a[r, r] = s_r * d * sum_{c != r} |a[r, c]|, with s_r = +1 or -1 from the
-  sign of the stream-1 draw at index r (fair coin);
+  sign of the stream-1 draw at index r (fair coin); for K = 0 (no
+  off-diagonals) a[r, r] = s_r * d;
 * optional row scaling: row r multiplied by 10**(2*u_r), u_r from stream 3,
   applied after the diagonal is set (so every row keeps its dominance d);
 * x_true ~ U[-1, 1) from stream 2; b = A x_true;
@@ -138,7 +139,7 @@ def make_problem(n: int, k: int, d: float = 1.0, seed: int = 0,
     sign = np.where(splitmix64_uniform(seed, STREAM_SIGN,
                                        np.arange(n, dtype=np.uint64)) < 0.0,
                     -1.0, 1.0)
-    band[k, :] = sign * d * rowabs
+    band[k, :] = sign * d * (rowabs if k > 0 else 1.0)
     scale = None
     if row_scale_decades > 0.0:
         u = splitmix64_uniform(seed, STREAM_ROWSCALE, np.arange(n, dtype=np.uint64))

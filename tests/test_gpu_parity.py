@@ -1,0 +1,265 @@
+"""GPU parity: every step of the HIP path against the CPU oracle, through the
+C ABI (via the ctypes binding).  Tolerances:
+
+* FP64 factors: preconditioner outputs agree with the oracle to 1e-12
+  relative (both are exact-arithmetic equivalents; differences are rounding
+  order in K-term sums and the reciprocal-multiply for 1/u_jj).
+* FP32 factors: 2e-5 relative, i.e. ~300 units of FP32 roundoff (2^-23 =
+  1.2e-7) for the factor, tip and sweep arithmetic of well-conditioned
+  blocks (d >= 0.5).
+* Solves: relative error to the FP64 direct solution <= 1e-8 for d >= 0.5
+  and <= 1e-6 for weak dominance; true relative residual <= tol.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import sapgen
+
+pytestmark = pytest.mark.gpu
+
+DEV = torch.device("cuda:0")
+
+
+def solver(n, k, p, mode="coupled", prec="fp64", adjoint=False, boost_eps=0.0):
+    from paper_1509_07919_amd import SapSolver
+    return SapSolver(n, k, p, mode=mode, factor_prec=prec, adjoint=adjoint,
+                     boost_eps=boost_eps, device=DEV)
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64)).to(DEV)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def case(*a):
+    print("CASE", *a, flush=True)
+
+
+# --------------------------------------------------------------------- SpMV
+
+@pytest.mark.parametrize("n,k", [(1, 0), (257, 3), (1000, 0), (4097, 17), (10000, 63),
+                                 (3001, 64), (5000, 200), (20011, 255)])
+def test_spmv_parity(n, k):
+    case("spmv", n, k)
+    pb = sapgen.make_problem(n, k, seed=31, pad=np.nan)       # NaN padding is never read
+    s = solver(n, k, 1, mode="decoupled", prec="fp32" if k >= 128 else "fp64")
+    a = dev(pb.band)
+    s.factor(a)
+    v = sapgen.splitmix64_uniform(3, 7, np.arange(n))
+    y = host(s.spmv(dev(v)))
+    yt = host(s.spmv(dev(v), trans=True))
+    band0 = np.nan_to_num(pb.band)
+    want, want_t = oracle.bandmv(band0, n, k, v), oracle.bandmv(band0, n, k, v, trans=True)
+    scale = np.abs(band0).max() * max(np.abs(v).max(), 1e-300) * (2 * k + 1)
+    assert np.abs(y - want).max() <= 1e-15 * scale
+    assert np.abs(yt - want_t).max() <= 1e-15 * scale
+    s.close()
+
+
+# ----------------------------------------------------------- preconditioner
+
+PRECOND_CASES = [
+    (1000, 3, 4, "decoupled"), (1000, 3, 4, "coupled"), (3001, 10, 7, "coupled"),
+    (5003, 31, 9, "coupled"), (5003, 31, 9, "decoupled"), (20011, 50, 16, "coupled"),
+    (20000, 100, 16, "coupled"), (777, 0, 5, "coupled"), (64, 63, 1, "decoupled"),
+    (4000, 16, 125, "coupled"), (997, 12, 997, "decoupled"),
+]
+
+
+@pytest.mark.parametrize("n,k,p,mode", PRECOND_CASES)
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_precond_parity(n, k, p, mode, prec):
+    case("precond", n, k, p, mode, prec)
+    pb = sapgen.make_problem(n, k, d=1.0, seed=32)
+    eps = 2.0 ** -23 if prec == "fp32" else 2.0 ** -52
+    M = oracle.SapPrecond(pb.band, n, k, p, mode == "coupled", boost_eps=eps)
+    s = solver(n, k, p, mode=mode, prec=prec, adjoint=True)
+    s.factor(dev(pb.band))
+    r = sapgen.splitmix64_uniform(4, 7, np.arange(n))
+    z = host(s.precond(dev(r)))
+    zt = host(s.precond(dev(r), trans=True))
+    tol = 1e-12 if prec == "fp64" else 2e-5
+    assert rel(z, M.apply(r)) <= tol
+    assert rel(zt, M.apply_t(r)) <= tol
+    rc, nb = s.status()
+    assert rc == 0 and nb == M.n_boosted
+    s.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_tips_parity(prec):
+    n, k, p = 6007, 24, 11
+    case("tips", n, k, p, prec)
+    pb = sapgen.make_problem(n, k, d=0.7, seed=33)
+    M = oracle.SapPrecond(pb.band, n, k, p, True,
+                          boost_eps=2.0 ** -23 if prec == "fp32" else 2.0 ** -52)
+    s = solver(n, k, p, prec=prec)
+    s.factor(dev(pb.band))
+    tol = 1e-11 if prec == "fp64" else 5e-5
+    for i in (0, 4, p - 2):
+        v, w, rb = s.tips(i)
+        assert rel(v, M.V[i]) <= tol
+        assert rel(w, M.W[i]) <= tol
+        assert rel(rb, M.Rbar[i]) <= tol
+    s.close()
+
+
+# ------------------------------------------------------------------ solves
+
+SOLVE_CASES = [
+    # n, k, p, mode, prec, d, tol, err_tol
+    (4000, 8, 8, "coupled", "fp64", 1.0, 1e-12, 1e-10),
+    (4000, 8, 8, "decoupled", "fp64", 1.0, 1e-12, 1e-10),
+    (9973, 20, 13, "coupled", "fp32", 1.0, 1e-10, 1e-8),
+    (9973, 20, 13, "decoupled", "fp32", 0.5, 1e-10, 1e-8),
+    (12000, 40, 24, "coupled", "fp32", 0.5, 1e-10, 1e-8),
+    (30000, 70, 60, "coupled", "fp32", 1.0, 1e-10, 1e-8),
+    (30000, 70, 60, "coupled", "fp64", 1.0, 1e-10, 1e-8),
+    (8000, 12, 16, "coupled", "fp64", 0.1, 1e-10, 1e-6),
+]
+
+
+@pytest.mark.parametrize("n,k,p,mode,prec,d,tol,err_tol", SOLVE_CASES)
+def test_solve_parity(n, k, p, mode, prec, d, tol, err_tol):
+    case("solve", n, k, p, mode, prec, d)
+    pb = sapgen.make_problem(n, k, d=d, seed=34)
+    s = solver(n, k, p, mode=mode, prec=prec, adjoint=True)
+    s.factor(dev(pb.band))
+    x, st = s.solve(dev(pb.b), tol=tol, maxit=300)
+    x = host(x)
+    xr = oracle.solve_direct(pb.band, n, k, pb.b)
+    assert st.converged and st.rel_resid_true <= tol
+    assert st.iters == int(round(st.iters * 4)) / 4.0
+    r = pb.b - oracle.bandmv(pb.band, n, k, x)
+    assert np.linalg.norm(r) / np.linalg.norm(pb.b) <= tol * 1.0001
+    assert rel(x, xr) <= err_tol
+    # adjoint: A^T lambda = g with the transposed preconditioner
+    g = sapgen.splitmix64_uniform(5, 7, np.arange(n))
+    lam, st2 = s.solve_adjoint(dev(g), tol=tol, maxit=300)
+    lam = host(lam)
+    assert st2.converged
+    assert rel(lam, oracle.solve_direct(pb.band, n, k, g, trans=True)) <= err_tol
+    s.close()
+
+
+@pytest.mark.parametrize("p,mode", [(1, "decoupled"), (1, "coupled"), (2, "coupled")])
+def test_exact_cases_first_exit(p, mode):
+    """P=1 and coupled P=2 drop nothing: M^{-1} = A^{-1}, BiCGStab(2) exits at
+    the first exit point (0.25 iterations)."""
+    n, k = 6000, 9
+    case("exact", p, mode)
+    pb = sapgen.make_problem(n, k, d=1.0, seed=35)
+    s = solver(n, k, p, mode=mode, prec="fp64")
+    s.factor(dev(pb.band))
+    x, st = s.solve(dev(pb.b), tol=1e-12)
+    assert st.converged and st.iters == 0.25 and st.restarts == 0
+    assert rel(host(x), pb.x_true) <= 1e-12
+    s.close()
+
+
+def test_zero_rhs_and_determinism():
+    n, k, p = 5000, 7, 10
+    case("zero-rhs", n, k, p)
+    pb = sapgen.make_problem(n, k, seed=36)
+    s = solver(n, k, p, prec="fp32")
+    s.factor(dev(pb.band))
+    x, st = s.solve(torch.zeros(n, dtype=torch.float64, device=DEV))
+    assert st.converged and st.iters == 0.0 and np.abs(host(x)).max() == 0.0
+    x1, _ = s.solve(dev(pb.b), tol=1e-11)
+    x2, _ = s.solve(dev(pb.b), tol=1e-11)
+    assert np.array_equal(host(x1), host(x2))
+    s.factor(dev(pb.band))                      # refactor: same bits again
+    x3, _ = s.solve(dev(pb.b), tol=1e-11)
+    assert np.array_equal(host(x1), host(x3))
+    s.close()
+
+
+def test_pivot_boosting():
+    """Zero pivots: with boosting they are replaced by +-tau and counted (same
+    count as the oracle); with boosting disabled the factorization reports
+    SAP_ERR_SINGULAR."""
+    from paper_1509_07919_amd import SapError
+    n, k, p = 3000, 4, 6
+    case("boost", n, k, p)
+    pb = sapgen.make_problem(n, k, seed=37)
+    band = pb.band.copy()
+    for r in (0, 1000, 2500):                    # zero diagonal entries
+        band[k * n + r] = 0.0
+    b = oracle.bandmv(band, n, k, pb.x_true)
+    M = oracle.SapPrecond(band, n, k, p, True, boost_eps=2.0 ** -23)
+    s = solver(n, k, p, prec="fp32", boost_eps=0.0)
+    s.factor(dev(band))
+    rc, nbst = s.status()
+    assert rc == 0 and nbst == M.n_boosted and nbst >= 3
+    x, st = s.solve(dev(b), tol=1e-10, maxit=200)
+    assert st.converged
+    assert rel(host(x), oracle.solve_direct(band, n, k, b)) <= 1e-7
+    s.close()
+    s2 = solver(n, k, p, prec="fp64", boost_eps=-1.0)
+    s2.factor(dev(band))
+    rc, _ = s2.status()
+    assert rc == -5
+    with pytest.raises(SapError):
+        s2.solve(dev(b), raise_nc=True)
+    s2.close()
+
+
+def test_band_grad_parity():
+    n, k, p = 3000, 5, 4
+    case("band_grad", n, k, p)
+    pb = sapgen.make_problem(n, k, seed=38)
+    s = solver(n, k, p)
+    s.factor(dev(pb.band))
+    lam = sapgen.splitmix64_uniform(6, 7, np.arange(n))
+    g = host(s.band_grad(dev(lam), dev(pb.x_true)))
+    assert np.array_equal(g, oracle.band_grad(lam, pb.x_true, n, k))
+    s.close()
+
+
+def test_autograd_matches_oracle_gradient():
+    """L = 0.5||x - x_t||^2: dL/db and dL/dA_band from the adjoint solve agree
+    with the oracle's dense-definition gradients, and with central
+    differences of oracle direct solves (h = 1e-6)."""
+    from paper_1509_07919_amd import sap_solve_autograd
+    n, k, p = 400, 3, 2
+    case("autograd", n, k, p)
+    pb = sapgen.make_problem(n, k, seed=39)
+    xt = sapgen.normal_draws(39, sapgen.STREAM_XTARGET, n)
+    s = solver(n, k, p, prec="fp64", adjoint=True)
+    a = dev(pb.band).requires_grad_(True)
+    b = dev(pb.b).requires_grad_(True)
+    x = sap_solve_autograd(a, b, s, tol=1e-13)
+    loss = 0.5 * ((x - dev(xt)) ** 2).sum()
+    loss.backward()
+    _, gb, ga = oracle.gradients(pb.band, n, k, pb.b, xt)
+    assert rel(host(b.grad), gb) <= 1e-9
+    assert rel(host(a.grad), ga) <= 1e-9
+
+    def lossf(band, rhs):
+        y = oracle.solve_direct(band, n, k, rhs)
+        return 0.5 * np.sum((y - xt) ** 2)
+
+    h = 1e-6
+    gbh, gah = host(b.grad), host(a.grad)
+    for j in (3, 200):
+        e = np.zeros(n); e[j] = h
+        fd = (lossf(pb.band, pb.b + e) - lossf(pb.band, pb.b - e)) / (2 * h)
+        assert abs(fd - gbh[j]) <= 1e-6 * max(1.0, abs(gbh[j]))
+    for (r, c) in ((10, 10), (50, 52), (300, 297)):
+        pos = (k + r - c) * n + c
+        bp, bm = pb.band.copy(), pb.band.copy()
+        bp[pos] += h; bm[pos] -= h
+        fd = (lossf(bp, pb.b) - lossf(bm, pb.b)) / (2 * h)
+        assert abs(fd - gah[pos]) <= 1e-5 * max(1.0, abs(gah[pos]))
+    s.close()
