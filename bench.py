@@ -24,6 +24,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "solve ms & HBM GB/s, N=200k K=50; FP32-factor vs FP64 SaP at 1e-10 resid"
 HBM_PEAK_GBS = 8000.0           # MI355X HBM3E
+FP64_VEC_TFLOPS = 78.6          # MI355X vector FP64 (256 CU x 4 SIMD x 16 lanes x 2 x 2.4 GHz)
+FP32_VEC_TFLOPS = 157.3         # MI355X published vector FP32
 PROFILE_DIR = os.path.join(ROOT, "profiles")
 
 
@@ -45,6 +47,18 @@ def lu_bytes(n, k, sf, coupled):
     return dirs * 8.0 * (2 * k + 1) * n + 2.0 * n * (k + 1) * sf
 
 
+def lu_flops(n, k, coupled):
+    """Block LU (and UL for SaP-C): per pivot K divisions and K^2 FMAs."""
+    return (2 if coupled else 1) * (2.0 * n * k * k + n * k)
+
+
+def tips_flops(n, k, p):
+    """Per interface: four K x K triangular solves with K right-hand sides
+    (4 * K^3 flops), Rbar = I - W V (2 K^3), LU of Rbar (2/3 K^3) and its
+    inverse (2 K^3)."""
+    return (p - 1) * (4.0 + 2.0 + 2.0 / 3.0 + 2.0) * k ** 3
+
+
 def kernel_source_hash(name: str) -> str:
     path = os.path.join(ROOT, "paper_1509_07919_amd", "csrc", name)
     with open(path, "rb") as f:
@@ -55,7 +69,7 @@ def traffic_from_profiles(kernel_file: str, tag: str):
     """HBM bytes per launch measured with rocprofv3 counters, from a committed
     summary that records the hash of the kernel source it was taken on; None
     if absent or if the kernel changed since."""
-    path = os.path.join(PROFILE_DIR, "traffic.json")
+    path = os.path.join(PROFILE_DIR, "traffic_%s.json" % tag.split("_", 2)[2])
     if not os.path.exists(path):
         return None
     with open(path) as f:
@@ -121,6 +135,8 @@ def main():
     ap.add_argument("--cpu-reps", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--precs", default="fp64,fp32")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only; --gpus %d is not supported"
@@ -165,18 +181,31 @@ def main():
             ent["bytes_per_launch"] = per_launch[name]
             ent["algorithmic_GBps"] = per_launch[name] / (1e-3 * tms / cnt) / 1e9
         kernels[name] = ent
+    flops_per_launch = {"lu": lu_flops(n, k, coupled), "tips": tips_flops(n, k, cfg["p"])}
+    for name, fl in flops_per_launch.items():
+        if name in kernels:
+            kernels[name]["flops_per_launch"] = fl
+            kernels[name]["algorithmic_TFLOPs"] = fl / (1e-6 * kernels[name]["avg_us"]) / 1e12
     dom = max(kernels, key=lambda q: kernels[q]["ms_per_step"])
-    if dom in per_launch:
-        src = {"sweep": "k_sweep.hip", "spmv": "k_vec.hip", "lu": "k_factor.hip"}[dom]
-        avg_s = 1e-3 * r["kt"][dom][0] / r["kt"][dom][1]
+    src = {"sweep": "k_sweep.hip", "spmv": "k_vec.hip", "lu": "k_factor.hip",
+           "tips": "k_tips.hip"}.get(dom)
+    avg_s = 1e-3 * r["kt"][dom][0] / r["kt"][dom][1]
+    traffic = traffic_from_profiles(src, "%s_%s_%s" % (dom, head, args.workload)) if src else None
+    if dom in per_launch and dom not in flops_per_launch:
         ach = per_launch[dom] / avg_s / 1e9
         roof = {"kernel": dom, "bound": "hbm", "achieved": round(ach, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
-                "traffic": traffic_from_profiles(src, "%s_%s_%s" % (dom, head, args.workload)),
-                "avg_us": round(avg_s * 1e6, 2),
+                "traffic": traffic, "avg_us": round(avg_s * 1e6, 2),
                 "bytes_per_launch": per_launch[dom]}
+    elif dom in flops_per_launch:
+        peak = FP64_VEC_TFLOPS if head == "fp64" else FP32_VEC_TFLOPS
+        ach = flops_per_launch[dom] / avg_s / 1e12
+        roof = {"kernel": dom, "bound": "alu", "achieved": round(ach, 4), "peak": peak,
+                "unit": "TFLOP/s", "frac": round(ach / peak, 5), "traffic": traffic,
+                "avg_us": round(avg_s * 1e6, 2), "flops_per_launch": flops_per_launch[dom],
+                "bytes_per_launch": per_launch.get(dom)}
     else:
-        roof = {"kernel": dom, "bound": None, "note": "no byte model for this kernel class"}
+        roof = {"kernel": dom, "bound": None, "note": "no work model for this kernel class"}
 
     def summary(prec):
         q = runs[prec]
@@ -206,6 +235,13 @@ def main():
         out["race"] = {"fp64_ms": round(runs["fp64"]["ms"], 4),
                        "fp32_factor_ms": round(runs["fp32"]["ms"], 4),
                        "fp32_speedup": round(runs["fp64"]["ms"] / runs["fp32"]["ms"], 3)}
+    if args.copy_calibration:
+        src_t = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
+        dst_t = torch.empty_like(src_t)
+        dst_t.copy_(src_t)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = {"read": src_t.numel() * 8, "write": dst_t.numel() * 8}
+        del src_t, dst_t
     if not args.no_cpu:
         cms, xo, res = cpu_baseline(cfg, pb, args.cpu_reps)
         out["cpu_baseline"] = {

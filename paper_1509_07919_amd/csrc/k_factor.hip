@@ -90,9 +90,11 @@ __global__ __launch_bounds__(NT) void k_banded_lu(LuArgs<T> a)
     constexpr int KMAX = WC - 1;
     constexpr int PR = ((2 * KMAX + 1) * S + NT - 1) / NT;   // prefetch regs
 
+    // stage buffer b: rows q = -1..2K+1 of S entries at stage + b*stage_sz +
+    // (q+1)*S; rows -1 and 2K+1 stay zero, so clamped row indices need no mask
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    T *stage = reinterpret_cast<T *>(smem_raw);               // [2][(2K+1)*S]
-    T *obuf = stage + 2 * (2 * a.pt.k + 1) * S;               // [S][2][K+1]
+    T *stage = reinterpret_cast<T *>(smem_raw);               // [2][(2K+3)*S]
+    T *obuf = stage + 2 * (2 * a.pt.k + 3) * S;               // [S][2][K+1]
     __shared__ __align__(16) T lcol[2][WC];                   // perm: [rs*RPT+i]
     __shared__ __align__(16) T urow[2][WC];
     __shared__ double tau_sh;
@@ -109,7 +111,7 @@ __global__ __launch_bounds__(NT) void k_banded_lu(LuArgs<T> a)
     const int rs = tid / WC;
     const int CS = k + 1;
     const int W2 = 2 * k + 1;
-    const int stage_sz = W2 * S;
+    const int stage_sz = (W2 + 2) * S;
 
     // boost threshold tau = eps * max|A_i| (in the factor precision)
     if (tid == 0) {
@@ -148,7 +150,7 @@ __global__ __launch_bounds__(NT) void k_banded_lu(LuArgs<T> a)
             const int delta = q - k;
             const int64_t m = WC + t * S + ss;
             T v = T(0);
-            if (q < W2 && m < nb) {      // m > K >= |delta|: other index >= 0
+            if (f < W2 * S && m < nb) {  // m > K >= |delta|: other index >= 0
                 const int64_t base = (int64_t)(ul ? (k - delta) : (k + delta)) * n;
                 const int64_t col = ul ? (s0 + nb - 1 - m + (delta > 0 ? delta : 0))
                                        : (s0 + m - (delta > 0 ? delta : 0));
@@ -158,13 +160,17 @@ __global__ __launch_bounds__(NT) void k_banded_lu(LuArgs<T> a)
         }
     };
     auto commit = [&](int64_t t) {
-        T *dst = stage + (t & 1) * stage_sz;
+        T *dst = stage + (t & 1) * stage_sz + S;
 #pragma unroll
         for (int i = 0; i < PR; ++i) {
             const int f = tid + NT * i;
-            if (f < stage_sz) dst[f] = pre[i];
+            if (f < W2 * S) dst[f] = pre[i];
         }
     };
+    for (int idx = tid; idx < 4 * S; idx += NT) {          // the zero rows
+        const int bsel = idx / (2 * S), r = (idx / S) & 1, c = idx % S;
+        stage[bsel * stage_sz + (r ? (W2 + 1) * S : 0) + c] = T(0);
+    }
     // Outputs of one chunk of S steps (L column and U row of each step) are
     // kept in LDS and written out by all threads at the next chunk boundary,
     // so no global access is pending between boundaries.
@@ -253,20 +259,22 @@ __global__ __launch_bounds__(NT) void k_banded_lu(LuArgs<T> a)
         }
 
         // entering row and column j+WC replace ring slot u
-        const T *stg = stage + ((j / S) & 1) * stage_sz;
+        // (row q of the stage holds delta = q - K; out-of-band deltas are
+        // clamped onto the zero rows -1 and 2K+1)
+        const T *stg = stage + ((j / S) & 1) * stage_sz + S;
         const int so = (int)(j & (S - 1));
         if (own_row) {
             const int dc = (sc - u - 1) & (WC - 1);          // col = j+1+dc
-            const int delta = WC - 1 - dc;                   // (j+WC) - col
-            w[0] = delta <= k ? stg[(delta + k) * S + so] : T(0);
+            const int delta = WC - 1 - dc;                   // (j+WC) - col >= 0
+            w[0] = stg[min(delta + k, W2) * S + so];
         }
         if (sc == u) {
 #pragma unroll
             for (int i = 0; i < RPT; ++i) {
                 const int sr = rs + RS * ((i + rot) & (RPT - 1));
                 const int dr = (sr - u - 1) & (WC - 1);
-                const int delta = WC - 1 - dr;               // (j+WC) - row
-                w[i] = delta <= k ? stg[(k - delta) * S + so] : T(0);
+                const int delta = WC - 1 - dr;               // (j+WC) - row >= 0
+                w[i] = stg[max(k - delta, -1) * S + so];
             }
         }
         if (own_row) {
@@ -286,7 +294,7 @@ __global__ __launch_bounds__(NT) void k_banded_lu(LuArgs<T> a)
 template <typename T, int WC, int S, int NT>
 static hipError_t launch_lu_cfg(const LuArgs<T> &a, hipStream_t s)
 {
-    const size_t lds = (2 * (size_t)(2 * a.pt.k + 1) * S + (size_t)S * 2 * (a.pt.k + 1)) * sizeof(T);
+    const size_t lds = (2 * (size_t)(2 * a.pt.k + 3) * S + (size_t)S * 2 * (a.pt.k + 1)) * sizeof(T);
     auto kern = k_banded_lu<T, WC, S, NT>;
     hipError_t e = hipFuncSetAttribute((const void *)kern,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

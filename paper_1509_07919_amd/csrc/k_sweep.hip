@@ -41,7 +41,9 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs<T> a)
 {
     static_assert(S % 64 == 0, "chunk must hold whole 64-step blocks");
     static_assert(KR >= 2, "ring must cover 64 + K slots");
-    constexpr int PITCH = 64 * (KR - 1);              // LDS row pitch, >= K + 1
+    // LDS row pitch: slots 0..K hold a coefficient row, slots K+1..PITCH-1
+    // are zero (the last 8 always), so a clamped offset needs no mask
+    constexpr int PITCH = 64 * (KR - 1) + 8;
 
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *cst = reinterpret_cast<T *>(smem_raw);         // [2][S][PITCH]
@@ -58,6 +60,9 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs<T> a)
     const int64_t nchunks = (nb + S - 1) / S;
     const T *dtop = (a.dtop && blk > 0) ? a.dtop + (int64_t)blk * k : nullptr;
     const T *dbot = (a.dbot && blk < a.pt.p - 1) ? a.dbot + (int64_t)blk * k : nullptr;
+
+    for (int idx = tid; idx < 2 * S * 8; idx += 256)
+        cst[(idx >> 3) * PITCH + 64 * (KR - 1) + (idx & 7)] = T(0);
 
     // row of the block handled at step t
     auto row_of = [&](int64_t t) -> int64_t { return FWD ? t : nb - 1 - t; };
@@ -159,10 +164,11 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs<T> a)
                     q.vd[e] = vv[64 * g + u] * q.d[e];
 #pragma unroll
                     for (int s = 0; s < KR; ++s) {
-                        const int m = 64 * s + lane - u;     // step offset of slot (s, lane)
-                        const int mc = min(max(m, 0), PITCH - 1);
-                        const T raw = crow[mc];
-                        q.cf[e][s] = (m >= 1 && m <= k) ? raw : T(0);
+                        // step offset of slot (s, lane).  Offsets > K read a
+                        // zero slot; offsets <= 0 occur only for s = 0 in lanes
+                        // whose step is already done, where the value is unused.
+                        const int m = 64 * s + lane - u;
+                        q.cf[e][s] = crow[min(max(m, 0), PITCH - 1)];
                     }
                 }
             };
@@ -205,7 +211,7 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs<T> a)
 template <typename T, int KR, int S, bool FWD, bool DIAG>
 static hipError_t launch_sweep_cfg(const SweepArgs<T> &a, hipStream_t s)
 {
-    const size_t lds = (2 * (size_t)S * 64 * (KR - 1) + 2 * S) * sizeof(T);
+    const size_t lds = (2 * (size_t)S * (64 * (KR - 1) + 8) + 2 * S) * sizeof(T);
     auto kern = k_sweep<T, KR, S, FWD, DIAG>;
     hipError_t e = hipFuncSetAttribute((const void *)kern,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -226,17 +232,23 @@ static hipError_t launch_sweep_kr(const SweepArgs<T> &a, hipStream_t s)
     return launch_sweep_cfg<T, KR, 64, false, false>(a, s);
 }
 
-template <typename T>
-hipError_t launch_sweep(const SweepArgs<T> &a, hipStream_t s)
+template <>
+hipError_t launch_sweep<float>(const SweepArgs<float> &a, hipStream_t s)
 {
     const int k = a.pt.k;
-    if (k < 64) return launch_sweep_kr<T, 2>(a, s);
-    if (k < 128) return launch_sweep_kr<T, 3>(a, s);
-    if (k < 192) return launch_sweep_kr<T, 4>(a, s);
-    return launch_sweep_kr<T, 5>(a, s);
+    if (k < 64) return launch_sweep_kr<float, 2>(a, s);
+    if (k < 128) return launch_sweep_kr<float, 3>(a, s);
+    if (k < 192) return launch_sweep_kr<float, 4>(a, s);
+    return launch_sweep_kr<float, 5>(a, s);
 }
 
-template hipError_t launch_sweep<float>(const SweepArgs<float> &, hipStream_t);
-template hipError_t launch_sweep<double>(const SweepArgs<double> &, hipStream_t);
+template <>
+hipError_t launch_sweep<double>(const SweepArgs<double> &a, hipStream_t s)
+{
+    const int k = a.pt.k;
+    if (k < 64) return launch_sweep_kr<double, 2>(a, s);
+    if (k < 128) return launch_sweep_kr<double, 3>(a, s);
+    return hipErrorInvalidValue;               // FP64 factors support K <= 127
+}
 
 }  // namespace sap

@@ -23,9 +23,12 @@
 
 namespace sap {
 
+// Workgroup barrier that also orders the workgroup's global-memory
+// accesses (needed only when the working matrices live in global memory).
+template <bool LDS>
 __device__ __forceinline__ void block_sync()
 {
-    __threadfence();
+    if (!LDS) __threadfence_block();
     __syncthreads();
 }
 
@@ -59,7 +62,7 @@ __global__ __launch_bounds__(256) void k_tips(TipsArgs<T> a)
         const int64_t cr = s1 + r, cc = s1 - k + c;          // C: a[cr][cc]
         C[e] = (r <= c) ? (T)a.band[(int64_t)(k + cr - cc) * n + cc] : T(0);
     }
-    block_sync();
+    block_sync<LDS>();
 
     const int64_t base = s1 - k;                // first row of block i's bottom corner
     const int b = tid;
@@ -96,7 +99,7 @@ __global__ __launch_bounds__(256) void k_tips(TipsArgs<T> a)
         }
         for (int r = 0; r < k; ++r) W[r * k + b] = Y[r * k + b];
     }
-    block_sync();
+    block_sync<LDS>();
     // Rbar = I - W V (column b), from the working copies; Rbar kept in X
     if (b < k) {
         for (int r = 0; r < k; ++r) {
@@ -105,9 +108,9 @@ __global__ __launch_bounds__(256) void k_tips(TipsArgs<T> a)
             R[r * k + b] = s;
         }
     }
-    block_sync();
+    block_sync<LDS>();
     for (int64_t e = tid; e < kk; e += 256) X[e] = R[e];
-    block_sync();
+    block_sync<LDS>();
     // LU with partial pivoting of Rbar in X, ties to the lowest row
     for (int j = 0; j < k; ++j) {
         if (tid == 0) {
@@ -121,7 +124,7 @@ __global__ __launch_bounds__(256) void k_tips(TipsArgs<T> a)
             pr_sh = p;
             if (best == T(0)) a.status[1] = 2;
         }
-        block_sync();
+        block_sync<LDS>();
         const int p = pr_sh;
         if (p != j)
             for (int c = tid; c < k; c += 256) {
@@ -129,15 +132,15 @@ __global__ __launch_bounds__(256) void k_tips(TipsArgs<T> a)
                 X[j * k + c] = X[p * k + c];
                 X[p * k + c] = t;
             }
-        block_sync();
+        block_sync<LDS>();
         const T d = X[j * k + j];
         for (int r = j + 1 + tid; r < k; r += 256) X[r * k + j] = X[r * k + j] / d;
-        block_sync();
+        block_sync<LDS>();
         for (int c = j + 1 + tid; c < k; c += 256) {
             const T ujc = X[j * k + c];
             for (int r = j + 1; r < k; ++r) X[r * k + c] = fma(-X[r * k + j], ujc, X[r * k + c]);
         }
-        block_sync();
+        block_sync<LDS>();
     }
     // Rinv = Rbar^{-1}: column b solves Rbar y = e_b with the pivoted LU (in Y)
     if (b < k) {
