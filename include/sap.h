@@ -67,7 +67,7 @@ extern "C" {
 
 typedef struct sap_options {
     int64_t n;            /* matrix order N >= 1                            */
-    int32_t k;            /* half-bandwidth K, 0 <= K < N, K <= 255         */
+    int32_t k;            /* half-bandwidth K, 0 <= K < N, K <= 255 (K <= 208 with FP64 factors) */
     int32_t p;            /* partitions P, 1 <= P <= N (SaP-C: N/P >= 2K)   */
     int32_t mode;         /* SAP_DECOUPLED or SAP_COUPLED                   */
     int32_t factor_prec;  /* SAP_PREC_FP64 or SAP_PREC_FP32                 */
@@ -76,7 +76,10 @@ typedef struct sap_options {
                           /*  2^-23); < 0 disables boosting.                 */
     int32_t adjoint;      /* nonzero: also keep the transposed factor copies */
                           /*  needed by sap_solve_adjoint                    */
-    int32_t reserved;     /* must be 0                                      */
+    int32_t sweep_chunks; /* chains per block in each triangular sweep:     */
+                          /*  0 -> chosen by the library, 1 -> one chain    */
+                          /*  per block, >= 2 -> at most this many (each    */
+                          /*  chunk then holds >= 64 rows); must be >= 0    */
 } sap_options;
 
 typedef struct sap_stats {

@@ -24,8 +24,10 @@
 // (2K+1 diagonal segments, each a coalesced run) into double-buffered LDS,
 // one chunk ahead of use.
 #include "sap_internal.h"
+#include "dev_common.h"
 
 namespace sap {
+
 
 // ---------------------------------------------------------------- norms
 
@@ -70,16 +72,6 @@ hipError_t launch_block_norm(const double *band, const Partition &pt, double *pa
 
 // Entry (r, c) of the block as seen by the LU (ul = 0) or by the LU of the
 // reversed block (ul = 1); 0 outside the block or the band.
-__device__ __forceinline__ double block_entry(const double *__restrict__ band, int64_t n,
-                                              int k, int64_t s0, int64_t nb, int ul,
-                                              int64_t r, int64_t c)
-{
-    const int64_t d = r - c;
-    if (r < 0 || c < 0 || r >= nb || c >= nb || d > k || d < -k) return 0.0;
-    const int64_t q = ul ? (k - d) : (k + d);
-    const int64_t col = ul ? (s0 + nb - 1 - c) : (s0 + c);
-    return band[q * n + col];
-}
 
 template <typename T, int WC, int S, int NT>
 __global__ __launch_bounds__(NT) void k_banded_lu(LuArgs<T> a)
@@ -291,6 +283,285 @@ __global__ __launch_bounds__(NT) void k_banded_lu(LuArgs<T> a)
     if (tid == 0 && nboost) atomicAdd(&a.status[0], nboost);
 }
 
+// ------------------------------------------------------------ blocked LU
+//
+// The same factorization, B pivots per panel.  The active window of the block
+// -- rows and columns j0 .. j0+K+B-1 -- is a (K+B) x (K+B) array in LDS,
+// double-buffered.  Per panel (three barriers):
+//   1. wave 0 factors the (K+B) x B panel in registers (one row per lane,
+//      pivot rows broadcast with v_readlane), with the same boosting rule;
+//   2. K threads form U12 = L11^{-1} A12 (B x K), one column each;
+//   3. all threads apply the rank-B Schur update A22 -= L21 U12 and write the
+//      result straight into the other buffer shifted by (B, B), so the window
+//      slides for free; the B rows and columns that enter are copied from the
+//      LDS stage, and the panel's L columns and U rows go to the output buffer.
+// Row r of block i appears at window row r - j0 for the LU; the UL runs the
+// same code on the reversed block.
+template <typename T, int B, int S, int NT, int RPL>
+__global__ __launch_bounds__(NT) void k_banded_lu_blk(LuArgs<T> a)
+{
+    static_assert(S % B == 0, "chunks hold whole panels");
+    constexpr int KMAX = 64 * RPL - B;          // window K + B fits RPL rows per lane
+    constexpr int NW = NT / 64;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ double tau_sh;
+
+    const int k = a.pt.k;
+    const int64_t n = a.pt.n;
+    const int P = a.pt.p;
+    const int ul = (int)blockIdx.x >= P;
+    const int blk = ul ? (int)blockIdx.x - P : (int)blockIdx.x;
+    const int64_t s0 = a.pt.starts[blk];
+    const int64_t nb = a.pt.starts[blk + 1] - s0;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int CS = k + 1;
+    const int KB = k + B;                       // window size
+    const int WP = KB + 1;                      // LDS pitch (odd: no bank conflicts on columns)
+    const int W2 = 2 * k + 1;
+    const int stage_sz = (W2 + 2) * S;
+
+    T *win0 = reinterpret_cast<T *>(smem_raw);  // [2][KB][WP]
+    T *stage = win0 + 2 * KB * WP;              // [2][(2K+3)][S], zero rows at q = -1, 2K+1
+    T *obuf = stage + 2 * stage_sz;             // [S][2][K+1]
+
+    if (tid == 0) {
+        double m = 0.0;
+        for (int c = 0; c < a.nchunk; ++c) m = fmax(m, a.partial[(int64_t)blk * a.nchunk + c]);
+        tau_sh = a.boost_eps >= 0.0 ? a.boost_eps * (double)(T)m : -1.0;
+    }
+    if (!ul) {
+        for (int idx = tid; idx < k * CS; idx += NT) {
+            const int c = idx / CS, m = idx % CS;
+            if (c < nb && m > c) {
+                a.Uc[(s0 + c) * CS + m] = T(0);
+                if (a.Lr) a.Lr[(s0 + c) * CS + m] = T(0);
+            }
+        }
+    }
+    // initial window: rows/cols 0 .. KB-1
+    for (int idx = tid; idx < KB * KB; idx += NT) {
+        const int r = idx / KB, c = idx % KB;
+        win0[r * WP + c] = (T)block_entry(a.band, n, k, s0, nb, ul, r, c);
+    }
+    // entering index e >= 0 is global index m = KB + e; chunk t stages
+    // e in [t*S, t*S+S): stage[(q+1)*S + s] = entry (m, m-delta) for delta >= 0
+    // or (m+delta, m) for delta < 0, delta = q - K
+    constexpr int PR = ((2 * KMAX + 1) * S + NT - 1) / NT;
+    const int nitems = W2 * S;
+    T pre[PR];
+    auto prefetch = [&](int64_t t) {
+#pragma unroll
+        for (int i = 0; i < PR; ++i) {
+            const int f = tid + NT * i;
+            const int q = f / S, ss = f % S;
+            const int delta = q - k;
+            const int64_t m = KB + t * S + ss;
+            T v = T(0);
+            if (f < nitems && m < nb) {       // m >= KB > K >= |delta|
+                const int64_t base = (int64_t)(ul ? (k - delta) : (k + delta)) * n;
+                const int64_t col = ul ? (s0 + nb - 1 - m + (delta > 0 ? delta : 0))
+                                       : (s0 + m - (delta > 0 ? delta : 0));
+                v = (T)a.band[base + col];
+            }
+            pre[i] = v;
+        }
+    };
+    auto commit = [&](int64_t t) {
+        T *dst = stage + (t & 1) * stage_sz + S;
+#pragma unroll
+        for (int i = 0; i < PR; ++i) {
+            const int f = tid + NT * i;
+            if (f < nitems) dst[f] = pre[i];
+        }
+    };
+    for (int idx = tid; idx < 4 * S; idx += NT) {
+        const int bsel = idx / (2 * S), r = (idx / S) & 1, c = idx % S;
+        stage[bsel * stage_sz + (r ? (W2 + 1) * S : 0) + c] = T(0);
+    }
+    auto flush = [&](int64_t j0f) {
+        if (ul) return;
+        const int tot = S * CS;
+        for (int idx = tid; idx < tot; idx += NT) {
+            const int jj = idx / CS, m = idx - jj * CS;
+            const int64_t j = j0f + jj;
+            if (j >= nb) continue;
+            const T lv = obuf[jj * 2 * CS + m];
+            const T uv = obuf[jj * 2 * CS + CS + m];
+            const bool in = j + m < nb;
+            a.Lc[(s0 + j) * CS + m] = lv;
+            if (in) a.Uc[(s0 + j + m) * CS + m] = uv;
+            if (a.Ur) a.Ur[(s0 + j) * CS + m] = in ? uv : T(0);
+            if (a.Lr && in) a.Lr[(s0 + j + m) * CS + m] = lv;
+        }
+    };
+    prefetch(0);
+    __syncthreads();
+    __builtin_amdgcn_s_waitcnt(0);
+    const double tau_d = tau_sh;
+    const T tau = (T)tau_d;
+    const bool do_boost = tau_d >= 0.0;
+    int nboost = 0;
+
+    const int64_t npanel = (nb + B - 1) / B;
+    for (int64_t pnl = 0; pnl < npanel; ++pnl) {
+        const int64_t j0 = pnl * B;
+        T *W = win0 + (pnl & 1) * KB * WP;            // current window
+        T *Wn = win0 + ((pnl + 1) & 1) * KB * WP;     // next window
+        const int64_t e0 = j0;                        // entering indices of this panel
+        if ((e0 % S) == 0) {
+            commit(e0 / S);
+            if (j0 > 0) flush(j0 - S);
+        }
+        const int nact = (int)min((int64_t)B, nb - j0);   // pivots in this panel
+
+        // 1. panel factorization by wave 0
+        if (wave == 0) {
+            T pv[RPL][B];
+#pragma unroll
+            for (int x = 0; x < RPL; ++x) {
+                const int rr = lane + 64 * x;
+#pragma unroll
+                for (int t = 0; t < B; ++t) pv[x][t] = rr < KB ? W[rr * WP + t] : T(0);
+            }
+#pragma unroll
+            for (int t = 0; t < B; ++t) {
+                if (t < nact) {
+                    T praw = pv[0][t];
+                    praw = lane_bcast(praw, t);
+                    T piv = praw;
+                    bool boosted = false;
+                    if (do_boost && fabs((double)praw) < (double)tau) {
+                        piv = praw >= T(0) ? tau : -tau;
+                        boosted = true;
+                    }
+                    if (lane == 0) {
+                        nboost += boosted ? 1 : 0;
+                        if (piv == T(0)) a.status[1] = 1;
+                    }
+                    const T inv = T(1) / piv;
+                    T urow[B];
+#pragma unroll
+                    for (int c = t + 1; c < B; ++c) urow[c] = lane_bcast(pv[0][c], t);
+#pragma unroll
+                    for (int x = 0; x < RPL; ++x) {
+                        const int rr = lane + 64 * x;
+                        if (rr > t) {
+                            const T l = pv[x][t] * inv;
+                            pv[x][t] = l;
+#pragma unroll
+                            for (int c = t + 1; c < B; ++c) pv[x][c] = fma(-l, urow[c], pv[x][c]);
+                        } else if (rr == t) {
+                            pv[x][t] = piv;
+                        }
+                    }
+                }
+            }
+#pragma unroll
+            for (int x = 0; x < RPL; ++x) {
+                const int rr = lane + 64 * x;
+                if (rr < KB)
+#pragma unroll
+                    for (int t = 0; t < B; ++t) W[rr * WP + t] = pv[x][t];
+            }
+        }
+        __syncthreads();
+
+        // 2. U12 = L11^{-1} A12 (rows 0..B-1, window columns B..KB-1)
+        for (int c = B + tid; c < KB; c += NT) {
+            T u[B];
+#pragma unroll
+            for (int t = 0; t < B; ++t) {
+                T v = W[t * WP + c];
+#pragma unroll
+                for (int s2 = 0; s2 < t; ++s2) v = fma(-W[t * WP + s2], u[s2], v);
+                u[t] = v;
+            }
+#pragma unroll
+            for (int t = 0; t < B; ++t) W[t * WP + c] = u[t];
+        }
+        __syncthreads();
+
+        // 3a. Schur update into the next window: Wn[r-B][c-B] = W[r][c] - L21 U12
+        {
+            const int cols = KB - B;                  // = K
+            for (int cb = lane; cb < cols; cb += 64) {
+                const int c = B + cb;
+                T uc[B];
+#pragma unroll
+                for (int t = 0; t < B; ++t) uc[t] = W[t * WP + c];
+                for (int rb = wave; rb < cols; rb += NW) {
+                    const int r = B + rb;
+                    T v = W[r * WP + c];
+#pragma unroll
+                    for (int t = 0; t < B; ++t) v = fma(-W[r * WP + t], uc[t], v);
+                    Wn[rb * WP + cb] = v;
+                }
+            }
+        }
+        // 3b. entering rows/cols of the next window (window rows or columns
+        // >= K), from the stage: global (j1+r, j1+c), m = j1 + max(r, c),
+        // delta = r - c; entering index of m is m - KB = j0 + max(r, c) - K
+        {
+            const T *stg = stage + (((e0) / S) & 1) * stage_sz + S;
+            const int nent = KB * KB - k * k;          // entries with r >= K or c >= K
+            for (int idx = tid; idx < nent; idx += NT) {
+                int r, c;
+                if (idx < B * KB) { r = k + idx / KB; c = idx % KB; }          // bottom B rows
+                else { const int q2 = idx - B * KB; r = q2 / B; c = k + q2 % B; } // right B cols, r < K
+                const int delta = r - c;
+                const int so = (int)((j0 + max(r, c) - k) - (e0 / S) * S);      // in [0, S)
+                const int qrow = min(max(delta + k, -1), W2);
+                Wn[r * WP + c] = stg[qrow * S + so];
+            }
+        }
+        // 3c. outputs of the panel's pivots: L column and U row of j = j0+t
+        for (int idx = tid; idx < nact * CS; idx += NT) {
+            const int t = idx / CS, m = idx - t * CS;
+            const int64_t j = j0 + t;
+            const T piv = W[t * WP + t];
+            const T lv = m == 0 ? T(1) : W[(t + m) * WP + t];
+            const T uv = m == 0 ? T(1) / piv : W[t * WP + t + m];
+            if (!ul) {
+                T *ob = obuf + (int)(j % S) * 2 * CS;
+                ob[m] = lv;
+                ob[CS + m] = uv;
+            } else if (a.corner && j >= nb - k && j + m < nb) {
+                const int64_t b0 = j - (nb - k);
+                T *cn = a.corner + (int64_t)blk * k * k;
+                if (m >= 1) cn[(b0 + m) * k + b0] = lv;
+                cn[b0 * k + b0 + m] = m == 0 ? piv : uv;
+            }
+        }
+        if ((e0 % S) == 0) prefetch(e0 / S + 1);
+        __syncthreads();
+    }
+    flush((nb - 1) / S * S);
+    if (tid == 0 && nboost) atomicAdd(&a.status[0], nboost);
+}
+
+template <typename T, int B, int S, int NT, int RPL>
+static hipError_t launch_lu_blk(const LuArgs<T> &a, hipStream_t s)
+{
+    const int k = a.pt.k, KB = k + B;
+    const size_t lds = (2 * (size_t)KB * (KB + 1) + 2 * (size_t)(2 * k + 3) * S +
+                        (size_t)S * 2 * (k + 1)) * sizeof(T);
+    auto kern = k_banded_lu_blk<T, B, S, NT, RPL>;
+    hipError_t e = hipFuncSetAttribute((const void *)kern,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    dim3 grid(a.with_ul ? 2 * a.pt.p : a.pt.p);
+    hipLaunchKernelGGL(kern, grid, dim3(NT), lds, s, a);
+    return hipGetLastError();
+}
+
+// LDS bytes of the blocked kernel for panel width B and chunk S
+static size_t lu_blk_lds(int k, int B, int S, size_t sz)
+{
+    const size_t KB = (size_t)k + B;
+    return (2 * KB * (KB + 1) + 2 * (size_t)(2 * k + 3) * S + (size_t)S * 2 * (k + 1)) * sz;
+}
+
 template <typename T, int WC, int S, int NT>
 static hipError_t launch_lu_cfg(const LuArgs<T> &a, hipStream_t s)
 {
@@ -308,17 +579,35 @@ template <>
 hipError_t launch_banded_lu<double>(const LuArgs<double> &a, hipStream_t s)
 {
     const int k = a.pt.k;
+    // blocked kernel: panel width B with K + B <= 64 (one panel row per lane)
+    // when possible, else two rows per lane
+    if (k + 16 <= 64) return launch_lu_blk<double, 16, 32, 512, 1>(a, s);
+    if (k + 14 <= 64) return launch_lu_blk<double, 14, 28, 512, 1>(a, s);
+    if (k + 12 <= 64) return launch_lu_blk<double, 12, 24, 512, 1>(a, s);
+    if (k + 8 <= 64) return launch_lu_blk<double, 8, 32, 512, 1>(a, s);
+    // matrix-core kernel where its register window fits without spilling
+    // (K <= 96), the register ring up to K = 127, then the matrix-core kernel
+    // again (its larger windows spill part of the registers)
+    if (k >= 64 && k <= 96) return launch_lu_mfma<double>(a, s);
+    if (k >= 128 && lu_mfma_supported(k, false)) return launch_lu_mfma<double>(a, s);
     if (k < 16) return launch_lu_cfg<double, 16, 16, 256>(a, s);
     if (k < 32) return launch_lu_cfg<double, 32, 32, 256>(a, s);
     if (k < 64) return launch_lu_cfg<double, 64, 32, 256>(a, s);
     if (k < 128) return launch_lu_cfg<double, 128, 16, 1024>(a, s);
-    return hipErrorInvalidValue;   // FP64 window for K >= 128 exceeds the VGPR budget
+    return hipErrorInvalidValue;   // FP64 factors support K <= 208
 }
 
 template <>
 hipError_t launch_banded_lu<float>(const LuArgs<float> &a, hipStream_t s)
 {
     const int k = a.pt.k;
+    // blocked kernel: panel width B with K + B <= 64 (one panel row per lane)
+    // when possible, else two rows per lane
+    if (k + 16 <= 64) return launch_lu_blk<float, 16, 32, 512, 1>(a, s);
+    if (k + 14 <= 64) return launch_lu_blk<float, 14, 28, 512, 1>(a, s);
+    if (k + 12 <= 64) return launch_lu_blk<float, 12, 24, 512, 1>(a, s);
+    if (k + 8 <= 64) return launch_lu_blk<float, 8, 32, 512, 1>(a, s);
+    if (k >= 64 && lu_mfma_supported(k, true)) return launch_lu_mfma<float>(a, s);
     if (k < 16) return launch_lu_cfg<float, 16, 16, 256>(a, s);
     if (k < 32) return launch_lu_cfg<float, 32, 32, 256>(a, s);
     if (k < 64) return launch_lu_cfg<float, 64, 32, 256>(a, s);

@@ -21,28 +21,81 @@
 // Per step: one FMA for x_j in lane u, a v_readlane broadcast (lane index in
 // an SGPR), and one FMA per register in every lane.  Outputs are gathered in a register and
 // written 64 at a time, coalesced.
+//
+// Chunked form (sap_internal.h): the same chain runs over one row chunk per
+// workgroup, so a block's sweep has nch chains in flight instead of one.  The
+// zero-state pass ends by reading the K pending sums out of the register ring
+// (its outgoing state); the last workgroup of each block to finish then chains
+// p_in(c+1) = q(c) + X(c) p_in(c) over the block's chunks.  The from-state pass
+// seeds the ring with -p_in and writes the outputs.
 #include "sap_internal.h"
+#include "dev_common.h"
 
 namespace sap {
 
-__device__ __forceinline__ double lane_bcast(double x, int l)
+
+// Chains the chunk states of block blk (run by the last workgroup of the
+// zero-state pass, 256 threads, K < 64): wave w sums the terms i in
+// [16w, 16w+16) of X(c)^T p for output slot m = lane.
+template <typename T, bool FWD>
+__device__ void chain_states(const SweepArgs<T> &a, int blk, int nchb, T *sh)
 {
-    const int lo = __builtin_amdgcn_readlane(__double2loint(x), l);
-    const int hi = __builtin_amdgcn_readlane(__double2hiint(x), l);
-    return __hiloint2double(hi, lo);
-}
-__device__ __forceinline__ float lane_bcast(float x, int l)
-{
-    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
+    const int k = a.pt.k;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int64_t base = (int64_t)blk * a.nch;
+    T *cur = sh;                 // [64] state entering the current chunk
+    T *part = sh + 64;           // [4][64] partial sums
+    if (nchb < 2) return;                          // one chunk: nothing to chain
+    const int c0 = FWD ? 0 : nchb - 1;            // chunk whose q seeds the chain
+    const int dir = FWD ? 1 : -1;
+    const int nlink = nchb - 2;                    // chunks both receiving and passing on
+    // the state entering chunk c0 + dir is q(c0)
+    if (tid < k) {
+        const T v = a.q[(base + c0) * k + tid];
+        cur[tid] = v;
+        a.st[(base + c0 + dir) * k + tid] = v;
+    }
+    T xr[16], xn[16];
+    auto load_x = [&](int c, T *dst) {
+        const T *x = a.xf + (base + c) * k * k;
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const int i = 16 * wave + e;
+            dst[e] = (i < k && lane < k) ? x[i * k + lane] : T(0);
+        }
+    };
+    if (nlink > 0) load_x(c0 + dir, xr);
+    __syncthreads();
+    for (int l = 0; l < nlink; ++l) {
+        const int c = c0 + dir * (1 + l);           // chunk of this link
+        if (l + 1 < nlink) load_x(c + dir, xn);
+        const T qm = (wave == 0 && lane < k) ? a.q[(base + c) * k + lane] : T(0);
+        T s0 = T(0), s1 = T(0);
+#pragma unroll
+        for (int e = 0; e < 16; e += 2) {
+            s0 = fma(xr[e], cur[16 * wave + e], s0);
+            s1 = fma(xr[e + 1], cur[16 * wave + e + 1], s1);
+        }
+        part[wave * 64 + lane] = s0 + s1;
+        __syncthreads();
+        if (wave == 0) {
+            const T v = qm + ((part[lane] + part[64 + lane]) + (part[128 + lane] + part[192 + lane]));
+            cur[lane] = lane < k ? v : T(0);
+            if (lane < k) a.st[(base + c + dir) * k + lane] = v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < 16; ++e) xr[e] = xn[e];
+    }
 }
 
-template <typename T, int KR, int S, bool FWD, bool DIAG>
+template <typename T, int KR, int S, bool FWD, bool DIAG, int PH>
 __global__ __launch_bounds__(256) void k_sweep(SweepArgs<T> a)
 {
     static_assert(S % 64 == 0, "chunk must hold whole 64-step blocks");
     static_assert(KR >= 2, "ring must cover 64 + K slots");
     // LDS row pitch: slots 0..K hold a coefficient row, slots K+1..PITCH-1
-    // are zero (the last 8 always), so a clamped offset needs no mask
+    // are zero (at least 8 of them), so a clamped offset needs no mask
     constexpr int PITCH = 64 * (KR - 1) + 8;
 
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -51,50 +104,72 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs<T> a)
 
     const int k = a.pt.k;
     const int CS = k + 1;
-    const int blk = blockIdx.x;
+    const int blk = PH == SWEEP_WHOLE ? (int)blockIdx.x : (int)(blockIdx.x % a.pt.p);
+    const int ch = PH == SWEEP_WHOLE ? 0 : (int)(blockIdx.x / a.pt.p);
     const int64_t s0 = a.pt.starts[blk];
     const int64_t nb = a.pt.starts[blk + 1] - s0;
     const int tid = threadIdx.x;
     const int wave = tid >> 6;
     const int lane = tid & 63;
-    const int64_t nchunks = (nb + S - 1) / S;
+    // rows [r0, r1) of the block handled here
+    const int nchb = PH == SWEEP_WHOLE ? 1 : (int)((nb + a.clen - 1) / a.clen);
+    const int64_t r0 = PH == SWEEP_WHOLE ? 0 : min((int64_t)ch * a.clen, nb);
+    const int64_t r1 = PH == SWEEP_WHOLE ? nb : min(r0 + a.clen, nb);
+    const int64_t nst = r1 - r0;
+    // a chunk hands a state on if a chunk follows it in the sweep direction
+    const bool passes = ch < nchb && (FWD ? ch + 1 < nchb : ch > 0);
+    const bool receives = ch < nchb && (FWD ? ch > 0 : ch + 1 < nchb);
+    if (PH == SWEEP_FROM_STATE && ch >= nchb) return;      // empty chunk
+    // the zero-state pass has nothing to run for the last chunk of a sweep,
+    // but its workgroup still takes part in the block's ticket
+    const int64_t nchunks = (PH == SWEEP_ZERO_STATE && !passes) ? 0 : (nst + S - 1) / S;
     const T *dtop = (a.dtop && blk > 0) ? a.dtop + (int64_t)blk * k : nullptr;
     const T *dbot = (a.dbot && blk < a.pt.p - 1) ? a.dbot + (int64_t)blk * k : nullptr;
 
-    for (int idx = tid; idx < 2 * S * 8; idx += 256)
-        cst[(idx >> 3) * PITCH + 64 * (KR - 1) + (idx & 7)] = T(0);
+    // slots K+1 .. PITCH-1 of every staged row stay zero: the copies below
+    // write slots 0..K only
+    for (int idx = tid; idx < 2 * S * (PITCH - CS); idx += 256) {
+        const int row = idx / (PITCH - CS), m = CS + idx % (PITCH - CS);
+        cst[row * PITCH + m] = T(0);
+    }
 
     // row of the block handled at step t
-    auto row_of = [&](int64_t t) -> int64_t { return FWD ? t : nb - 1 - t; };
+    auto row_of = [&](int64_t t) -> int64_t { return FWD ? r0 + t : r1 - 1 - t; };
 
     if (wave != 0) {
         // ------------------------------------------------------ loaders
-        // loader wave lw (0..2) stages chunk rows lw, lw+3, ...; lane l loads
-        // coefficient slots l, l+64, ... of each row, and the input values of
-        // the chunk are spread over all loader threads
-        const int lw = wave - 1;
+        // loader wave lw (0..2) copies chunk rows lw, lw+3, ... from HBM
+        // straight into LDS (global_load_lds: lane l moves dword l + 64x of
+        // the row, lanes past the row end are masked off), and the input
+        // values of the chunk are spread over all loader threads
+        const int lw = __builtin_amdgcn_readfirstlane(wave - 1);
         constexpr int RPW = (S + 2) / 3;              // rows per loader wave
-        constexpr int NSEG = KR - 1;                  // 64-slot segments per row
-        T pre[RPW * NSEG];
+        const int ndw = CS * (int)(sizeof(T) / 4);    // dwords per row
         T vin = T(0);
-        auto load = [&](int64_t t) {
-#pragma unroll
+        auto copy_rows = [&](int64_t t) {
+            T *c = cst + (t & 1) * S * PITCH;
             for (int y = 0; y < RPW; ++y) {
                 const int rr = lw + 3 * y;                    // row inside the chunk
                 const int64_t st = t * S + rr;
-                const bool ok = rr < S && st < nb;
-                const T *src = a.F + (s0 + (ok ? row_of(st) : 0)) * CS;
-#pragma unroll
-                for (int x = 0; x < NSEG; ++x) {
-                    const int m = lane + 64 * x;
-                    pre[y * NSEG + x] = (ok && m < CS) ? src[m] : T(0);
+                if (rr >= S || st >= nst) break;
+                const unsigned *src =
+                    reinterpret_cast<const unsigned *>(a.F + (s0 + row_of(st)) * CS);
+                for (int x = 0; 64 * x < ndw; ++x) {
+                    const int dw = lane + 64 * x;
+                    if (dw < ndw)
+                        __builtin_amdgcn_global_load_lds(
+                            (const void *)(src + dw),
+                            (__attribute__((address_space(3))) void *)(c + rr * PITCH + (64 * x * 4) / (int)sizeof(T)),
+                            4, 0, 0);
                 }
             }
+        };
+        auto load_in = [&](int64_t t) {
             const int f = tid - 64;
             vin = T(0);
             if (f < S) {
                 const int64_t st = t * S + f;
-                if (st < nb) {
+                if (st < nst) {
                     const int64_t r = row_of(st);
                     if (a.xin) {
                         double x = a.xin[s0 + r];
@@ -110,116 +185,152 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs<T> a)
                 }
             }
         };
-        auto commit = [&](int64_t t) {
-            T *c = cst + (t & 1) * S * PITCH;
-#pragma unroll
-            for (int y = 0; y < RPW; ++y) {
-                const int rr = lw + 3 * y;
-                if (rr < S) {
-#pragma unroll
-                    for (int x = 0; x < NSEG; ++x) c[rr * PITCH + lane + 64 * x] = pre[y * NSEG + x];
-                }
-            }
+        auto commit_in = [&](int64_t t) {
             const int f = tid - 64;
             if (f < S) vst[(t & 1) * S + f] = vin;
         };
-        load(0);
-        commit(0);
-        load(1);
+        copy_rows(0);
+        load_in(0);
+        __builtin_amdgcn_s_waitcnt(0);
+        commit_in(0);
+        copy_rows(1);
+        load_in(1);
         __syncthreads();
         for (int64_t t = 0; t < nchunks; ++t) {
-            commit(t + 1);
+            __builtin_amdgcn_s_waitcnt(0);            // copies of chunk t+1 landed
+            commit_in(t + 1);
             __syncthreads();
-            load(t + 2);
+            copy_rows(t + 2);
+            load_in(t + 2);
         }
-        return;
-    }
-
-    // ------------------------------------------------------- compute wave
-    // Steps run in groups of G; the LDS operands of group g+1 (diagonal
-    // factor, input, and the KR coefficients each lane pushes) are read while
-    // the dependent chain of group g runs.
-    constexpr int G = 8;
-    struct Grp {
-        T d[G], vd[G], cf[G][KR];
-    };
-    __syncthreads();
-    T acc[KR];
+    } else {
+        // ------------------------------------------------------- compute wave
+        // Steps run in groups of G; the LDS operands of group g+1 (diagonal
+        // factor, input, and the KR coefficients each lane pushes) are read while
+        // the dependent chain of group g runs.
+        constexpr int G = 4;
+        struct Grp {
+            T d[G], vd[G], cf[G][KR];
+        };
+        __syncthreads();
+        T acc[KR];
 #pragma unroll
-    for (int s = 0; s < KR; ++s) acc[s] = T(0);
+        for (int s = 0; s < KR; ++s) {
+            // a chunk that receives a state starts from acc = -p_in
+            const int m = 64 * s + lane;
+            acc[s] = (PH == SWEEP_FROM_STATE && receives && m < k)
+                         ? -a.st[((int64_t)blk * a.nch + ch) * k + m] : T(0);
+        }
 
-    for (int64_t t = 0; t < nchunks; ++t) {
-        const T *c = cst + (t & 1) * S * PITCH;
-        const T *vv = vst + (t & 1) * S;
-        for (int g = 0; g < S / 64; ++g) {
-            const int64_t jb = t * S + 64 * g;        // first step of this 64-block
-            if (jb >= nb) break;
-            const int ulim = (int)min((int64_t)64, nb - jb);
-            auto load = [&](int u0, Grp &q) {
+        for (int64_t t = 0; t < nchunks; ++t) {
+            const T *c = cst + (t & 1) * S * PITCH;
+            const T *vv = vst + (t & 1) * S;
+            for (int g = 0; g < S / 64; ++g) {
+                const int64_t jb = t * S + 64 * g;        // first step of this 64-block
+                if (jb >= nst) break;
+                const int ulim = (int)min((int64_t)64, nst - jb);
+                auto load = [&](int u0, Grp &q) {
 #pragma unroll
-                for (int e = 0; e < G; ++e) {
-                    const int u = min(u0 + e, 63);
-                    const T *crow = c + (64 * g + u) * PITCH;
-                    q.d[e] = DIAG ? crow[0] : T(1);
-                    q.vd[e] = vv[64 * g + u] * q.d[e];
+                    for (int e = 0; e < G; ++e) {
+                        const int u = min(u0 + e, 63);
+                        const T *crow = c + (64 * g + u) * PITCH;
+                        q.d[e] = DIAG ? crow[0] : T(1);
+                        q.vd[e] = vv[64 * g + u] * q.d[e];
+#pragma unroll
+                        for (int s = 0; s < KR; ++s) {
+                            // step offset of slot (s, lane).  Offsets > K read a
+                            // zero slot; offsets <= 0 occur only for s = 0 in lanes
+                            // whose step is already done, where the value is unused.
+                            const int m = 64 * s + lane - u;
+                            q.cf[e][s] = crow[min(max(m, 0), PITCH - 1)];
+                        }
+                    }
+                };
+                T ov = T(0);
+                auto run = [&](int u0, const Grp &q) {
+#pragma unroll
+                    for (int e = 0; e < G; ++e) {
+                        const int u = u0 + e;
+                        if (u < ulim) {
+                            const T x = fma(acc[0], q.d[e], q.vd[e]);   // acc = -pending
+                            const T xb = lane_bcast(x, u);
+#pragma unroll
+                            for (int s = 0; s < KR; ++s) acc[s] = fma(-q.cf[e][s], xb, acc[s]);
+                            ov = lane == u ? xb : ov;
+                        }
+                    }
+                };
+                Grp ga, gb;
+                load(0, ga);
+                for (int u0 = 0; u0 < ulim; u0 += 2 * G) {
+                    load(u0 + G, gb);
+                    run(u0, ga);
+                    load(u0 + 2 * G, ga);
+                    run(u0 + G, gb);
+                }
+                const int64_t st = jb + lane;
+                if (PH != SWEEP_ZERO_STATE && st < nst) {
+                    const int64_t r = s0 + row_of(st);
+                    if (a.dout) a.dout[r] = (double)ov;
+                    else a.tout[r] = ov;
+                }
+                if (PH == SWEEP_ZERO_STATE && jb + ulim == nst) {
+                    // outgoing state: pending sums of the K steps after the
+                    // chunk, slots ulim .. ulim+K-1 of the ring before it shifts
 #pragma unroll
                     for (int s = 0; s < KR; ++s) {
-                        // step offset of slot (s, lane).  Offsets > K read a
-                        // zero slot; offsets <= 0 occur only for s = 0 in lanes
-                        // whose step is already done, where the value is unused.
-                        const int m = 64 * s + lane - u;
-                        q.cf[e][s] = crow[min(max(m, 0), PITCH - 1)];
+                        const int m = 64 * s + lane - ulim;
+                        if (m >= 0 && m < k) a.q[((int64_t)blk * a.nch + ch) * k + m] = -acc[s];
                     }
                 }
-            };
-            T ov = T(0);
-            auto run = [&](int u0, const Grp &q) {
 #pragma unroll
-                for (int e = 0; e < G; ++e) {
-                    const int u = u0 + e;
-                    if (u < ulim) {
-                        const T x = fma(acc[0], q.d[e], q.vd[e]);   // acc = -pending
-                        const T xb = lane_bcast(x, u);
-#pragma unroll
-                        for (int s = 0; s < KR; ++s) acc[s] = fma(-q.cf[e][s], xb, acc[s]);
-                        ov = lane == u ? xb : ov;
-                    }
-                }
-            };
-            Grp ga, gb;
-            load(0, ga);
-            for (int u0 = 0; u0 < ulim; u0 += 2 * G) {
-                load(u0 + G, gb);
-                run(u0, ga);
-                load(u0 + 2 * G, ga);
-                run(u0 + G, gb);
+                for (int s = 0; s < KR - 1; ++s) acc[s] = acc[s + 1];
+                acc[KR - 1] = T(0);
             }
-            const int64_t st = jb + lane;
-            if (st < nb) {
-                const int64_t r = s0 + row_of(st);
-                if (a.dout) a.dout[r] = (double)ov;
-                else a.tout[r] = ov;
-            }
-#pragma unroll
-            for (int s = 0; s < KR - 1; ++s) acc[s] = acc[s + 1];
-            acc[KR - 1] = T(0);
+            __syncthreads();
         }
-        __syncthreads();
     }
+    if (PH != SWEEP_ZERO_STATE) return;
+    // ------------------------------------------- ticket: last one chains
+    __shared__ int last_sh;
+    __syncthreads();
+    if (tid == 0) {
+        __threadfence();                        // publish this chunk's q
+        const unsigned old = atomicAdd(a.ticket + blk, 1u);
+        last_sh = old == (unsigned)(a.nch - 1);
+    }
+    __syncthreads();
+    if (!last_sh) return;
+    __threadfence();                            // see every chunk's q
+    chain_states<T, FWD>(a, blk, nchb, cst);
+    if (tid == 0) a.ticket[blk] = 0u;           // ready for the next sweep
+}
+
+template <typename T, int KR, int S, bool FWD, bool DIAG, int PH>
+static hipError_t launch_sweep_ph(const SweepArgs<T> &a, hipStream_t s)
+{
+    const size_t lds = (2 * (size_t)S * (64 * (KR - 1) + 8) + 2 * S) * sizeof(T);
+    auto kern = k_sweep<T, KR, S, FWD, DIAG, PH>;
+    hipError_t e = hipFuncSetAttribute((const void *)kern,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    const unsigned grid = PH == SWEEP_WHOLE ? a.pt.p : a.pt.p * a.nch;
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(256), lds, s, a);
+    return hipGetLastError();
 }
 
 template <typename T, int KR, int S, bool FWD, bool DIAG>
 static hipError_t launch_sweep_cfg(const SweepArgs<T> &a, hipStream_t s)
 {
-    const size_t lds = (2 * (size_t)S * (64 * (KR - 1) + 8) + 2 * S) * sizeof(T);
-    auto kern = k_sweep<T, KR, S, FWD, DIAG>;
-    hipError_t e = hipFuncSetAttribute((const void *)kern,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, dim3(a.pt.p), dim3(256), lds, s, a);
-    return hipGetLastError();
+    if constexpr (KR == 2) {                   // chained states need K < 64
+        if (a.phase == SWEEP_ZERO_STATE)
+            return launch_sweep_ph<T, KR, S, FWD, DIAG, SWEEP_ZERO_STATE>(a, s);
+        if (a.phase == SWEEP_FROM_STATE)
+            return launch_sweep_ph<T, KR, S, FWD, DIAG, SWEEP_FROM_STATE>(a, s);
+    }
+    if (a.phase != SWEEP_WHOLE) return hipErrorInvalidValue;
+    return launch_sweep_ph<T, KR, S, FWD, DIAG, SWEEP_WHOLE>(a, s);
 }
-
 // chunks of 64 steps: two LDS buffers of 64 rows of pitch 64*(KR-1)
 template <typename T, int KR>
 static hipError_t launch_sweep_kr(const SweepArgs<T> &a, hipStream_t s)
@@ -248,7 +359,98 @@ hipError_t launch_sweep<double>(const SweepArgs<double> &a, hipStream_t s)
     const int k = a.pt.k;
     if (k < 64) return launch_sweep_kr<double, 2>(a, s);
     if (k < 128) return launch_sweep_kr<double, 3>(a, s);
-    return hipErrorInvalidValue;               // FP64 factors support K <= 127
+    if (k < 192) return launch_sweep_kr<double, 4>(a, s);
+    return launch_sweep_kr<double, 5>(a, s);
 }
+
+// ------------------------------------------------------ transfer matrices
+// One wave per chunk that hands a state on.  Lane i runs the chunk's chain
+// with zero inputs from the incoming state e_i (pending sum 1 for the i-th
+// step of the chunk); its K pending sums after the last step form row i of
+// X(c).  p[m] holds the pending sum of the m-th step after the current one,
+// so one step is x = -p[0]*d, p[m-1] = p[m] + F[j][m]*x.  Coefficient rows
+// are loaded one per lane (coefficient m in lane m), eight rows ahead, and
+// broadcast with v_readlane.
+template <typename T, int KM, bool FWD, bool DIAG>
+__global__ __launch_bounds__(64) void k_sweep_xfer(XferArgs<T> a)
+{
+    static_assert(KM <= 64, "coefficients are spread one per lane");
+    const int k = a.pt.k;
+    const int CS = k + 1;
+    const int blk = (int)(blockIdx.x % a.pt.p), ch = (int)(blockIdx.x / a.pt.p);
+    const int64_t s0 = a.pt.starts[blk];
+    const int64_t nb = a.pt.starts[blk + 1] - s0;
+    const int nchb = (int)((nb + a.clen - 1) / a.clen);
+    if (!(ch < nchb && (FWD ? ch + 1 < nchb : ch > 0))) return;
+    const int64_t r0 = (int64_t)ch * a.clen, r1 = min(r0 + a.clen, nb);
+    const int64_t nst = r1 - r0;
+    const int lane = threadIdx.x;
+    T p[KM];
+#pragma unroll
+    for (int m = 0; m < KM; ++m) p[m] = (m == lane) ? T(1) : T(0);
+    constexpr int D = 8;
+    T fr[D], fn[D];
+    auto load = [&](int64_t t0, T *dst) {
+#pragma unroll
+        for (int e = 0; e < D; ++e) {
+            const int64_t t = t0 + e;
+            const int64_t row = FWD ? r0 + t : r1 - 1 - t;
+            dst[e] = (t < nst && lane <= k) ? a.F[(s0 + row) * CS + lane] : T(0);
+        }
+    };
+    load(0, fr);
+    for (int64_t t0 = 0; t0 < nst; t0 += D) {
+        load(t0 + D, fn);
+#pragma unroll
+        for (int e = 0; e < D; ++e) {
+            if (t0 + e < nst) {
+                const T d = DIAG ? lane_bcast(fr[e], 0) : T(1);
+                const T x = -p[0] * d;
+#pragma unroll
+                for (int m = 1; m < KM; ++m) p[m - 1] = fma(lane_bcast(fr[e], m), x, p[m]);
+                p[KM - 1] = T(0);
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < D; ++e) fr[e] = fn[e];
+    }
+    if (lane < k) {
+        T *out = a.xf + (((int64_t)blk * a.nch + ch) * k + lane) * k;
+#pragma unroll
+        for (int m = 0; m < KM; ++m)
+            if (m < k) out[m] = p[m];
+    }
+}
+
+template <typename T, int KM>
+static hipError_t launch_xfer_km(const XferArgs<T> &a, hipStream_t s)
+{
+    const dim3 grid(a.pt.p * a.nch), blk(64);
+    if (a.fwd) {
+        if (a.diag) hipLaunchKernelGGL((k_sweep_xfer<T, KM, true, true>), grid, blk, 0, s, a);
+        else hipLaunchKernelGGL((k_sweep_xfer<T, KM, true, false>), grid, blk, 0, s, a);
+    } else {
+        if (a.diag) hipLaunchKernelGGL((k_sweep_xfer<T, KM, false, true>), grid, blk, 0, s, a);
+        else hipLaunchKernelGGL((k_sweep_xfer<T, KM, false, false>), grid, blk, 0, s, a);
+    }
+    return hipGetLastError();
+}
+
+bool sweep_chunking_supported(int k, bool) { return k >= 1 && k < 64; }
+
+template <typename T>
+hipError_t launch_sweep_xfer(const XferArgs<T> &a, hipStream_t s)
+{
+    const int k = a.pt.k;
+    if (!sweep_chunking_supported(k, sizeof(T) == 4) || a.nch < 2) return hipErrorInvalidValue;
+    // KM >= K + 1 slots: the K pending sums plus the zero that enters
+    if (k < 16) return launch_xfer_km<T, 16>(a, s);
+    if (k < 32) return launch_xfer_km<T, 32>(a, s);
+    if (k < 48) return launch_xfer_km<T, 48>(a, s);
+    return launch_xfer_km<T, 64>(a, s);
+}
+
+template hipError_t launch_sweep_xfer<float>(const XferArgs<float> &, hipStream_t);
+template hipError_t launch_sweep_xfer<double>(const XferArgs<double> &, hipStream_t);
 
 }  // namespace sap

@@ -15,10 +15,9 @@
 // each preconditioner application only needs small matrix-vector products.
 //
 // One 256-thread workgroup per interface; thread b owns column b of every
-// K x K right-hand side (K <= 255).  The two K x K working matrices live in
-// LDS when they fit (2 K^2 elements <= 96 KB), else in global memory; the
-// factor corners are read from global memory (L1/L2 resident).  This step is
-// O(P K^3) and runs once per factorization.
+// K x K right-hand side (K <= 255).  The working matrices and the staged
+// factor corner live in LDS when they fit (3 K^2 elements <= 128 KB), else in
+// global memory.  This step is O(P K^3) and runs once per factorization.
 #include "sap_internal.h"
 
 namespace sap {
@@ -32,9 +31,27 @@ __device__ __forceinline__ void block_sync()
     __syncthreads();
 }
 
-// X and Y are the two K x K working matrices (row-major, thread b owns
-// column b): in LDS when 2*K*K elements fit, else in the Rlu / Rinv slots of
-// global memory.
+// dot of row r of M (entries c in [c0, c1)) with column b of X, both row-major
+// K x K in the same memory space; four partial sums shorten the FMA chain
+template <typename T>
+__device__ __forceinline__ T rowdot(const T *M, const T *X, int k, int r, int b, int c0, int c1)
+{
+    T s0 = T(0), s1 = T(0), s2 = T(0), s3 = T(0);
+    int c = c0;
+    for (; c + 3 < c1; c += 4) {
+        s0 = fma(M[r * k + c], X[c * k + b], s0);
+        s1 = fma(M[r * k + c + 1], X[(c + 1) * k + b], s1);
+        s2 = fma(M[r * k + c + 2], X[(c + 2) * k + b], s2);
+        s3 = fma(M[r * k + c + 3], X[(c + 3) * k + b], s3);
+    }
+    for (; c < c1; ++c) s0 = fma(M[r * k + c], X[c * k + b], s0);
+    return (s0 + s1) + (s2 + s3);
+}
+
+// X, Y (right-hand-side columns, thread b owns column b) and F (the staged
+// K x K factor corner, later Rbar and its LU) are row-major K x K working
+// matrices: in LDS when 3*K*K elements fit, else in global memory (the V, W
+// and Rlu slots; the Rinv columns are then solved in place in Rinv).
 template <typename T, bool LDS>
 __global__ __launch_bounds__(256) void k_tips(TipsArgs<T> a)
 {
@@ -47,124 +64,130 @@ __global__ __launch_bounds__(256) void k_tips(TipsArgs<T> a)
     const int64_t kk = (int64_t)k * k;
     T *B = a.B + i * kk, *C = a.C + i * kk, *V = a.V + i * kk, *W = a.W + i * kk;
     T *R = a.Rbar + i * kk, *RI = a.Rinv + i * kk;
-    T *X = LDS ? reinterpret_cast<T *>(smem_raw) : a.Rlu + i * kk;
-    T *Y = LDS ? reinterpret_cast<T *>(smem_raw) + kk : RI;
+    T *X = LDS ? reinterpret_cast<T *>(smem_raw) : V;
+    T *Y = LDS ? reinterpret_cast<T *>(smem_raw) + kk : W;
+    T *F = LDS ? reinterpret_cast<T *>(smem_raw) + 2 * kk : a.Rlu + i * kk;
+    T *Z = LDS ? Y : RI;                        // Rinv working columns
     int *piv = a.piv + (int64_t)i * k;
     const T *cn = a.corner + (int64_t)(i + 1) * kk;   // UL corner of block i+1
     const int tid = threadIdx.x;
+    const int64_t base = s1 - k;                // first row of block i's bottom corner
     __shared__ int pr_sh;
+    __shared__ int piv_sh[kMaxK];
+    __shared__ T zero_sh;
 
-    // B_i (lower triangular incl. diagonal) and C_{i+1} (upper triangular)
+    // B_i (lower triangular incl. diagonal) -> X, C_{i+1} (upper triangular)
+    // -> Y, and the bottom-right corner of LU(A_i) -> F, with
+    // F[r][c] = l(base+r, base+c) for r > c (unit diagonal implied) and
+    // F[r][c] = u(base+r, base+c) for r <= c; the stored diagonal of U is
+    // its reciprocal.
     for (int64_t e = tid; e < kk; e += 256) {
         const int r = (int)(e / k), c = (int)(e % k);
         const int64_t br = s1 - k + r, bc = s1 + c;          // B: a[br][bc]
-        B[e] = (c <= r) ? (T)a.band[(int64_t)(k + br - bc) * n + bc] : T(0);
+        const T bv = (c <= r) ? (T)a.band[(int64_t)(k + br - bc) * n + bc] : T(0);
         const int64_t cr = s1 + r, cc = s1 - k + c;          // C: a[cr][cc]
-        C[e] = (r <= c) ? (T)a.band[(int64_t)(k + cr - cc) * n + cc] : T(0);
+        const T cv = (r <= c) ? (T)a.band[(int64_t)(k + cr - cc) * n + cc] : T(0);
+        B[e] = bv;
+        C[e] = cv;
+        X[e] = bv;
+        Y[e] = cv;
+        F[e] = (r > c) ? a.Lc[(base + c) * CS + (r - c)]
+                       : a.Uc[(base + c) * CS + (c - r)];    // c == r: 1/u_rr
     }
+    if (tid == 0) zero_sh = T(0);
     block_sync<LDS>();
 
-    const int64_t base = s1 - k;                // first row of block i's bottom corner
     const int b = tid;
     if (b < k) {
-        // V = U_bb^{-1} (L_bb^{-1} B) on column b, working column in X.
-        // L_bb[r][c] = l(base+r, base+c) = Lc[(base+c)*CS + (r-c)], r > c.
-        for (int r = 0; r < k; ++r) {
-            T s = B[r * k + b];
-            for (int c = 0; c < r; ++c) s = fma(-a.Lc[(base + c) * CS + (r - c)], X[c * k + b], s);
-            X[r * k + b] = s;
-        }
-        // U_bb[r][c] = u(base+r, base+c) = Uc[(base+c)*CS + (c-r)], c > r;
-        // 1/u(base+r, base+r) = Uc[(base+r)*CS].
-        for (int r = k - 1; r >= 0; --r) {
-            T s = X[r * k + b];
-            for (int c = r + 1; c < k; ++c) s = fma(-a.Uc[(base + c) * CS + (c - r)], X[c * k + b], s);
-            X[r * k + b] = s * a.Uc[(base + r) * CS];
-        }
-        for (int r = 0; r < k; ++r) V[r * k + b] = X[r * k + b];
-        // W = L'_tt^{-1} (U'_tt^{-1} C) on column b, working column in Y.
-        // With the corner cn of LU(J A J): U'_tt[r][c] = cn[(k-1-r)*k + (k-1-c)]
-        // for r < c (unit diagonal), L'_tt[r][c] = cn[(k-1-r)*k + (k-1-c)], r >= c.
-        for (int r = k - 1; r >= 0; --r) {
-            T s = C[r * k + b];
-            for (int c = r + 1; c < k; ++c)
-                s = fma(-cn[(k - 1 - r) * k + (k - 1 - c)], Y[c * k + b], s);
-            Y[r * k + b] = s;
-        }
-        for (int r = 0; r < k; ++r) {
-            T s = Y[r * k + b];
-            for (int c = 0; c < r; ++c)
-                s = fma(-cn[(k - 1 - r) * k + (k - 1 - c)], Y[c * k + b], s);
-            Y[r * k + b] = s / cn[(k - 1 - r) * k + (k - 1 - r)];
-        }
-        for (int r = 0; r < k; ++r) W[r * k + b] = Y[r * k + b];
+        // V = U_bb^{-1} (L_bb^{-1} B_i), column b, in X
+        for (int r = 1; r < k; ++r) X[r * k + b] -= rowdot(F, X, k, r, b, 0, r);
+        for (int r = k - 1; r >= 0; --r)
+            X[r * k + b] = (X[r * k + b] - rowdot(F, X, k, r, b, r + 1, k)) * F[r * k + r];
     }
     block_sync<LDS>();
-    // Rbar = I - W V (column b), from the working copies; Rbar kept in X
+    // corner of LU(J A_{i+1} J) -> F reversed: F[r][c] = cn[(k-1-r)*k + (k-1-c)],
+    // i.e. U'_tt (unit upper) above the diagonal and L'_tt on and below it
+    for (int64_t e = tid; e < kk; e += 256) {
+        const int r = (int)(e / k), c = (int)(e % k);
+        F[e] = cn[(int64_t)(k - 1 - r) * k + (k - 1 - c)];
+        V[e] = X[e];
+    }
+    block_sync<LDS>();
+    if (b < k) {
+        // W = L'_tt^{-1} (U'_tt^{-1} C_{i+1}), column b, in Y
+        for (int r = k - 2; r >= 0; --r) Y[r * k + b] -= rowdot(F, Y, k, r, b, r + 1, k);
+        for (int r = 0; r < k; ++r)
+            Y[r * k + b] = (Y[r * k + b] - rowdot(F, Y, k, r, b, 0, r)) / F[r * k + r];
+    }
+    block_sync<LDS>();
+    // Rbar = I - W V -> F and R (global)
+    for (int64_t e = tid; e < kk; e += 256) W[e] = Y[e];
     if (b < k) {
         for (int r = 0; r < k; ++r) {
-            T s = (r == b) ? T(1) : T(0);
-            for (int c = 0; c < k; ++c) s = fma(-Y[r * k + c], X[c * k + b], s);
+            const T s = ((r == b) ? T(1) : T(0)) - rowdot(Y, X, k, r, b, 0, k);
             R[r * k + b] = s;
+            F[r * k + b] = s;
         }
     }
     block_sync<LDS>();
-    for (int64_t e = tid; e < kk; e += 256) X[e] = R[e];
-    block_sync<LDS>();
-    // LU with partial pivoting of Rbar in X, ties to the lowest row
+    // LU with partial pivoting of Rbar in F (ties to the lowest row); the
+    // pivot search is a wave-0 argmax
     for (int j = 0; j < k; ++j) {
-        if (tid == 0) {
+        if (tid < 64) {
+            T best = T(-1);
             int p = j;
-            T best = fabs(X[j * k + j]);
-            for (int r = j + 1; r < k; ++r) {
-                const T v = fabs(X[r * k + j]);
+            for (int r = j + tid; r < k; r += 64) {
+                const T v = fabs(F[r * k + j]);
                 if (v > best) { best = v; p = r; }
             }
-            piv[j] = p;
-            pr_sh = p;
-            if (best == T(0)) a.status[1] = 2;
+            for (int o = 32; o > 0; o >>= 1) {
+                const T ob = __shfl_xor(best, o, 64);
+                const int op = __shfl_xor(p, o, 64);
+                if (ob > best || (ob == best && op < p)) { best = ob; p = op; }
+            }
+            if (tid == 0) {
+                piv[j] = p;
+                piv_sh[j] = p;
+                pr_sh = p;
+                if (best == T(0)) a.status[1] = 2;
+            }
         }
         block_sync<LDS>();
         const int p = pr_sh;
         if (p != j)
             for (int c = tid; c < k; c += 256) {
-                const T t = X[j * k + c];
-                X[j * k + c] = X[p * k + c];
-                X[p * k + c] = t;
+                const T t = F[j * k + c];
+                F[j * k + c] = F[p * k + c];
+                F[p * k + c] = t;
             }
         block_sync<LDS>();
-        const T d = X[j * k + j];
-        for (int r = j + 1 + tid; r < k; r += 256) X[r * k + j] = X[r * k + j] / d;
-        block_sync<LDS>();
-        for (int c = j + 1 + tid; c < k; c += 256) {
-            const T ujc = X[j * k + c];
-            for (int r = j + 1; r < k; ++r) X[r * k + c] = fma(-X[r * k + j], ujc, X[r * k + c]);
+        const T d = F[j * k + j];
+        const T dinv = d != T(0) ? T(1) / d : zero_sh;
+        const int m = k - 1 - j;                               // trailing size
+        for (int e = tid; e < m * m; e += 256) {
+            const int r = j + 1 + e / m, c = j + 1 + e % m;
+            F[r * k + c] = fma(-F[r * k + j] * dinv, F[j * k + c], F[r * k + c]);
         }
+        block_sync<LDS>();
+        for (int r = j + 1 + tid; r < k; r += 256) F[r * k + j] *= dinv;
         block_sync<LDS>();
     }
-    // Rinv = Rbar^{-1}: column b solves Rbar y = e_b with the pivoted LU (in Y)
+    // Rinv = Rbar^{-1}: column b solves Rbar y = e_b with the pivoted LU (in Z)
     if (b < k) {
-        for (int r = 0; r < k; ++r) Y[r * k + b] = (r == b) ? T(1) : T(0);
+        for (int r = 0; r < k; ++r) Z[r * k + b] = (r == b) ? T(1) : T(0);
         for (int j = 0; j < k; ++j) {                  // apply interchanges
-            const int p = piv[j];
+            const int p = piv_sh[j];
             if (p != j) {
-                const T t = Y[j * k + b];
-                Y[j * k + b] = Y[p * k + b];
-                Y[p * k + b] = t;
+                const T t = Z[j * k + b];
+                Z[j * k + b] = Z[p * k + b];
+                Z[p * k + b] = t;
             }
         }
-        for (int r = 0; r < k; ++r) {                  // unit lower
-            T s = Y[r * k + b];
-            for (int c = 0; c < r; ++c) s = fma(-X[r * k + c], Y[c * k + b], s);
-            Y[r * k + b] = s;
-        }
-        for (int r = k - 1; r >= 0; --r) {            // upper
-            T s = Y[r * k + b];
-            for (int c = r + 1; c < k; ++c) s = fma(-X[r * k + c], Y[c * k + b], s);
-            Y[r * k + b] = s / X[r * k + r];
-        }
+        for (int r = 1; r < k; ++r) Z[r * k + b] -= rowdot(F, Z, k, r, b, 0, r);
+        for (int r = k - 1; r >= 0; --r)
+            Z[r * k + b] = (Z[r * k + b] - rowdot(F, Z, k, r, b, r + 1, k)) / F[r * k + r];
         if (LDS)
-            for (int r = 0; r < k; ++r) RI[r * k + b] = Y[r * k + b];
+            for (int r = 0; r < k; ++r) RI[r * k + b] = Z[r * k + b];
     }
 }
 
@@ -172,8 +195,8 @@ template <typename T>
 hipError_t launch_tips(const TipsArgs<T> &a, hipStream_t s)
 {
     if (a.pt.p < 2) return hipSuccess;
-    const size_t lds = 2 * (size_t)a.pt.k * a.pt.k * sizeof(T);
-    if (lds <= 96 * 1024) {
+    const size_t lds = 3 * (size_t)a.pt.k * a.pt.k * sizeof(T);
+    if (lds <= 128 * 1024) {
         auto kern = k_tips<T, true>;
         hipError_t e = hipFuncSetAttribute((const void *)kern,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

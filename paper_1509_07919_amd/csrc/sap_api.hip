@@ -35,10 +35,34 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
     size_t starts, partial, status, Lc, Uc, Lr, Ur, corner, B, C, V, W, Rbar, Rlu, Rinv, piv,
-        gT, yT, dtop, dbot, kv, dpart, counter, sc, total;
+        gT, yT, dtop, dbot, kv, dpart, counter, sc, xLc, xUc, xLr, xUr, sq, sst, ticket, total;
 };
 
 bool coupled_active(const sap_options &o) { return o.mode == SAP_COUPLED && o.p > 1 && o.k > 0; }
+
+// Chains per block for the triangular sweeps (chunked form, sap_internal.h).
+// Automatic choice: about as many sweep workgroups as the chip keeps resident
+// (the LDS staging of one workgroup allows two per CU for FP64 factors, four
+// for FP32, on 256 CUs), with at least 64 rows per chunk.
+struct Chunking {
+    int nch, clen;
+};
+Chunking chunking_for(const sap_options &o)
+{
+    const int64_t maxnb = o.n / o.p + (o.n % o.p ? 1 : 0);
+    const bool fp32 = o.factor_prec == SAP_PREC_FP32;
+    Chunking c{1, (int)maxnb};
+    if (o.sweep_chunks == 1 || !sweep_chunking_supported(o.k, fp32)) return c;
+    int64_t want = o.sweep_chunks >= 2 ? o.sweep_chunks : (fp32 ? 1024 : 512) / o.p;
+    if (want < 2) return c;
+    int64_t clen = (maxnb + want - 1) / want;
+    if (clen < 64) clen = 64;
+    const int64_t nch = (maxnb + clen - 1) / clen;
+    if (nch < 2) return c;
+    c.nch = (int)nch;
+    c.clen = (int)clen;
+    return c;
+}
 
 int validate(const sap_options *o)
 {
@@ -52,9 +76,9 @@ int validate(const sap_options *o)
         return fail(SAP_ERR_INVALID, "mode must be SAP_DECOUPLED or SAP_COUPLED");
     if (o->factor_prec != SAP_PREC_FP64 && o->factor_prec != SAP_PREC_FP32)
         return fail(SAP_ERR_INVALID, "factor_prec must be SAP_PREC_FP64 or SAP_PREC_FP32");
-    if (o->reserved != 0) return fail(SAP_ERR_INVALID, "reserved field must be 0");
-    if (o->factor_prec == SAP_PREC_FP64 && o->k >= 128)
-        return fail(SAP_ERR_INVALID, "FP64 factors support K <= 127");
+    if (o->sweep_chunks < 0) return fail(SAP_ERR_INVALID, "sweep_chunks must be >= 0");
+    if (o->factor_prec == SAP_PREC_FP64 && o->k > 208)
+        return fail(SAP_ERR_INVALID, "FP64 factors support K <= 208");
     if (o->mode == SAP_COUPLED && o->p > 1 && o->n / o->p < 2 * (int64_t)o->k)
         return fail(SAP_ERR_INVALID, "coupled mode needs floor(N/P) >= 2K");
     if (std::isnan(o->boost_eps)) return fail(SAP_ERR_INVALID, "boost_eps is NaN");
@@ -102,6 +126,17 @@ Layout layout_for(const sap_options &o)
     L.dpart = take(sizeof(double) * 3 * kDotBlocks);
     L.counter = take(64);
     L.sc = take(sizeof(double) * kScalars);
+    const Chunking ck = chunking_for(o);
+    if (ck.nch >= 2) {
+        const size_t xb = sf * (size_t)p * ck.nch * kk;
+        L.xLc = take(xb);
+        L.xUc = take(xb);
+        L.xLr = o.adjoint ? take(xb) : 0;
+        L.xUr = o.adjoint ? take(xb) : 0;
+        L.sq = take(sf * (size_t)p * ck.nch * k);
+        L.sst = take(sf * (size_t)p * ck.nch * k);
+        L.ticket = take(sizeof(unsigned) * (size_t)p);
+    }
     L.total = off;
     return L;
 }
@@ -113,6 +148,7 @@ struct sap_handle_ {
     bool coupled, fp32;
     Partition pt;
     int nchunk;
+    Chunking ck;             // sweep chains per block
     unsigned char *ws;
     Layout L;
     int64_t *h_starts;       // pinned copy of the partition
@@ -187,13 +223,36 @@ int dinv(sap_handle h, int trans, const double *xin, const T *dtop, const T *dbo
         a1.F = h->ptr<T>(h->L.Ur); a1.fwd = 1; a1.diag = 1;
         a2.F = h->ptr<T>(h->L.Lr); a2.fwd = 0; a2.diag = 0;
     }
-    {
-        ProfScope ps(h, SAP_KERNEL_SWEEP, s);
-        HIP_TRY(launch_sweep<T>(a1, s));
+    if (trans) {
+        a1.xf = h->ptr<T>(h->L.xUr);
+        a2.xf = h->ptr<T>(h->L.xLr);
+    } else {
+        a1.xf = h->ptr<T>(h->L.xLc);
+        a2.xf = h->ptr<T>(h->L.xUc);
     }
-    {
-        ProfScope ps(h, SAP_KERNEL_SWEEP, s);
-        HIP_TRY(launch_sweep<T>(a2, s));
+    for (SweepArgs<T> *a : {&a1, &a2}) {
+        if (h->ck.nch < 2) {
+            a->phase = SWEEP_WHOLE;
+            a->nch = 1;
+            ProfScope ps(h, SAP_KERNEL_SWEEP, s);
+            HIP_TRY(launch_sweep<T>(*a, s));
+            continue;
+        }
+        a->nch = h->ck.nch;
+        a->clen = h->ck.clen;
+        a->q = h->ptr<T>(h->L.sq);
+        a->st = h->ptr<T>(h->L.sst);
+        a->ticket = h->ptr<unsigned>(h->L.ticket);
+        a->phase = SWEEP_ZERO_STATE;
+        {
+            ProfScope ps(h, SAP_KERNEL_SWEEP, s);
+            HIP_TRY(launch_sweep<T>(*a, s));
+        }
+        a->phase = SWEEP_FROM_STATE;
+        {
+            ProfScope ps(h, SAP_KERNEL_SWEEP, s);
+            HIP_TRY(launch_sweep<T>(*a, s));
+        }
     }
     return SAP_OK;
 }
@@ -461,6 +520,26 @@ int factor_t(sap_handle h, const double *a_band, hipStream_t s)
         ProfScope ps(h, SAP_KERNEL_LU, s);
         HIP_TRY(launch_banded_lu<T>(lu, s));
     }
+    if (h->ck.nch >= 2) {
+        // transfer matrices of the chunked sweeps (sap_internal.h)
+        HIP_TRY(hipMemsetAsync(h->ptr<unsigned>(h->L.ticket), 0, sizeof(unsigned) * h->opt.p, s));
+        struct Arr { T *F; size_t xf; int fwd, diag; };
+        const Arr arrs[4] = {{lu.Lc, h->L.xLc, 1, 0}, {lu.Uc, h->L.xUc, 0, 1},
+                             {lu.Ur, h->L.xUr, 1, 1}, {lu.Lr, h->L.xLr, 0, 0}};
+        for (const Arr &r : arrs) {
+            if (!r.F) continue;
+            XferArgs<T> xa{};
+            xa.F = r.F;
+            xa.pt = h->pt;
+            xa.fwd = r.fwd;
+            xa.diag = r.diag;
+            xa.nch = h->ck.nch;
+            xa.clen = h->ck.clen;
+            xa.xf = h->ptr<T>(r.xf);
+            ProfScope ps(h, SAP_KERNEL_LU, s);
+            HIP_TRY(launch_sweep_xfer<T>(xa, s));
+        }
+    }
     HIP_TRY(hipEventRecord(h->ev[1], s));
     if (h->coupled) {
         TipsArgs<T> ta{};
@@ -524,6 +603,7 @@ int sap_create(const sap_options *opt, void *workspace, size_t ws_bytes, sap_han
     h->pt.maxnb = n / p + (n % p ? 1 : 0);
     h->pt.starts = h->ptr<int64_t>(L.starts);
     h->nchunk = (int)((h->pt.maxnb + 255) / 256);
+    h->ck = chunking_for(*opt);
     auto cleanup = [&](int code, const std::string &m) {
         if (h->h_starts) (void)hipHostFree(h->h_starts);
         if (h->h_slots) (void)hipHostFree(h->h_slots);

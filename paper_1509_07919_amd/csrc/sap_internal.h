@@ -77,6 +77,10 @@ struct LuArgs {
 };
 template <typename T>
 hipError_t launch_banded_lu(const LuArgs<T> &a, hipStream_t s);
+// blocked LU with matrix-core trailing updates (used for K >= 64)
+template <typename T>
+hipError_t launch_lu_mfma(const LuArgs<T> &a, hipStream_t s);
+bool lu_mfma_supported(int k, bool fp32);
 
 template <typename T>
 struct TipsArgs {
@@ -95,6 +99,23 @@ hipError_t launch_tips(const TipsArgs<T> &a, hipStream_t s);
 // to j+m; otherwise j = nb-1..0 pushing to j-m.  diag: multiply by F[j][0].
 // Input: xin (double) or tin (T), plus optional boundary deltas (T) added to
 // the top/bottom K rows of each block.  Output: dout (double) or tout (T).
+//
+// Chunked sweeps.  With nch >= 2 each block is cut into row chunks
+// [c*clen, min((c+1)*clen, nb)) and one dependent chain runs per chunk.
+// The state a chain hands to the next chunk (in its direction) is the
+// vector of K pending sums p for the K rows that follow the chunk; it is
+// linear in the chunk's inputs and in the state it received, so
+//     p_out(c) = q(c) + X(c) p_in(c),
+// where q(c) is the output state for a zero incoming state and X(c) is the
+// K x K transfer matrix of the chunk (inputs zero), computed once per
+// factorization.  A sweep then runs in two launches: phase 1 runs every
+// chunk with a zero incoming state and writes q; the last workgroup of
+// each block to finish chains the recurrence and writes the true incoming
+// states st; phase 2 reruns every chunk from st and writes the outputs.
+// Storage: q, st [p][nch][K]; X [p][nch][K][K] with X[c][i][m] = d p_out[m]
+// / d p_in[i] (row i contiguous in m); ticket [p] (zero between launches).
+enum SweepPhase : int { SWEEP_WHOLE = 0, SWEEP_ZERO_STATE = 1, SWEEP_FROM_STATE = 2 };
+
 template <typename T>
 struct SweepArgs {
     const T *F;
@@ -105,9 +126,28 @@ struct SweepArgs {
     const T *dtop, *dbot;    // [p][K] or null
     double *dout;
     T *tout;
+    int phase;               // SweepPhase
+    int nch, clen;           // chunks per block (grid p*nch), rows per chunk
+    T *q, *st;
+    const T *xf;
+    unsigned *ticket;
 };
 template <typename T>
 hipError_t launch_sweep(const SweepArgs<T> &a, hipStream_t s);
+
+// Transfer matrices X(c) of every chunk that hands a state on (see above).
+template <typename T>
+struct XferArgs {
+    const T *F;
+    Partition pt;
+    int fwd, diag;
+    int nch, clen;
+    T *xf;
+};
+template <typename T>
+hipError_t launch_sweep_xfer(const XferArgs<T> &a, hipStream_t s);
+// true when chunked sweeps are implemented for this K and precision
+bool sweep_chunking_supported(int k, bool fp32);
 
 // SaP-C interface correction: from g (T, full vector) compute the deltas
 // added to the top (dtop) and bottom (dbot) K rows of each block before the

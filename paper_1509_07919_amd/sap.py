@@ -53,7 +53,7 @@ class sap_options(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("k", ctypes.c_int32), ("p", ctypes.c_int32),
                 ("mode", ctypes.c_int32), ("factor_prec", ctypes.c_int32),
                 ("boost_eps", ctypes.c_double), ("adjoint", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("sweep_chunks", ctypes.c_int32)]
 
 
 class sap_stats(ctypes.Structure):
@@ -120,11 +120,12 @@ def _stream() -> ctypes.c_void_p:
 
 
 def make_options(n: int, k: int, p: int, mode: str = "coupled", factor_prec: str = "fp64",
-                 boost_eps: float = 0.0, adjoint: bool = False) -> sap_options:
+                 boost_eps: float = 0.0, adjoint: bool = False,
+                 sweep_chunks: int = 0) -> sap_options:
     m = {"decoupled": SAP_DECOUPLED, "coupled": SAP_COUPLED}[mode]
     f = {"fp64": SAP_PREC_FP64, "fp32": SAP_PREC_FP32}[factor_prec]
     return sap_options(n=n, k=k, p=p, mode=m, factor_prec=f, boost_eps=boost_eps,
-                       adjoint=1 if adjoint else 0, reserved=0)
+                       adjoint=1 if adjoint else 0, sweep_chunks=sweep_chunks)
 
 
 # ------------------------------------------------------------ thin wrappers
@@ -156,9 +157,9 @@ class SapSolver:
 
     def __init__(self, n: int, k: int, p: int, mode: str = "coupled",
                  factor_prec: str = "fp64", boost_eps: float = 0.0, adjoint: bool = False,
-                 device=None):
+                 device=None, sweep_chunks: int = 0):
         lib = load_library()
-        self.opt = make_options(n, k, p, mode, factor_prec, boost_eps, adjoint)
+        self.opt = make_options(n, k, p, mode, factor_prec, boost_eps, adjoint, sweep_chunks)
         self.n, self.k, self.p = n, k, p
         nbytes = sap_workspace_bytes(self.opt)
         dev = torch.device("cuda") if device is None else torch.device(device)

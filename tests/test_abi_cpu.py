@@ -47,7 +47,7 @@ def ws(lib, **kw):
     (dict(n=100, k=2, p=0), "P must be"),
     (dict(n=100, k=2, p=101), "P must be"),
     (dict(n=100, k=10, p=6, mode="coupled"), "floor(N/P) >= 2K"),
-    (dict(n=10000, k=128, p=4, factor_prec="fp64"), "FP64 factors"),
+    (dict(n=10000, k=209, p=4, factor_prec="fp64"), "FP64 factors"),
 ])
 def test_invalid_options(lib, kw, msg):
     rc, _, err = ws(lib, **kw)
@@ -69,11 +69,21 @@ def test_workspace_size_accounts_for_layout(lib):
     assert bd < b64                                  # no interface matrices
 
 
-def test_reserved_must_be_zero(lib):
+def test_sweep_chunks_must_be_non_negative(lib):
     opt = binding.make_options(n=100, k=2, p=2)
-    opt.reserved = 7
+    opt.sweep_chunks = -1
     out = ctypes.c_size_t(0)
     assert lib.sap_workspace_bytes(ctypes.byref(opt), ctypes.byref(out)) == -1
+
+
+def test_chunked_sweeps_need_transfer_storage(lib):
+    # splitting every block's sweep into chains adds K x K transfer matrices
+    rc1, one, _ = ws(lib, n=200_000, k=50, p=64, mode="coupled", factor_prec="fp64",
+                     sweep_chunks=1)
+    rc8, eight, _ = ws(lib, n=200_000, k=50, p=64, mode="coupled", factor_prec="fp64",
+                       sweep_chunks=8)
+    assert rc1 == rc8 == 0
+    assert eight - one >= 2 * 8 * 64 * 7 * 50 * 50
 
 
 def test_null_handle_calls_fail_cleanly(lib):

@@ -23,10 +23,10 @@ pytestmark = pytest.mark.gpu
 DEV = torch.device("cuda:0")
 
 
-def solver(n, k, p, mode="coupled", prec="fp64", adjoint=False, boost_eps=0.0):
+def solver(n, k, p, mode="coupled", prec="fp64", adjoint=False, boost_eps=0.0, chunks=0):
     from paper_1509_07919_amd import SapSolver
     return SapSolver(n, k, p, mode=mode, factor_prec=prec, adjoint=adjoint,
-                     boost_eps=boost_eps, device=DEV)
+                     boost_eps=boost_eps, device=DEV, sweep_chunks=chunks)
 
 
 def dev(x):
@@ -95,6 +95,73 @@ def test_precond_parity(n, k, p, mode, prec):
     rc, nb = s.status()
     assert rc == 0 and nb == M.n_boosted
     s.close()
+
+
+# wide bands: the matrix-core blocked LU (K >= 64; several window sizes, a
+# partial last panel), the register-ring LU (FP64 97..127, FP32 > 208) and
+# the global-memory tips kernel (3 K^2 elements beyond 128 KB)
+WIDE_CASES = [
+    (4001, 64, 4, "fp32"), (4001, 64, 4, "fp64"), (5003, 96, 5, "fp64"),
+    (5003, 100, 5, "fp32"), (6007, 127, 5, "fp64"), (6007, 128, 5, "fp64"),
+    (6007, 150, 7, "fp32"), (6400, 200, 8, "fp32"), (6400, 200, 8, "fp64"),
+    (6400, 208, 8, "fp64"), (7001, 255, 6, "fp32"),
+]
+
+
+@pytest.mark.parametrize("n,k,p,prec", WIDE_CASES)
+def test_wide_band_precond(n, k, p, prec):
+    case("wide", n, k, p, prec)
+    pb = sapgen.make_problem(n, k, d=1.0, seed=35)
+    eps = 2.0 ** -23 if prec == "fp32" else 2.0 ** -52
+    M = oracle.SapPrecond(pb.band, n, k, p, True, boost_eps=eps)
+    s = solver(n, k, p, prec=prec, adjoint=True)
+    s.factor(dev(pb.band))
+    r = sapgen.splitmix64_uniform(6, 7, np.arange(n))
+    tol = 1e-12 if prec == "fp64" else 2e-5
+    assert rel(host(s.precond(dev(r))), M.apply(r)) <= tol
+    assert rel(host(s.precond(dev(r), trans=True)), M.apply_t(r)) <= tol
+    v, w, rb = s.tips(p - 2)
+    assert rel(v, M.V[p - 2]) <= 10 * tol
+    assert rel(w, M.W[p - 2]) <= 10 * tol
+    rc, nbst = s.status()
+    assert rc == 0 and nbst == M.n_boosted
+    s.close()
+
+
+# chunked sweeps: (n, k, p, mode, sweep_chunks); blocks of unequal size, chunk
+# counts that leave a short last chunk, and K up to the largest chained one
+CHUNK_CASES = [
+    (1000, 1, 2, "decoupled", 3), (3001, 5, 7, "coupled", 2), (5003, 31, 9, "coupled", 7),
+    (20011, 50, 16, "coupled", 0), (20011, 50, 16, "coupled", 19), (8191, 63, 4, "coupled", 5),
+    (12000, 40, 3, "decoupled", 50),
+]
+
+
+@pytest.mark.parametrize("n,k,p,mode,chunks", CHUNK_CASES)
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_chunked_sweeps(n, k, p, mode, chunks, prec):
+    case("chunked", n, k, p, mode, chunks, prec)
+    pb = sapgen.make_problem(n, k, d=0.8, seed=34)
+    eps = 2.0 ** -23 if prec == "fp32" else 2.0 ** -52
+    M = oracle.SapPrecond(pb.band, n, k, p, mode == "coupled", boost_eps=eps)
+    one = solver(n, k, p, mode=mode, prec=prec, adjoint=True, chunks=1)
+    many = solver(n, k, p, mode=mode, prec=prec, adjoint=True, chunks=chunks)
+    a = dev(pb.band)
+    one.factor(a)
+    many.factor(a)
+    r = sapgen.splitmix64_uniform(5, 7, np.arange(n))
+    tol = 1e-12 if prec == "fp64" else 2e-5
+    for trans in (False, True):
+        z1 = host(one.precond(dev(r), trans=trans))
+        zc = host(many.precond(dev(r), trans=trans))
+        want = M.apply_t(r) if trans else M.apply(r)
+        assert rel(zc, want) <= tol
+        assert rel(zc, z1) <= tol
+    # twice in a row: the per-block tickets must be back at zero
+    zc2 = host(many.precond(dev(r)))
+    assert np.array_equal(zc2, host(many.precond(dev(r))))
+    one.close()
+    many.close()
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
