@@ -171,39 +171,46 @@ def main():
         "spmv": spmv_bytes(n, k),
         "lu": lu_bytes(n, k, sf, coupled),
     }
+    # a sweep (one triangular solve over all blocks) is one or two launches
+    # (chunked form: zero-state pass, then the pass from the chained states);
+    # its unit is the whole sweep.  Sweeps per step: 2 (SaP-D) or 4 (SaP-C)
+    # per preconditioner application, n_apply + 1 applications per solve.
+    sweeps = sum((st.n_apply + 1) * (4 if coupled else 2) for st in r["stats"])
+    units = {"sweep": sweeps}
     kernels = {}
     for name, (tms, cnt) in r["kt"].items():
         if cnt == 0:
             continue
+        nu = units.get(name, cnt)
         ent = {"ms_per_step": tms / steps, "launches_per_step": cnt / steps,
-               "avg_us": 1e3 * tms / cnt}
+               "units_per_step": nu / steps, "avg_us": 1e3 * tms / nu}
         if name in per_launch:
-            ent["bytes_per_launch"] = per_launch[name]
-            ent["algorithmic_GBps"] = per_launch[name] / (1e-3 * tms / cnt) / 1e9
+            ent["bytes_per_unit"] = per_launch[name]
+            ent["algorithmic_GBps"] = per_launch[name] / (1e-3 * tms / nu) / 1e9
         kernels[name] = ent
     flops_per_launch = {"lu": lu_flops(n, k, coupled), "tips": tips_flops(n, k, cfg["p"])}
     for name, fl in flops_per_launch.items():
         if name in kernels:
-            kernels[name]["flops_per_launch"] = fl
+            kernels[name]["flops_per_unit"] = fl
             kernels[name]["algorithmic_TFLOPs"] = fl / (1e-6 * kernels[name]["avg_us"]) / 1e12
     dom = max(kernels, key=lambda q: kernels[q]["ms_per_step"])
-    src = {"sweep": "k_sweep.hip", "spmv": "k_vec.hip", "lu": "k_factor.hip",
-           "tips": "k_tips.hip"}.get(dom)
-    avg_s = 1e-3 * r["kt"][dom][0] / r["kt"][dom][1]
+    src = {"sweep": "k_sweep.hip", "spmv": "k_vec.hip",
+           "lu": "k_lu_mfma.hip" if k >= 64 else "k_factor.hip", "tips": "k_tips.hip"}.get(dom)
+    avg_s = 1e-6 * kernels[dom]["avg_us"]
     traffic = traffic_from_profiles(src, "%s_%s_%s" % (dom, head, args.workload)) if src else None
     if dom in per_launch and dom not in flops_per_launch:
         ach = per_launch[dom] / avg_s / 1e9
         roof = {"kernel": dom, "bound": "hbm", "achieved": round(ach, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
                 "traffic": traffic, "avg_us": round(avg_s * 1e6, 2),
-                "bytes_per_launch": per_launch[dom]}
+                "bytes_per_unit": per_launch[dom]}
     elif dom in flops_per_launch:
         peak = FP64_VEC_TFLOPS if head == "fp64" else FP32_VEC_TFLOPS
         ach = flops_per_launch[dom] / avg_s / 1e12
         roof = {"kernel": dom, "bound": "alu", "achieved": round(ach, 4), "peak": peak,
                 "unit": "TFLOP/s", "frac": round(ach / peak, 5), "traffic": traffic,
-                "avg_us": round(avg_s * 1e6, 2), "flops_per_launch": flops_per_launch[dom],
-                "bytes_per_launch": per_launch.get(dom)}
+                "avg_us": round(avg_s * 1e6, 2), "flops_per_unit": flops_per_launch[dom],
+                "bytes_per_unit": per_launch.get(dom)}
     else:
         roof = {"kernel": dom, "bound": None, "note": "no work model for this kernel class"}
 

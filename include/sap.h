@@ -187,7 +187,8 @@ int sap_get_tips(sap_handle h, int32_t i, double *v, double *w, double *rbar,
 #define SAP_KERNEL_CORR    4   /* SaP-C interface correction                 */
 #define SAP_KERNEL_SPMV    5   /* banded SpMV (A or A^T, plain or residual)  */
 #define SAP_KERNEL_KRYLOV  6   /* BiCGStab(2) dots and fused vector updates  */
-#define SAP_KERNEL_COUNT   7
+#define SAP_KERNEL_XFER    7   /* chunk transfer matrices of the sweeps      */
+#define SAP_KERNEL_COUNT   8
 int sap_profile(sap_handle h, int32_t enable);
 int sap_kernel_time(sap_handle h, int32_t kernel, double *ms /* host */,
                     int64_t *launches /* host */);

@@ -363,7 +363,7 @@ class Breakdown(RuntimeError):
 
 
 def bicgstab_l(matvec, precond, b, tol: float = 1e-10, maxit: int = 500,
-               ell: int = 2) -> KrylovResult:
+               ell: int = 2, reliable: float = 0.0) -> KrylovResult:
     """Left-preconditioned BiCGStab(l) (Sleijpen & Fokkema 1993), x0 = 0.
 
     Solves M^{-1} A x = M^{-1} b.  Exit points follow every BiCG step j (after
@@ -375,6 +375,13 @@ def bicgstab_l(matvec, precond, b, tol: float = 1e-10, maxit: int = 500,
     solve stops if that is <= tol.  Otherwise the method restarts from the
     current x with the recomputed residual M^{-1}(b - A x) and rescales the
     threshold by ||M^{-1} t|| / ||t|| of that fresh residual t.
+
+    reliable > 0 adds the reliable-update rule of Sleijpen and van der Vorst
+    (1996): the same true-residual test and restart also happen once the
+    recursive residual has dropped by the factor `reliable` since the last
+    (re)start.  With a preconditioner applied in lower precision the recursive
+    residual stops tracking the true one near that precision; restarting there
+    lets the next steps reduce the true residual again.
     """
     b = np.asarray(b, dtype=np.float64)
     n = b.size
@@ -400,13 +407,14 @@ def bicgstab_l(matvec, precond, b, tol: float = 1e-10, maxit: int = 500,
     st = fresh_state(r0)
     rel_true = 1.0
     pnorm = pnorm0
+    pstart = pnorm0
 
     def check():
         """Exit test at an exit point.  Returns True when converged."""
-        nonlocal thr, st, napply, restarts, rel_true, x
+        nonlocal thr, st, napply, restarts, rel_true, x, pstart
         pn = float(np.linalg.norm(st["r"][0]))
         history.append((napply / (2 * ell), pn / pnorm0))
-        if pn > thr:
+        if pn > thr and not (reliable > 0.0 and pn <= reliable * pstart):
             return False
         t = b - matvec(x)
         rel_true = float(np.linalg.norm(t)) / bnorm
@@ -416,7 +424,8 @@ def bicgstab_l(matvec, precond, b, tol: float = 1e-10, maxit: int = 500,
         napply += 1
         restarts += 1
         tn = float(np.linalg.norm(t))
-        thr = tol * bnorm * float(np.linalg.norm(rfresh)) / tn
+        pstart = float(np.linalg.norm(rfresh))
+        thr = tol * bnorm * pstart / tn
         st = fresh_state(rfresh)
         return False
 

@@ -546,6 +546,7 @@ static hipError_t launch_lu_blk(const LuArgs<T> &a, hipStream_t s)
     const int k = a.pt.k, KB = k + B;
     const size_t lds = (2 * (size_t)KB * (KB + 1) + 2 * (size_t)(2 * k + 3) * S +
                         (size_t)S * 2 * (k + 1)) * sizeof(T);
+    if (lds > kMaxLds) return hipErrorInvalidValue;
     auto kern = k_banded_lu_blk<T, B, S, NT, RPL>;
     hipError_t e = hipFuncSetAttribute((const void *)kern,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -555,17 +556,11 @@ static hipError_t launch_lu_blk(const LuArgs<T> &a, hipStream_t s)
     return hipGetLastError();
 }
 
-// LDS bytes of the blocked kernel for panel width B and chunk S
-static size_t lu_blk_lds(int k, int B, int S, size_t sz)
-{
-    const size_t KB = (size_t)k + B;
-    return (2 * KB * (KB + 1) + 2 * (size_t)(2 * k + 3) * S + (size_t)S * 2 * (k + 1)) * sz;
-}
-
 template <typename T, int WC, int S, int NT>
 static hipError_t launch_lu_cfg(const LuArgs<T> &a, hipStream_t s)
 {
     const size_t lds = (2 * (size_t)(2 * a.pt.k + 3) * S + (size_t)S * 2 * (a.pt.k + 1)) * sizeof(T);
+    if (lds > kMaxLds) return hipErrorInvalidValue;
     auto kern = k_banded_lu<T, WC, S, NT>;
     hipError_t e = hipFuncSetAttribute((const void *)kern,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

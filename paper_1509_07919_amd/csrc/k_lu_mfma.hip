@@ -37,9 +37,8 @@ template <typename T> struct Acc4;
 template <> struct Acc4<float> { typedef float type __attribute__((ext_vector_type(4))); };
 template <> struct Acc4<double> { typedef double type __attribute__((ext_vector_type(4))); };
 
-// D += A B for a 16 x 16 x 4 slice.  Operand and result layouts (lane l):
-//   A: A[l & 15][l >> 4]      B: B[l >> 4][l & 15]
-//   D: element r is D[4 * (l >> 4) + r][l & 15]
+// D += A B for a 16 x 16 x 4 slice.  Operand layouts (lane l): A[l & 15][l >> 4]
+// and B[l >> 4][l & 15].  Result: element r of lane l is D[drow][dcol] below.
 __device__ __forceinline__ Acc4<float>::type mfma16(float a, float b, Acc4<float>::type c)
 {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
@@ -48,6 +47,16 @@ __device__ __forceinline__ Acc4<double>::type mfma16(double a, double b, Acc4<do
 {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
+
+template <typename T> struct DLayout;
+template <> struct DLayout<float> {     // rows 4(l >> 4) .. +3 of column l & 15
+    static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+    static __device__ __forceinline__ int col(int lane, int) { return lane & 15; }
+};
+template <> struct DLayout<double> {    // rows l >> 4, +4, +8, +12 of column l & 15
+    static __device__ __forceinline__ int row(int lane, int r) { return (lane >> 4) + 4 * r; }
+    static __device__ __forceinline__ int col(int lane, int) { return lane & 15; }
+};
 
 constexpr int kMfmaWaves = 4;
 
@@ -66,6 +75,7 @@ template <typename T, int NTL>
 __global__ __launch_bounds__(kMfmaWaves * 64) void k_lu_mfma(LuArgs<T> a)
 {
     using v4 = typename Acc4<T>::type;
+    using DL = DLayout<T>;
     constexpr int NW = kMfmaWaves;
     constexpr int NT = NW * 64;
     constexpr int RPW = (NTL + NW - 1) / NW;   // slot rows per wave
@@ -121,7 +131,8 @@ __global__ __launch_bounds__(kMfmaWaves * 64) void k_lu_mfma(LuArgs<T> a)
 #pragma unroll
             for (int r = 0; r < 4; ++r)
                 acc[ai][b][r] = (T)block_entry(a.band, n, k, s0, nb, ul,
-                                               16 * (wave + NW * ai) + 4 * lq + r, 16 * b + lr);
+                                               16 * (wave + NW * ai) + DL::row(lane, r),
+                                               16 * b + DL::col(lane, r));
     // offset of slot index x from the panel slot ap, i.e. tile index minus p
     auto off = [](int x, int ap) { return x >= ap ? x - ap : x - ap + NTL; };
 
@@ -175,11 +186,11 @@ __global__ __launch_bounds__(kMfmaWaves * 64) void k_lu_mfma(LuArgs<T> a)
                     if (co == 0) {
 #pragma unroll
                         for (int r = 0; r < 4; ++r)
-                            PC[(16 * ro + 4 * lq + r) * 17 + lr] = acc[ai][b][r];
+                            PC[(16 * ro + DL::row(lane, r)) * 17 + DL::col(lane, r)] = acc[ai][b][r];
                     } else if (ro == 0) {
 #pragma unroll
                         for (int r = 0; r < 4; ++r)
-                            PR[(4 * lq + r) * PRP + 16 * co + lr] = acc[ai][b][r];
+                            PR[DL::row(lane, r) * PRP + 16 * co + DL::col(lane, r)] = acc[ai][b][r];
                     }
                 }
             }
@@ -259,10 +270,10 @@ __global__ __launch_bounds__(kMfmaWaves * 64) void k_lu_mfma(LuArgs<T> a)
             }
             if (isl) {
 #pragma unroll
-                for (int r = 0; r < 4; ++r) PC[(16 * o + 4 * lq + r) * 17 + lr] = d[r];
+                for (int r = 0; r < 4; ++r) PC[(16 * o + DL::row(lane, r)) * 17 + DL::col(lane, r)] = d[r];
             } else {
 #pragma unroll
-                for (int r = 0; r < 4; ++r) PR[(4 * lq + r) * PRP + 16 * o + lr] = d[r];
+                for (int r = 0; r < 4; ++r) PR[DL::row(lane, r) * PRP + 16 * o + DL::col(lane, r)] = d[r];
             }
         }
         __syncthreads();
@@ -359,6 +370,7 @@ template <typename T, int NTL>
 static hipError_t launch_lu_mfma_ntl(const LuArgs<T> &a, hipStream_t s)
 {
     const size_t lds = lu_mfma_lds_bytes(a.pt.k, NTL, sizeof(T));
+    if (lds > kMaxLds) return hipErrorInvalidValue;
     auto kern = k_lu_mfma<T, NTL>;
     hipError_t e = hipFuncSetAttribute((const void *)kern,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -380,6 +392,9 @@ hipError_t launch_lu_mfma(const LuArgs<T> &a, hipStream_t s)
     const int k = a.pt.k;
     if (!lu_mfma_supported(k, sizeof(T) == 4)) return hipErrorInvalidValue;
     const int ntl = (k + 15) / 16 + 1;
+    if (ntl <= 2) return launch_lu_mfma_ntl<T, 2>(a, s);
+    if (ntl <= 3) return launch_lu_mfma_ntl<T, 3>(a, s);
+    if (ntl <= 4) return launch_lu_mfma_ntl<T, 4>(a, s);
     if (ntl <= 5) return launch_lu_mfma_ntl<T, 5>(a, s);
     if (ntl <= 7) return launch_lu_mfma_ntl<T, 7>(a, s);
     if (ntl <= 9) return launch_lu_mfma_ntl<T, 9>(a, s);

@@ -92,7 +92,7 @@ __device__ void chain_states(const SweepArgs<T> &a, int blk, int nchb, T *sh)
 template <typename T, int KR, int S, bool FWD, bool DIAG, int PH>
 __global__ __launch_bounds__(256) void k_sweep(SweepArgs<T> a)
 {
-    static_assert(S % 64 == 0, "chunk must hold whole 64-step blocks");
+    static_assert(S == 32 || S == 64, "a chunk is one or half a 64-step block");
     static_assert(KR >= 2, "ring must cover 64 + K slots");
     // LDS row pitch: slots 0..K hold a coefficient row, slots K+1..PITCH-1
     // are zero (at least 8 of them), so a clamped offset needs no mask
@@ -208,7 +208,7 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs<T> a)
         // Steps run in groups of G; the LDS operands of group g+1 (diagonal
         // factor, input, and the KR coefficients each lane pushes) are read while
         // the dependent chain of group g runs.
-        constexpr int G = 4;
+        constexpr int G = (KR * sizeof(T) > 16) ? 4 : 8;
         struct Grp {
             T d[G], vd[G], cf[G][KR];
         };
@@ -222,59 +222,64 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs<T> a)
                          ? -a.st[((int64_t)blk * a.nch + ch) * k + m] : T(0);
         }
 
+        T ov = T(0);                                  // outputs of the current 64-block
         for (int64_t t = 0; t < nchunks; ++t) {
             const T *c = cst + (t & 1) * S * PITCH;
             const T *vv = vst + (t & 1) * S;
-            for (int g = 0; g < S / 64; ++g) {
-                const int64_t jb = t * S + 64 * g;        // first step of this 64-block
-                if (jb >= nst) break;
-                const int ulim = (int)min((int64_t)64, nst - jb);
-                auto load = [&](int u0, Grp &q) {
+            // the staged steps t*S .. t*S+cnt-1 are steps ub .. ub+cnt-1 of the
+            // 64-step block that starts at step jb (S = 32: two chunks per block)
+            const int ub = (int)((t * S) & 63);
+            const int64_t jb = t * S - ub;
+            const int cnt = (int)min((int64_t)S, nst - t * S);
+            const int ulim = ub + cnt;
+            auto load = [&](int u0, Grp &q) {
 #pragma unroll
-                    for (int e = 0; e < G; ++e) {
-                        const int u = min(u0 + e, 63);
-                        const T *crow = c + (64 * g + u) * PITCH;
-                        q.d[e] = DIAG ? crow[0] : T(1);
-                        q.vd[e] = vv[64 * g + u] * q.d[e];
+                for (int e = 0; e < G; ++e) {
+                    const int uc = min(u0 + e, S - 1);       // staged row
+                    const int u = ub + uc;                    // step in the 64-block
+                    const T *crow = c + uc * PITCH;
+                    q.d[e] = DIAG ? crow[0] : T(1);
+                    q.vd[e] = vv[uc] * q.d[e];
 #pragma unroll
-                        for (int s = 0; s < KR; ++s) {
-                            // step offset of slot (s, lane).  Offsets > K read a
-                            // zero slot; offsets <= 0 occur only for s = 0 in lanes
-                            // whose step is already done, where the value is unused.
-                            const int m = 64 * s + lane - u;
-                            q.cf[e][s] = crow[min(max(m, 0), PITCH - 1)];
-                        }
+                    for (int s = 0; s < KR; ++s) {
+                        // step offset of slot (s, lane).  Offsets > K read a
+                        // zero slot; offsets <= 0 occur only for s = 0 in lanes
+                        // whose step is already done, where the value is unused.
+                        const int m = 64 * s + lane - u;
+                        q.cf[e][s] = crow[min(max(m, 0), PITCH - 1)];
                     }
-                };
-                T ov = T(0);
-                auto run = [&](int u0, const Grp &q) {
-#pragma unroll
-                    for (int e = 0; e < G; ++e) {
-                        const int u = u0 + e;
-                        if (u < ulim) {
-                            const T x = fma(acc[0], q.d[e], q.vd[e]);   // acc = -pending
-                            const T xb = lane_bcast(x, u);
-#pragma unroll
-                            for (int s = 0; s < KR; ++s) acc[s] = fma(-q.cf[e][s], xb, acc[s]);
-                            ov = lane == u ? xb : ov;
-                        }
-                    }
-                };
-                Grp ga, gb;
-                load(0, ga);
-                for (int u0 = 0; u0 < ulim; u0 += 2 * G) {
-                    load(u0 + G, gb);
-                    run(u0, ga);
-                    load(u0 + 2 * G, ga);
-                    run(u0 + G, gb);
                 }
+            };
+            auto run = [&](int u0, const Grp &q) {
+#pragma unroll
+                for (int e = 0; e < G; ++e) {
+                    if (u0 + e < cnt) {
+                        const int u = ub + u0 + e;
+                        const T x = fma(acc[0], q.d[e], q.vd[e]);   // acc = -pending
+                        const T xb = lane_bcast(x, u);
+#pragma unroll
+                        for (int s = 0; s < KR; ++s) acc[s] = fma(-q.cf[e][s], xb, acc[s]);
+                        ov = lane == u ? xb : ov;
+                    }
+                }
+            };
+            Grp ga, gb;
+            load(0, ga);
+            for (int u0 = 0; u0 < cnt; u0 += 2 * G) {
+                load(u0 + G, gb);
+                run(u0, ga);
+                load(u0 + 2 * G, ga);
+                run(u0 + G, gb);
+            }
+            const bool last = t * S + cnt == nst;
+            if (ulim == 64 || last) {
                 const int64_t st = jb + lane;
-                if (PH != SWEEP_ZERO_STATE && st < nst) {
+                if (PH != SWEEP_ZERO_STATE && lane < ulim) {
                     const int64_t r = s0 + row_of(st);
                     if (a.dout) a.dout[r] = (double)ov;
                     else a.tout[r] = ov;
                 }
-                if (PH == SWEEP_ZERO_STATE && jb + ulim == nst) {
+                if (PH == SWEEP_ZERO_STATE && last) {
                     // outgoing state: pending sums of the K steps after the
                     // chunk, slots ulim .. ulim+K-1 of the ring before it shifts
 #pragma unroll
@@ -286,6 +291,7 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs<T> a)
 #pragma unroll
                 for (int s = 0; s < KR - 1; ++s) acc[s] = acc[s + 1];
                 acc[KR - 1] = T(0);
+                ov = T(0);
             }
             __syncthreads();
         }
@@ -310,6 +316,7 @@ template <typename T, int KR, int S, bool FWD, bool DIAG, int PH>
 static hipError_t launch_sweep_ph(const SweepArgs<T> &a, hipStream_t s)
 {
     const size_t lds = (2 * (size_t)S * (64 * (KR - 1) + 8) + 2 * S) * sizeof(T);
+    if (lds > kMaxLds) return hipErrorInvalidValue;
     auto kern = k_sweep<T, KR, S, FWD, DIAG, PH>;
     hipError_t e = hipFuncSetAttribute((const void *)kern,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -331,16 +338,18 @@ static hipError_t launch_sweep_cfg(const SweepArgs<T> &a, hipStream_t s)
     if (a.phase != SWEEP_WHOLE) return hipErrorInvalidValue;
     return launch_sweep_ph<T, KR, S, FWD, DIAG, SWEEP_WHOLE>(a, s);
 }
-// chunks of 64 steps: two LDS buffers of 64 rows of pitch 64*(KR-1)
+// two LDS buffers of S rows of pitch 64*(KR-1)+8: S = 64, or 32 where that
+// would not fit (FP64 with K >= 128)
 template <typename T, int KR>
 static hipError_t launch_sweep_kr(const SweepArgs<T> &a, hipStream_t s)
 {
+    constexpr int S = (sizeof(T) == 8 && KR >= 4) ? 32 : 64;
     if (a.fwd) {
-        if (a.diag) return launch_sweep_cfg<T, KR, 64, true, true>(a, s);
-        return launch_sweep_cfg<T, KR, 64, true, false>(a, s);
+        if (a.diag) return launch_sweep_cfg<T, KR, S, true, true>(a, s);
+        return launch_sweep_cfg<T, KR, S, true, false>(a, s);
     }
-    if (a.diag) return launch_sweep_cfg<T, KR, 64, false, true>(a, s);
-    return launch_sweep_cfg<T, KR, 64, false, false>(a, s);
+    if (a.diag) return launch_sweep_cfg<T, KR, S, false, true>(a, s);
+    return launch_sweep_cfg<T, KR, S, false, false>(a, s);
 }
 
 template <>

@@ -420,14 +420,21 @@ int krylov(sap_handle h, int trans, const double *b, double *x, double tol, int3
     const double pnorm0 = std::sqrt(nrm2);
     double thr = tol * pnorm0;
     int napply = 0;
+    // Reliable updates (Sleijpen and van der Vorst 1996): with FP32 factors
+    // the recursive residual stops tracking the true one near FP32 accuracy,
+    // so once it has dropped by this factor since the last (re)start the true
+    // residual is tested and the iteration restarted from it.
+    const double reliable = h->fp32 ? 1e-4 : 0.0;
+    double pstart = pnorm0;
 
     // exit test: returns 1 = converged, 2 = restarted, 0 = continue, < 0 error
     auto exit_test = [&]() -> int {
         TRY(sync_read(h, s, &nrm2, &brk));
         if (brk != 0.0) return SAP_ERR_BREAKDOWN;
         if (!std::isfinite(nrm2)) return SAP_ERR_BREAKDOWN;
-        loc.rel_resid_precond = std::sqrt(nrm2) / pnorm0;
-        if (std::sqrt(nrm2) > thr) return 0;
+        const double pn = std::sqrt(nrm2);
+        loc.rel_resid_precond = pn / pnorm0;
+        if (pn > thr && !(pn <= reliable * pstart)) return 0;
         {
             ProfScope ps(h, SAP_KERNEL_SPMV, s);
             HIP_TRY(launch_spmv(A, n, k, x, b, t, trans, s));    // t = b - A x
@@ -443,7 +450,8 @@ int krylov(sap_handle h, int trans, const double *b, double *x, double tol, int3
         ++loc.restarts;
         TRY(update(h, UPD_RESTART, x, OP_INIT, 2, s));
         TRY(sync_read(h, s, &nrm2, &brk));
-        thr = tol * bnorm * std::sqrt(nrm2) / tn;
+        pstart = std::sqrt(nrm2);
+        thr = tol * bnorm * pstart / tn;
         return 2;
     };
 
@@ -536,7 +544,7 @@ int factor_t(sap_handle h, const double *a_band, hipStream_t s)
             xa.nch = h->ck.nch;
             xa.clen = h->ck.clen;
             xa.xf = h->ptr<T>(r.xf);
-            ProfScope ps(h, SAP_KERNEL_LU, s);
+            ProfScope ps(h, SAP_KERNEL_XFER, s);
             HIP_TRY(launch_sweep_xfer<T>(xa, s));
         }
     }

@@ -29,6 +29,7 @@
 namespace sap {
 
 constexpr int kMaxK = 255;
+constexpr size_t kMaxLds = 160 * 1024;    // LDS bytes per workgroup on gfx950
 constexpr int kDotBlocks = 512;   // fixed grid of the reduction kernels
 
 enum KrylovOp : int {

@@ -36,7 +36,7 @@ EXPORTED = ("sap_workspace_bytes", "sap_create", "sap_factor", "sap_solve",
             "sap_precond_apply", "sap_get_tips", "sap_profile", "sap_kernel_time",
             "sap_destroy", "sap_last_error")
 
-KERNELS = ("norm", "lu", "tips", "sweep", "corr", "spmv", "krylov")
+KERNELS = ("norm", "lu", "tips", "sweep", "corr", "spmv", "krylov", "xfer")
 
 
 class SapLibraryMissing(RuntimeError):

@@ -1,0 +1,187 @@
+"""The five benchmark configurations at their full sizes, through the C ABI.
+
+Every solve is checked against properties the oracle computes at any size:
+the true relative residual ||b - A x|| / ||b|| (FP64 band SpMV of the
+oracle) must meet the tolerance, and the solution must match x_true, from
+which b = A x_true was formed (relative error <= 1e-8 for d >= 0.5, <= 1e-6
+for the weakly dominant case).  Where the oracle's banded LU with partial
+pivoting finishes in seconds, the solution is also compared with it.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import sapgen
+
+pytestmark = pytest.mark.gpu
+
+DEV = torch.device("cuda:0")
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64)).to(DEV)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def problem(name, seed=0):
+    cfg = sapgen.WORKLOADS[name]
+    pb = sapgen.make_problem(cfg["n"], cfg["k"], d=cfg["d"], seed=seed,
+                             row_scale_decades=cfg["row_scale_decades"])
+    return cfg, pb
+
+
+def solver(cfg, prec=None, adjoint=False):
+    from paper_1509_07919_amd import SapSolver
+    return SapSolver(cfg["n"], cfg["k"], cfg["p"], mode=cfg["mode"],
+                     factor_prec=prec or cfg["factor_prec"], adjoint=adjoint, device=DEV)
+
+
+def err_tol(cfg):
+    return 1e-8 if cfg["d"] >= 0.5 else 1e-6
+
+
+# direct FP64 solves for the workloads where the oracle takes seconds
+DIRECT = {"sapd_n10k_k10", "sapc_n200k_k50", "sapc_n100k_k32_adjoint", "sapc_n200k_k100_weak"}
+
+
+@pytest.mark.parametrize("name", list(sapgen.WORKLOADS))
+def test_workload_solve(name):
+    print("CASE workload", name, flush=True)
+    cfg, pb = problem(name)
+    n, k = cfg["n"], cfg["k"]
+    s = solver(cfg)
+    s.factor(dev(pb.band))
+    x, st = s.solve(dev(pb.b), tol=cfg["tol"], maxit=500)
+    x = host(x)
+    assert st.converged
+    r = pb.b - oracle.bandmv(pb.band, n, k, x)
+    assert np.linalg.norm(r) / np.linalg.norm(pb.b) <= cfg["tol"] * 1.001
+    assert rel(x, pb.x_true) <= err_tol(cfg)
+    if name in DIRECT:
+        assert rel(x, oracle.solve_direct(pb.band, n, k, pb.b)) <= err_tol(cfg)
+    s.close()
+
+
+def test_mixed_precision_matches_fp64_run():
+    """N=500k, K=200, d=0.5: FP32 factors, tips and sweeps with the FP64
+    Krylov loop reach the same solution as the all-FP64 run on the seed."""
+    name = "sapc_n500k_k200_mixed"
+    print("CASE mixed vs fp64", name, flush=True)
+    cfg, pb = problem(name)
+    a, b = dev(pb.band), dev(pb.b)
+    xs = {}
+    for prec in ("fp32", "fp64"):
+        s = solver(cfg, prec=prec)
+        s.factor(a)
+        x, st = s.solve(b, tol=cfg["tol"], maxit=500)
+        assert st.converged and st.rel_resid_true <= cfg["tol"]
+        xs[prec] = host(x)
+        s.close()
+    assert rel(xs["fp32"], xs["fp64"]) <= 1e-8
+    assert rel(xs["fp64"], pb.x_true) <= 1e-8
+
+
+def _picks(n, k, count, seed):
+    """`count` distinct b indices and `count` distinct valid band slots (r, c),
+    drawn with the PICK stream."""
+    u = 0.5 * (sapgen.splitmix64_uniform(seed, sapgen.STREAM_PICK, np.arange(8 * count)) + 1.0)
+    bi = []
+    for v in u[:4 * count]:
+        j = int(v * n)
+        if j not in bi:
+            bi.append(j)
+        if len(bi) == count:
+            break
+    slots = []
+    for q in range(4 * count, 8 * count, 2):
+        r = int(u[q] * n)
+        c = r + int(u[q + 1] * (2 * k + 1)) - k
+        if 0 <= c < n and (r, c) not in slots:
+            slots.append((r, c))
+        if len(slots) == count:
+            break
+    return bi, slots
+
+
+def test_adjoint_gradient_finite_differences():
+    """N=100k, K=32, P=32, FP32 preconditioner: L = 0.5||x - x_target||^2.
+    dL/db and dL/dA (band) from the adjoint solve agree with the oracle's
+    gradients from direct solves, and with central differences (h = 1e-6) on
+    20 band entries and 20 entries of b."""
+    from paper_1509_07919_amd import sap_solve_autograd
+    name = "sapc_n100k_k32_adjoint"
+    print("CASE adjoint fd", name, flush=True)
+    cfg, pb = problem(name)
+    n, k = cfg["n"], cfg["k"]
+    xt = sapgen.normal_draws(0, sapgen.STREAM_XTARGET, n)
+    s = solver(cfg, adjoint=True)
+    a = dev(pb.band).requires_grad_(True)
+    b = dev(pb.b).requires_grad_(True)
+    x = sap_solve_autograd(a, b, s, tol=1e-12)
+    loss = 0.5 * ((x - dev(xt)) ** 2).sum()
+    loss.backward()
+    gb, ga = host(b.grad), host(a.grad)
+    _, gb_o, ga_o = oracle.gradients(pb.band, n, k, pb.b, xt)
+    assert rel(gb, gb_o) <= 1e-8
+    assert rel(ga, ga_o) <= 1e-8
+
+    fd_solver = solver(cfg)
+
+    def lossf(band_t, rhs_t):
+        fd_solver.factor(band_t)
+        y, st = fd_solver.solve(rhs_t, tol=1e-13, maxit=500)
+        assert st.converged
+        return 0.5 * float(((y - dev(xt)) ** 2).sum())
+
+    h = 1e-6
+    bi, slots = _picks(n, k, 20, 7)
+    assert len(bi) == 20 and len(slots) == 20
+    band0, b0 = dev(pb.band), dev(pb.b)
+    for j in bi:
+        bp, bm = b0.clone(), b0.clone()
+        bp[j] += h
+        bm[j] -= h
+        fd = (lossf(band0, bp) - lossf(band0, bm)) / (2 * h)
+        assert abs(fd - gb[j]) <= 1e-4 * max(1.0, abs(gb[j]))
+    for (r, c) in slots:
+        pos = (k + r - c) * n + c
+        ap, am = band0.clone(), band0.clone()
+        ap[pos] += h
+        am[pos] -= h
+        fd = (lossf(ap, b0) - lossf(am, b0)) / (2 * h)
+        assert abs(fd - ga[pos]) <= 1e-4 * max(1.0, abs(ga[pos]))
+    s.close()
+    fd_solver.close()
+
+
+def test_weak_dominance_adjoint_wrt_b():
+    """N=200k, K=100, d=0.1, rows scaled by 10^U[-2,2]: FP32 factors with
+    pivot boosting, FP64 BiCGStab(2) to 1e-8; the adjoint solve gives
+    dL/db = A^{-T}(x - x_target), compared with the oracle's direct solve."""
+    name = "sapc_n200k_k100_weak"
+    print("CASE weak adjoint", name, flush=True)
+    cfg, pb = problem(name)
+    n, k = cfg["n"], cfg["k"]
+    xt = sapgen.normal_draws(0, sapgen.STREAM_XTARGET, n)
+    s = solver(cfg, adjoint=True)
+    s.factor(dev(pb.band))
+    x, st = s.solve(dev(pb.b), tol=cfg["tol"], maxit=500)
+    assert st.converged
+    lam, st2 = s.solve_adjoint(x - dev(xt), tol=cfg["tol"], maxit=500)
+    assert st2.converged
+    lu = oracle.DirectLU(pb.band, n, k)
+    xo = lu.solve(pb.b)
+    lam_o = lu.solve(xo - xt, trans=True)
+    assert rel(host(x), xo) <= 1e-6
+    assert rel(host(lam), lam_o) <= 1e-6
+    s.close()

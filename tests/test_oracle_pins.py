@@ -395,6 +395,30 @@ def test_bicgstab2_scalar_operator_first_exit():
     np.testing.assert_allclose(res.x, b / 3.0, rtol=1e-15)
 
 
+def test_reliable_updates_with_a_low_precision_preconditioner():
+    """The inverse of a nearby matrix (relative distance ~1e-6), its output
+    rounded to FP32: the recursive residual falls far below the true one,
+    which stalls near 1e-7.  The reliable-update rule restarts as soon as the
+    recursive residual has dropped by 1e-4 and reaches 1e-12 in fewer operator
+    applications than restarting only at the threshold; both end at the exact
+    solution."""
+    n = 60
+    rng = np.random.default_rng(2)
+    a = np.eye(n) * 5 + rng.standard_normal((n, n)) / np.sqrt(n)
+    b = rng.standard_normal(n)
+    ainv = np.linalg.inv(a + 1e-6 * rng.standard_normal((n, n)))
+    pre = lambda v: (ainv @ v).astype(np.float32).astype(np.float64)
+    plain = bicgstab_l(lambda v: a @ v, pre, b, tol=1e-12)
+    rel = bicgstab_l(lambda v: a @ v, pre, b, tol=1e-12, reliable=1e-4)
+    xs = np.linalg.solve(a, b)
+    for res in (plain, rel):
+        assert res.converged and res.rel_resid_true <= 1e-12
+        np.testing.assert_allclose(res.x, xs, rtol=0, atol=1e-10 * np.abs(xs).max())
+    assert rel.restarts >= 1 and rel.iters < plain.iters
+    off = bicgstab_l(lambda v: a @ v, pre, b, tol=1e-12, reliable=0.0)
+    assert np.array_equal(off.x, plain.x) and off.iters == plain.iters
+
+
 @pytest.mark.parametrize("coupled,p,d", [(False, 16, 1.0), (True, 8, 1.0), (True, 8, 0.5)])
 def test_sap_bicgstab2_converges_to_direct(coupled, p, d):
     from oracle import sap_solve
