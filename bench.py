@@ -61,23 +61,25 @@ def tips_flops(n, k, p):
 
 def kernel_source_hash(name: str) -> str:
     path = os.path.join(ROOT, "paper_1509_07919_amd", "csrc", name)
+    if not name or not os.path.exists(path):
+        return ""
     with open(path, "rb") as f:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def traffic_from_profiles(kernel_file: str, tag: str):
-    """HBM bytes per launch measured with rocprofv3 counters, from a committed
-    summary that records the hash of the kernel source it was taken on; None
-    if absent or if the kernel changed since."""
+def traffic_from_profiles(tag: str):
+    """HBM bytes per unit (a launch; a whole sweep for the sweeps) measured with
+    rocprofv3 counters, from a committed summary that records the hash of the
+    kernel source it was taken on; None if absent or if the kernel changed."""
     path = os.path.join(PROFILE_DIR, "traffic_%s.json" % tag.split("_", 2)[2])
     if not os.path.exists(path):
         return None
     with open(path) as f:
         data = json.load(f)
     ent = data.get(tag)
-    if not ent or ent.get("source_sha256_16") != kernel_source_hash(kernel_file):
+    if not ent or ent.get("source_sha256_16") != kernel_source_hash(ent.get("source", "")):
         return None
-    return ent.get("bytes_per_launch")
+    return ent.get("bytes_per_unit")
 
 
 def run_gpu(args, prec, pb, a, b):
@@ -194,10 +196,8 @@ def main():
             kernels[name]["flops_per_unit"] = fl
             kernels[name]["algorithmic_TFLOPs"] = fl / (1e-6 * kernels[name]["avg_us"]) / 1e12
     dom = max(kernels, key=lambda q: kernels[q]["ms_per_step"])
-    src = {"sweep": "k_sweep.hip", "spmv": "k_vec.hip",
-           "lu": "k_lu_mfma.hip" if k >= 64 else "k_factor.hip", "tips": "k_tips.hip"}.get(dom)
     avg_s = 1e-6 * kernels[dom]["avg_us"]
-    traffic = traffic_from_profiles(src, "%s_%s_%s" % (dom, head, args.workload)) if src else None
+    traffic = traffic_from_profiles("%s_%s_%s" % (dom, head, args.workload))
     if dom in per_launch and dom not in flops_per_launch:
         ach = per_launch[dom] / avg_s / 1e9
         roof = {"kernel": dom, "bound": "hbm", "achieved": round(ach, 1),

@@ -67,7 +67,7 @@ extern "C" {
 
 typedef struct sap_options {
     int64_t n;            /* matrix order N >= 1                            */
-    int32_t k;            /* half-bandwidth K, 0 <= K < N, K <= 255 (K <= 208 with FP64 factors) */
+    int32_t k;            /* half-bandwidth K, 0 <= K < N, K <= 255 (K <= 160 with FP64 factors) */
     int32_t p;            /* partitions P, 1 <= P <= N (SaP-C: N/P >= 2K)   */
     int32_t mode;         /* SAP_DECOUPLED or SAP_COUPLED                   */
     int32_t factor_prec;  /* SAP_PREC_FP64 or SAP_PREC_FP32                 */

@@ -18,16 +18,16 @@
 // lifetime, so nothing moves when the window slides by one tile per panel.
 // Per panel of 16 pivots (tile index p, slot ap = p mod NTL):
 //   (a) the owners copy the panel tile column and tile row into LDS;
-//   (b) wave 0 factors the 16 x 16 diagonal tile (boosting each pivot) and
-//       forms U11^-1 and L11^-1 by substitution;
-//   (c) L21 = A21 U11^-1 and U12 = L11^-1 A12, one 16 x 16 x 16 MFMA product
-//       per tile;
+//   (b) wave 0 factors the 16 x 16 diagonal tile (boosting each pivot);
+//   (c) L21 solves X U11 = A21 (a thread per row) and U12 solves
+//       L11 Y = A12 (a thread per column) by substitution;
 //   (d) every trailing tile is updated in registers, A22 -= L21 U12 (4 MFMAs
 //       per tile), and the panel's L columns and U rows are written out;
 //   (e) the slots of the retired tile row and column receive the tiles that
 //       enter the window.  They are untouched entries of A, copied from HBM
 //       straight into LDS (global_load_lds, no registers) at the start of the
-//       panel as 2K+1 diagonal runs of 16 consecutive band entries.
+//       panel as 2K+1 diagonal runs of 16 consecutive band entries, then laid
+//       out as tiles by all threads.
 #include "sap_internal.h"
 #include "dev_common.h"
 
@@ -62,8 +62,8 @@ constexpr int kMfmaWaves = 4;
 
 // LDS layout: stage [2K+3][16] doubles (row 0 zero, row q+1 = diagonal q,
 // row 2K+2 receives the unused half of the last copy), then in elements of T:
-// PC [WR][17] panel tile column, PR [16][WR+1] panel tile row, UI and LI
-// [16][17] triangular inverses
+// PC [WR][17] panel tile column, PR [16][WR+1] panel tile row, UI [16]
+// reciprocal pivots (with room to spare)
 __host__ __device__ inline size_t lu_mfma_lds_bytes(int k, int ntl, size_t tsize)
 {
     const int wr = 16 * ntl;
@@ -101,8 +101,7 @@ __global__ __launch_bounds__(kMfmaWaves * 64) void k_lu_mfma(LuArgs<T> a)
     double *stage = reinterpret_cast<double *>(smem_raw);
     T *PC = reinterpret_cast<T *>(stage + (2 * k + 3) * 16);
     T *PR = PC + WR * 17;
-    T *UI = PR + 16 * PRP;
-    T *LI = UI + 16 * 17;
+    T *UI = PR + 16 * PRP;                       // reciprocal pivots of the panel
 
     if (tid == 0) {
         double m = 0.0;
@@ -197,10 +196,9 @@ __global__ __launch_bounds__(kMfmaWaves * 64) void k_lu_mfma(LuArgs<T> a)
         }
         __syncthreads();
 
-        // (b) diagonal tile: LU with boosting (lane t < 16 holds row t), then
-        // column lane of U11^-1 and of L11^-1 (pivots past the block end, only
-        // in the last panel, have zero rows and columns; they are left alone
-        // and count as 1 in the inverses)
+        // (b) diagonal tile: LU with boosting, lane t < 16 holding row t;
+        // the reciprocal pivots go to UI[0][t] (0 for pivots past the block
+        // end, which only the last panel has: their rows and columns are zero)
         if (wave == 0) {
             T row[16];
 #pragma unroll
@@ -219,61 +217,50 @@ __global__ __launch_bounds__(kMfmaWaves * 64) void k_lu_mfma(LuArgs<T> a)
                         nboost += boosted ? 1 : 0;
                         if (piv == T(0)) a.status[1] = 1;
                     }
-                    const T l = row[t] * (T(1) / piv);
+                    const T rp = T(1) / piv;
+                    const T l = row[t] * rp;
                     const bool below = lane > t;
 #pragma unroll
                     for (int c = t + 1; c < 16; ++c)
                         row[c] = below ? fma(-l, lane_bcast(row[c], t), row[c]) : row[c];
                     row[t] = below ? l : (lane == t ? piv : row[t]);
+                    if (lane == t) UI[t] = rp;
+                } else if (lane == t) {
+                    UI[t] = T(0);
                 }
             }
             if (lane < 16)
 #pragma unroll
                 for (int c = 0; c < 16; ++c) PC[lane * 17 + c] = row[c];
-            // lane c (< 16): column c of U11^-1 (back substitution), then of
-            // L11^-1 (forward substitution, unit diagonal)
-            T x[16];
-#pragma unroll
-            for (int i = 15; i >= 0; --i) {
-                T s = (lane == i) ? T(1) : T(0);
-#pragma unroll
-                for (int j = i + 1; j < 16; ++j) s = fma(-lane_bcast(row[j], i), x[j], s);
-                x[i] = s / (i < nact ? lane_bcast(row[i], i) : T(1));
-            }
-            if (lane < 16)
-#pragma unroll
-                for (int i = 0; i < 16; ++i) UI[i * 17 + lane] = x[i];
-#pragma unroll
-            for (int i = 0; i < 16; ++i) {
-                T s = (lane == i) ? T(1) : T(0);
-                if (i < nact)
-#pragma unroll
-                    for (int j = 0; j < i; ++j) s = fma(-lane_bcast(row[j], i), x[j], s);
-                x[i] = s;
-            }
-            if (lane < 16)
-#pragma unroll
-                for (int i = 0; i < 16; ++i) LI[i * 17 + lane] = x[i];
         }
         __syncthreads();
 
-        // (c) L21 = A21 U11^-1 (tile rows 1..NTL-1), U12 = L11^-1 A12
-        for (int task = wave; task < 2 * (NTL - 1); task += NW) {
-            const bool isl = task < NTL - 1;
-            const int o = 1 + (isl ? task : task - (NTL - 1));
-            v4 d = {T(0), T(0), T(0), T(0)};
+        // (c) L21 rows solve x U11 = a (one thread per row), U12 columns solve
+        // L11 y = a (one thread per column)
+        for (int task = tid; task < 2 * (WR - 16); task += NT) {
+            T x[16];
+            if (task < WR - 16) {
+                T *pr = PC + (16 + task) * 17;
 #pragma unroll
-            for (int s = 0; s < 4; ++s) {
-                const T av = isl ? PC[(16 * o + lr) * 17 + 4 * s + lq] : LI[lr * 17 + 4 * s + lq];
-                const T bv = isl ? UI[(4 * s + lq) * 17 + lr] : PR[(4 * s + lq) * PRP + 16 * o + lr];
-                d = mfma16(av, bv, d);
-            }
-            if (isl) {
+                for (int t = 0; t < 16; ++t) {
+                    T v = pr[t];
 #pragma unroll
-                for (int r = 0; r < 4; ++r) PC[(16 * o + DL::row(lane, r)) * 17 + DL::col(lane, r)] = d[r];
+                    for (int q = 0; q < t; ++q) v = fma(-x[q], PC[q * 17 + t], v);
+                    x[t] = v * UI[t];
+                }
+#pragma unroll
+                for (int t = 0; t < 16; ++t) pr[t] = x[t];
             } else {
+                const int c = 16 + task - (WR - 16);
 #pragma unroll
-                for (int r = 0; r < 4; ++r) PR[DL::row(lane, r) * PRP + 16 * o + DL::col(lane, r)] = d[r];
+                for (int t = 0; t < 16; ++t) {
+                    T v = PR[t * PRP + c];
+#pragma unroll
+                    for (int q = 0; q < t; ++q) v = fma(-PC[t * 17 + q], x[q], v);
+                    x[t] = v;
+                }
+#pragma unroll
+                for (int t = 0; t < 16; ++t) PR[t * PRP + c] = x[t];
             }
         }
         __syncthreads();
@@ -298,14 +285,62 @@ __global__ __launch_bounds__(kMfmaWaves * 64) void k_lu_mfma(LuArgs<T> a)
 #pragma unroll
                 for (int b = 0; b < NTL; ++b) acc[ai][b] = mfma16(av[ai], bv[b], acc[ai][b]);
         }
+        // outputs of pivot j = j0 + t: column-form coefficient rows
+        //   Lc[j] = [1, l(j+m, j)],  Uc[j+m][m] = u(j, j+m),  Uc[j][0] = 1/u_jj
+        // (and the row forms Ur, Lr), or the UL corner
+        for (int t = wave; t < nact; t += NW) {
+            const int64_t j = j0 + t;
+            const T piv = PC[t * 17 + t];
+            for (int m = lane; m < CS; m += 64) {
+                const T lv = m == 0 ? T(1) : PC[(t + m) * 17 + t];
+                const T uo = (t + m < 16) ? PC[t * 17 + t + m] : PR[t * PRP + t + m];
+                const T uv = m == 0 ? T(1) / piv : uo;
+                const bool in = j + m < nb;
+                if (!ul) {
+                    a.Lc[(s0 + j) * CS + m] = lv;
+                    if (in) a.Uc[(s0 + j + m) * CS + m] = uv;
+                    if (a.Ur) a.Ur[(s0 + j) * CS + m] = in ? uv : T(0);
+                    if (a.Lr && in) a.Lr[(s0 + j + m) * CS + m] = lv;
+                } else if (a.corner && j >= nb - k && in) {
+                    const int64_t b0 = j - (nb - k);
+                    T *cn = a.corner + (int64_t)blk * k * k;
+                    if (m >= 1) cn[(b0 + m) * k + b0] = lv;
+                    cn[b0 * k + b0 + m] = m == 0 ? piv : uv;
+                }
+            }
+        }
         __builtin_amdgcn_s_waitcnt(0);          // this wave's stage copies have landed
         __syncthreads();
-        // (e) entering tiles into the slots of the retired tile row and column:
-        // tile (I, J) with max(I, J) = p + NTL; entry (gr, gc) (relative to j0)
-        // is stage row gr - gc + K + 1 (row 0, zero, when |gr - gc| > K),
-        // column max(gr, gc) - 16 NTL; zero past the block end.  The tile is
-        // written as the product I E (4 MFMAs from a zero accumulator), so the
-        // accumulators are only ever produced by MFMAs and stay in AGPRs.
+        // (e) the tiles entering the window: tile row p + NTL (columns
+        // p+1 .. p+NTL) into PR, tile column p + NTL (rows p+1 .. p+NTL-1) into
+        // PC.  Entry (gr, gc) (relative to j0) is stage row gr - gc + K + 1
+        // (row 0, zero, when |gr - gc| > K), column max(gr, gc) - 16 NTL; zero
+        // past the block end.
+        for (int e = tid; e < 16 * WR + 16 * (WR - 16); e += NT) {
+            int gr, gc;
+            T *dst;
+            if (e < 16 * WR) {
+                const int rr = e / WR, cc = e - rr * WR;
+                gr = 16 * NTL + rr;
+                gc = 16 + cc;
+                dst = PR + rr * PRP + cc;
+            } else {
+                const int f = e - 16 * WR;
+                const int rr = f >> 4, cc = f & 15;
+                gr = 16 + rr;
+                gc = 16 * NTL + cc;
+                dst = PC + rr * 17 + cc;
+            }
+            const int dl = gr - gc;
+            const int mx = max(gr, gc);
+            const int srow = (dl >= -k && dl <= k) ? dl + k + 1 : 0;
+            const double v = stage[srow * 16 + mx - 16 * NTL];
+            *dst = (j0 + mx < nb) ? (T)v : T(0);
+        }
+        __syncthreads();
+        // the owners put them into the slots of the retired tile row and
+        // column as the product I E (4 MFMAs from a zero accumulator), so the
+        // accumulators are only ever produced by MFMAs and stay in AGPRs
         {
             const v4 zero = {T(0), T(0), T(0), T(0)};
 #pragma unroll
@@ -317,17 +352,12 @@ __global__ __launch_bounds__(kMfmaWaves * 64) void k_lu_mfma(LuArgs<T> a)
                     for (int b = 0; b < NTL; ++b) {
                         const int co = off(b, ap);
                         if (ro == 0 || co == 0) {
-                            const int ti = ro == 0 ? NTL : ro, tj = co == 0 ? NTL : co;
                             v4 d = zero;
 #pragma unroll
                             for (int s = 0; s < 4; ++s) {
-                                // B operand: E[4s + lq][lr]; A operand: identity
-                                const int gr = 16 * ti + 4 * s + lq, gc = 16 * tj + lr;
-                                const int dl = gr - gc;
-                                const int mx = max(gr, gc);
-                                const int row = (dl >= -k && dl <= k) ? dl + k + 1 : 0;
-                                const double v = stage[row * 16 + mx - 16 * NTL];
-                                const T e = (j0 + mx < nb) ? (T)v : T(0);
+                                // B operand E[4s + lq][lr]; A operand identity
+                                const T e = ro == 0 ? PR[(4 * s + lq) * PRP + 16 * (co == 0 ? NTL - 1 : co - 1) + lr]
+                                                    : PC[(16 * (ro - 1) + 4 * s + lq) * 17 + lr];
                                 const T id = (lr == 4 * s + lq) ? T(1) : T(0);
                                 d = mfma16(id, e, d);
                             }
@@ -335,29 +365,6 @@ __global__ __launch_bounds__(kMfmaWaves * 64) void k_lu_mfma(LuArgs<T> a)
                         }
                     }
                 }
-            }
-        }
-        // outputs of pivot j = j0 + t: column-form coefficient rows
-        //   Lc[j] = [1, l(j+m, j)],  Uc[j+m][m] = u(j, j+m),  Uc[j][0] = 1/u_jj
-        // (and the row forms Ur, Lr), or the UL corner
-        for (int idx = tid; idx < nact * CS; idx += NT) {
-            const int t = idx / CS, m = idx - t * CS;
-            const int64_t j = j0 + t;
-            const T piv = PC[t * 17 + t];
-            const T lv = m == 0 ? T(1) : PC[(t + m) * 17 + t];
-            const T uo = (t + m < 16) ? PC[t * 17 + t + m] : PR[t * PRP + t + m];
-            const T uv = m == 0 ? T(1) / piv : uo;
-            const bool in = j + m < nb;
-            if (!ul) {
-                a.Lc[(s0 + j) * CS + m] = lv;
-                if (in) a.Uc[(s0 + j + m) * CS + m] = uv;
-                if (a.Ur) a.Ur[(s0 + j) * CS + m] = in ? uv : T(0);
-                if (a.Lr && in) a.Lr[(s0 + j + m) * CS + m] = lv;
-            } else if (a.corner && j >= nb - k && in) {
-                const int64_t b0 = j - (nb - k);
-                T *cn = a.corner + (int64_t)blk * k * k;
-                if (m >= 1) cn[(b0 + m) * k + b0] = lv;
-                cn[b0 * k + b0 + m] = m == 0 ? piv : uv;
             }
         }
         __syncthreads();
@@ -383,8 +390,10 @@ static hipError_t launch_lu_mfma_ntl(const LuArgs<T> &a, hipStream_t s)
 // The window needs 16 (NTL - 1) >= K; a larger NTL only adds zero tiles, so
 // a few window sizes cover every K.  Up to K = 208 (14 x 14 tiles) the window
 // fits the 512 registers per lane of a wave alone on its SIMD for FP32
-// factors; FP64 windows above K = 96 spill part of it to scratch.
-bool lu_mfma_supported(int k, bool) { return k >= 1 && k <= 208; }
+// factors.  FP64 windows take twice the registers: above K = 96 part of the
+// window spills to scratch, and the 14 x 14 window (K > 160) leaves too few
+// registers for the rest of the kernel, so FP64 stops at 11 x 11 tiles.
+bool lu_mfma_supported(int k, bool fp32) { return k >= 1 && k <= (fp32 ? 208 : 160); }
 
 template <typename T>
 hipError_t launch_lu_mfma(const LuArgs<T> &a, hipStream_t s)
@@ -399,7 +408,8 @@ hipError_t launch_lu_mfma(const LuArgs<T> &a, hipStream_t s)
     if (ntl <= 7) return launch_lu_mfma_ntl<T, 7>(a, s);
     if (ntl <= 9) return launch_lu_mfma_ntl<T, 9>(a, s);
     if (ntl <= 11) return launch_lu_mfma_ntl<T, 11>(a, s);
-    return launch_lu_mfma_ntl<T, 14>(a, s);
+    if constexpr (sizeof(T) == 4) return launch_lu_mfma_ntl<T, 14>(a, s);
+    return hipErrorInvalidValue;
 }
 
 template hipError_t launch_lu_mfma<float>(const LuArgs<float> &, hipStream_t);

@@ -90,7 +90,7 @@ __device__ void chain_states(const SweepArgs<T> &a, int blk, int nchb, T *sh)
 }
 
 template <typename T, int KR, int S, bool FWD, bool DIAG, int PH>
-__global__ __launch_bounds__(256) void k_sweep(SweepArgs<T> a)
+__global__ __launch_bounds__(256, 2) void k_sweep(SweepArgs<T> a)
 {
     static_assert(S == 32 || S == 64, "a chunk is one or half a 64-step block");
     static_assert(KR >= 2, "ring must cover 64 + K slots");
@@ -208,7 +208,7 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs<T> a)
         // Steps run in groups of G; the LDS operands of group g+1 (diagonal
         // factor, input, and the KR coefficients each lane pushes) are read while
         // the dependent chain of group g runs.
-        constexpr int G = (KR * sizeof(T) > 16) ? 4 : 8;
+        constexpr int G = 4;
         struct Grp {
             T d[G], vd[G], cf[G][KR];
         };
@@ -373,27 +373,40 @@ hipError_t launch_sweep<double>(const SweepArgs<double> &a, hipStream_t s)
 }
 
 // ------------------------------------------------------ transfer matrices
-// One wave per chunk that hands a state on.  Lane i runs the chunk's chain
-// with zero inputs from the incoming state e_i (pending sum 1 for the i-th
-// step of the chunk); its K pending sums after the last step form row i of
-// X(c).  p[m] holds the pending sum of the m-th step after the current one,
-// so one step is x = -p[0]*d, p[m-1] = p[m] + F[j][m]*x.  Coefficient rows
-// are loaded one per lane (coefficient m in lane m), eight rows ahead, and
-// broadcast with v_readlane.
-template <typename T, int KM, bool FWD, bool DIAG>
-__global__ __launch_bounds__(64) void k_sweep_xfer(XferArgs<T> a)
+// One workgroup of four waves per chunk that hands a state on (blockIdx.y
+// selects the coefficient array).  Wave w takes the w-th quarter of the
+// chunk's steps: lane i runs those steps with zero inputs from the incoming
+// state e_i (pending sum 1 for the i-th step), so its K pending sums at the
+// end form row i of the quarter's transfer X_w.  p[m] holds the pending sum
+// of the m-th step after the current one: one step is x = -p[0]*d,
+// p[m-1] = p[m] + F[j][m]*x.  Coefficient rows are loaded one per lane
+// (coefficient m in lane m), eight rows ahead, and broadcast with
+// v_readlane.  The chunk's transfer is the product X_0 X_1 X_2 X_3 (a state
+// s maps to s X), formed in LDS.
+template <typename T, int KM>
+__global__ __launch_bounds__(256) void k_sweep_xfer(XferArgs<T> a)
 {
     static_assert(KM <= 64, "coefficients are spread one per lane");
+    constexpr int EPT = (63 * 63 + 255) / 256;  // product elements per thread
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T *Xs = reinterpret_cast<T *>(smem_raw);   // [4][K][K]
     const int k = a.pt.k;
     const int CS = k + 1;
+    const int kk = k * k;
+    const int arr = blockIdx.y;
+    const T *F = a.F[arr];
+    const bool fwd = a.fwd[arr] != 0, diag = a.diag[arr] != 0;
     const int blk = (int)(blockIdx.x % a.pt.p), ch = (int)(blockIdx.x / a.pt.p);
     const int64_t s0 = a.pt.starts[blk];
     const int64_t nb = a.pt.starts[blk + 1] - s0;
     const int nchb = (int)((nb + a.clen - 1) / a.clen);
-    if (!(ch < nchb && (FWD ? ch + 1 < nchb : ch > 0))) return;
+    if (!(ch < nchb && (fwd ? ch + 1 < nchb : ch > 0))) return;
     const int64_t r0 = (int64_t)ch * a.clen, r1 = min(r0 + a.clen, nb);
     const int64_t nst = r1 - r0;
-    const int lane = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int64_t t_lo = nst * wave / 4, t_hi = nst * (wave + 1) / 4;
+
     T p[KM];
 #pragma unroll
     for (int m = 0; m < KM; ++m) p[m] = (m == lane) ? T(1) : T(0);
@@ -403,17 +416,17 @@ __global__ __launch_bounds__(64) void k_sweep_xfer(XferArgs<T> a)
 #pragma unroll
         for (int e = 0; e < D; ++e) {
             const int64_t t = t0 + e;
-            const int64_t row = FWD ? r0 + t : r1 - 1 - t;
-            dst[e] = (t < nst && lane <= k) ? a.F[(s0 + row) * CS + lane] : T(0);
+            const int64_t row = fwd ? r0 + t : r1 - 1 - t;
+            dst[e] = (t < t_hi && lane <= k) ? F[(s0 + row) * CS + lane] : T(0);
         }
     };
-    load(0, fr);
-    for (int64_t t0 = 0; t0 < nst; t0 += D) {
+    load(t_lo, fr);
+    for (int64_t t0 = t_lo; t0 < t_hi; t0 += D) {
         load(t0 + D, fn);
 #pragma unroll
         for (int e = 0; e < D; ++e) {
-            if (t0 + e < nst) {
-                const T d = DIAG ? lane_bcast(fr[e], 0) : T(1);
+            if (t0 + e < t_hi) {
+                const T d = diag ? lane_bcast(fr[e], 0) : T(1);
                 const T x = -p[0] * d;
 #pragma unroll
                 for (int m = 1; m < KM; ++m) p[m - 1] = fma(lane_bcast(fr[e], m), x, p[m]);
@@ -424,24 +437,58 @@ __global__ __launch_bounds__(64) void k_sweep_xfer(XferArgs<T> a)
         for (int e = 0; e < D; ++e) fr[e] = fn[e];
     }
     if (lane < k) {
-        T *out = a.xf + (((int64_t)blk * a.nch + ch) * k + lane) * k;
+        T *xw = Xs + wave * kk + lane * k;
 #pragma unroll
         for (int m = 0; m < KM; ++m)
-            if (m < k) out[m] = p[m];
+            if (m < k) xw[m] = p[m];
+    }
+    __syncthreads();
+    // Y = X_0 X_1 and Z = X_2 X_3, then X = Y Z
+    T y[EPT], z[EPT];
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) {
+        const int e = tid + 256 * q;
+        y[q] = z[q] = T(0);
+        if (e < kk) {
+            const int i = e / k, m = e - (e / k) * k;
+            T sy = T(0), sz = T(0);
+            for (int c = 0; c < k; ++c) {
+                sy = fma(Xs[i * k + c], Xs[kk + c * k + m], sy);
+                sz = fma(Xs[2 * kk + i * k + c], Xs[3 * kk + c * k + m], sz);
+            }
+            y[q] = sy;
+            z[q] = sz;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) {
+        const int e = tid + 256 * q;
+        if (e < kk) {
+            Xs[e] = y[q];
+            Xs[kk + e] = z[q];
+        }
+    }
+    __syncthreads();
+    T *out = a.xf[arr] + ((int64_t)blk * a.nch + ch) * kk;
+    for (int e = tid; e < kk; e += 256) {
+        const int i = e / k, m = e - i * k;
+        T sx = T(0);
+        for (int c = 0; c < k; ++c) sx = fma(Xs[i * k + c], Xs[kk + c * k + m], sx);
+        out[e] = sx;
     }
 }
 
 template <typename T, int KM>
 static hipError_t launch_xfer_km(const XferArgs<T> &a, hipStream_t s)
 {
-    const dim3 grid(a.pt.p * a.nch), blk(64);
-    if (a.fwd) {
-        if (a.diag) hipLaunchKernelGGL((k_sweep_xfer<T, KM, true, true>), grid, blk, 0, s, a);
-        else hipLaunchKernelGGL((k_sweep_xfer<T, KM, true, false>), grid, blk, 0, s, a);
-    } else {
-        if (a.diag) hipLaunchKernelGGL((k_sweep_xfer<T, KM, false, true>), grid, blk, 0, s, a);
-        else hipLaunchKernelGGL((k_sweep_xfer<T, KM, false, false>), grid, blk, 0, s, a);
-    }
+    const size_t lds = 4 * (size_t)a.pt.k * a.pt.k * sizeof(T);
+    if (lds > kMaxLds) return hipErrorInvalidValue;
+    auto kern = k_sweep_xfer<T, KM>;
+    hipError_t e = hipFuncSetAttribute((const void *)kern,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kern, dim3(a.pt.p * a.nch, a.narr), dim3(256), lds, s, a);
     return hipGetLastError();
 }
 
@@ -451,11 +498,16 @@ template <typename T>
 hipError_t launch_sweep_xfer(const XferArgs<T> &a, hipStream_t s)
 {
     const int k = a.pt.k;
-    if (!sweep_chunking_supported(k, sizeof(T) == 4) || a.nch < 2) return hipErrorInvalidValue;
+    if (!sweep_chunking_supported(k, sizeof(T) == 4) || a.nch < 2 || a.narr < 1 || a.narr > 4)
+        return hipErrorInvalidValue;
     // KM >= K + 1 slots: the K pending sums plus the zero that enters
+    if (k < 8) return launch_xfer_km<T, 8>(a, s);
     if (k < 16) return launch_xfer_km<T, 16>(a, s);
+    if (k < 24) return launch_xfer_km<T, 24>(a, s);
     if (k < 32) return launch_xfer_km<T, 32>(a, s);
+    if (k < 40) return launch_xfer_km<T, 40>(a, s);
     if (k < 48) return launch_xfer_km<T, 48>(a, s);
+    if (k < 56) return launch_xfer_km<T, 56>(a, s);
     return launch_xfer_km<T, 64>(a, s);
 }
 

@@ -15,9 +15,11 @@
 // each preconditioner application only needs small matrix-vector products.
 //
 // One 256-thread workgroup per interface; thread b owns column b of every
-// K x K right-hand side (K <= 255).  The working matrices and the staged
-// factor corner live in LDS when they fit (3 K^2 elements <= 128 KB), else in
-// global memory.  This step is O(P K^3) and runs once per factorization.
+// K x K right-hand side (K <= 255).  The working matrices and both staged
+// factor corners live in LDS when they fit (4 K^2 elements <= 128 KB); then
+// the V and W solves run side by side (threads 0..K-1 and K..2K-1).  Else
+// they live in global memory and the two solves run one after the other.
+// This step is O(P K^3) and runs once per factorization.
 #include "sap_internal.h"
 
 namespace sap {
@@ -50,8 +52,9 @@ __device__ __forceinline__ T rowdot(const T *M, const T *X, int k, int r, int b,
 
 // X, Y (right-hand-side columns, thread b owns column b) and F (the staged
 // K x K factor corner, later Rbar and its LU) are row-major K x K working
-// matrices: in LDS when 3*K*K elements fit, else in global memory (the V, W
-// and Rlu slots; the Rinv columns are then solved in place in Rinv).
+// matrices, with G (the second corner) in LDS mode: in LDS when 4*K*K
+// elements fit, else in global memory (the V, W and Rlu slots; the Rinv
+// columns are then solved in place in Rinv).
 template <typename T, bool LDS>
 __global__ __launch_bounds__(256) void k_tips(TipsArgs<T> a)
 {
@@ -80,7 +83,10 @@ __global__ __launch_bounds__(256) void k_tips(TipsArgs<T> a)
     // -> Y, and the bottom-right corner of LU(A_i) -> F, with
     // F[r][c] = l(base+r, base+c) for r > c (unit diagonal implied) and
     // F[r][c] = u(base+r, base+c) for r <= c; the stored diagonal of U is
-    // its reciprocal.
+    // its reciprocal.  In LDS mode the reversed corner of LU(J A_{i+1} J) goes
+    // to G at the same time: U'_tt (unit upper) above the diagonal, L'_tt on
+    // and below it.
+    T *G = LDS ? reinterpret_cast<T *>(smem_raw) + 3 * kk : nullptr;
     for (int64_t e = tid; e < kk; e += 256) {
         const int r = (int)(e / k), c = (int)(e % k);
         const int64_t br = s1 - k + r, bc = s1 + c;          // B: a[br][bc]
@@ -93,31 +99,50 @@ __global__ __launch_bounds__(256) void k_tips(TipsArgs<T> a)
         Y[e] = cv;
         F[e] = (r > c) ? a.Lc[(base + c) * CS + (r - c)]
                        : a.Uc[(base + c) * CS + (c - r)];    // c == r: 1/u_rr
+        if (LDS) G[e] = cn[(int64_t)(k - 1 - r) * k + (k - 1 - c)];
     }
     if (tid == 0) zero_sh = T(0);
     block_sync<LDS>();
 
     const int b = tid;
-    if (b < k) {
-        // V = U_bb^{-1} (L_bb^{-1} B_i), column b, in X
-        for (int r = 1; r < k; ++r) X[r * k + b] -= rowdot(F, X, k, r, b, 0, r);
-        for (int r = k - 1; r >= 0; --r)
-            X[r * k + b] = (X[r * k + b] - rowdot(F, X, k, r, b, r + 1, k)) * F[r * k + r];
-    }
-    block_sync<LDS>();
-    // corner of LU(J A_{i+1} J) -> F reversed: F[r][c] = cn[(k-1-r)*k + (k-1-c)],
-    // i.e. U'_tt (unit upper) above the diagonal and L'_tt on and below it
-    for (int64_t e = tid; e < kk; e += 256) {
-        const int r = (int)(e / k), c = (int)(e % k);
-        F[e] = cn[(int64_t)(k - 1 - r) * k + (k - 1 - c)];
-        V[e] = X[e];
-    }
-    block_sync<LDS>();
-    if (b < k) {
-        // W = L'_tt^{-1} (U'_tt^{-1} C_{i+1}), column b, in Y
-        for (int r = k - 2; r >= 0; --r) Y[r * k + b] -= rowdot(F, Y, k, r, b, r + 1, k);
-        for (int r = 0; r < k; ++r)
-            Y[r * k + b] = (Y[r * k + b] - rowdot(F, Y, k, r, b, 0, r)) / F[r * k + r];
+    if (LDS) {
+        // V (threads 0..K-1) and W (threads K..2K-1) at the same time
+        if (b < k) {
+            // V = U_bb^{-1} (L_bb^{-1} B_i), column b, in X
+            for (int r = 1; r < k; ++r) X[r * k + b] -= rowdot(F, X, k, r, b, 0, r);
+            for (int r = k - 1; r >= 0; --r)
+                X[r * k + b] = (X[r * k + b] - rowdot(F, X, k, r, b, r + 1, k)) * F[r * k + r];
+        } else if (b < 2 * k) {
+            // W = L'_tt^{-1} (U'_tt^{-1} C_{i+1}), column b - K, in Y
+            const int w = b - k;
+            for (int r = k - 2; r >= 0; --r) Y[r * k + w] -= rowdot(G, Y, k, r, w, r + 1, k);
+            for (int r = 0; r < k; ++r)
+                Y[r * k + w] = (Y[r * k + w] - rowdot(G, Y, k, r, w, 0, r)) / G[r * k + r];
+        }
+        block_sync<LDS>();
+        for (int64_t e = tid; e < kk; e += 256) V[e] = X[e];
+    } else {
+        if (b < k) {
+            // V = U_bb^{-1} (L_bb^{-1} B_i), column b, in X
+            for (int r = 1; r < k; ++r) X[r * k + b] -= rowdot(F, X, k, r, b, 0, r);
+            for (int r = k - 1; r >= 0; --r)
+                X[r * k + b] = (X[r * k + b] - rowdot(F, X, k, r, b, r + 1, k)) * F[r * k + r];
+        }
+        block_sync<LDS>();
+        // corner of LU(J A_{i+1} J) -> F reversed: F[r][c] = cn[(k-1-r)*k + (k-1-c)],
+        // i.e. U'_tt (unit upper) above the diagonal and L'_tt on and below it
+        for (int64_t e = tid; e < kk; e += 256) {
+            const int r = (int)(e / k), c = (int)(e % k);
+            F[e] = cn[(int64_t)(k - 1 - r) * k + (k - 1 - c)];
+            V[e] = X[e];
+        }
+        block_sync<LDS>();
+        if (b < k) {
+            // W = L'_tt^{-1} (U'_tt^{-1} C_{i+1}), column b, in Y
+            for (int r = k - 2; r >= 0; --r) Y[r * k + b] -= rowdot(F, Y, k, r, b, r + 1, k);
+            for (int r = 0; r < k; ++r)
+                Y[r * k + b] = (Y[r * k + b] - rowdot(F, Y, k, r, b, 0, r)) / F[r * k + r];
+        }
     }
     block_sync<LDS>();
     // Rbar = I - W V -> F and R (global)
@@ -195,8 +220,8 @@ template <typename T>
 hipError_t launch_tips(const TipsArgs<T> &a, hipStream_t s)
 {
     if (a.pt.p < 2) return hipSuccess;
-    const size_t lds = 3 * (size_t)a.pt.k * a.pt.k * sizeof(T);
-    if (lds <= 128 * 1024) {
+    const size_t lds = 4 * (size_t)a.pt.k * a.pt.k * sizeof(T);
+    if (lds <= 128 * 1024 && 2 * a.pt.k <= 256) {
         auto kern = k_tips<T, true>;
         hipError_t e = hipFuncSetAttribute((const void *)kern,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

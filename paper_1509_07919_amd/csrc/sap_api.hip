@@ -42,8 +42,8 @@ bool coupled_active(const sap_options &o) { return o.mode == SAP_COUPLED && o.p 
 
 // Chains per block for the triangular sweeps (chunked form, sap_internal.h).
 // Automatic choice: about as many sweep workgroups as the chip keeps resident
-// (the LDS staging of one workgroup allows two per CU for FP64 factors, four
-// for FP32, on 256 CUs), with at least 64 rows per chunk.
+// (two per CU on 256 CUs: one wave per SIMD each, two waves per SIMD), with
+// at least 64 rows per chunk.
 struct Chunking {
     int nch, clen;
 };
@@ -53,7 +53,7 @@ Chunking chunking_for(const sap_options &o)
     const bool fp32 = o.factor_prec == SAP_PREC_FP32;
     Chunking c{1, (int)maxnb};
     if (o.sweep_chunks == 1 || !sweep_chunking_supported(o.k, fp32)) return c;
-    int64_t want = o.sweep_chunks >= 2 ? o.sweep_chunks : (fp32 ? 1024 : 512) / o.p;
+    int64_t want = o.sweep_chunks >= 2 ? o.sweep_chunks : 512 / o.p;
     if (want < 2) return c;
     int64_t clen = (maxnb + want - 1) / want;
     if (clen < 64) clen = 64;
@@ -77,8 +77,8 @@ int validate(const sap_options *o)
     if (o->factor_prec != SAP_PREC_FP64 && o->factor_prec != SAP_PREC_FP32)
         return fail(SAP_ERR_INVALID, "factor_prec must be SAP_PREC_FP64 or SAP_PREC_FP32");
     if (o->sweep_chunks < 0) return fail(SAP_ERR_INVALID, "sweep_chunks must be >= 0");
-    if (o->factor_prec == SAP_PREC_FP64 && o->k > 208)
-        return fail(SAP_ERR_INVALID, "FP64 factors support K <= 208");
+    if (o->factor_prec == SAP_PREC_FP64 && o->k > 160)
+        return fail(SAP_ERR_INVALID, "FP64 factors support K <= 160");
     if (o->mode == SAP_COUPLED && o->p > 1 && o->n / o->p < 2 * (int64_t)o->k)
         return fail(SAP_ERR_INVALID, "coupled mode needs floor(N/P) >= 2K");
     if (std::isnan(o->boost_eps)) return fail(SAP_ERR_INVALID, "boost_eps is NaN");
@@ -158,6 +158,8 @@ struct sap_handle_ {
     const double *a_band;
     bool factored, starts_uploaded;
     hipEvent_t ev[5];        // factor start / after LU / end, solve start / end
+    hipStream_t side;        // second stream: transfer matrices beside the tips
+    hipEvent_t fork, join;
     float t_factor, t_lu, t_tips;
     // per-kernel timing (sap_profile): event pairs recorded around launches
     bool prof;
@@ -528,25 +530,33 @@ int factor_t(sap_handle h, const double *a_band, hipStream_t s)
         ProfScope ps(h, SAP_KERNEL_LU, s);
         HIP_TRY(launch_banded_lu<T>(lu, s));
     }
+    // the transfer matrices of the chunked sweeps (sap_internal.h) depend only
+    // on the factors: they run on the side stream beside the tips
+    const bool side = h->ck.nch >= 2 && h->coupled;
+    hipStream_t xs = side ? h->side : s;
+    if (side) {
+        HIP_TRY(hipEventRecord(h->fork, s));
+        HIP_TRY(hipStreamWaitEvent(h->side, h->fork, 0));
+    }
     if (h->ck.nch >= 2) {
-        // transfer matrices of the chunked sweeps (sap_internal.h)
-        HIP_TRY(hipMemsetAsync(h->ptr<unsigned>(h->L.ticket), 0, sizeof(unsigned) * h->opt.p, s));
+        HIP_TRY(hipMemsetAsync(h->ptr<unsigned>(h->L.ticket), 0, sizeof(unsigned) * h->opt.p, xs));
         struct Arr { T *F; size_t xf; int fwd, diag; };
         const Arr arrs[4] = {{lu.Lc, h->L.xLc, 1, 0}, {lu.Uc, h->L.xUc, 0, 1},
                              {lu.Ur, h->L.xUr, 1, 1}, {lu.Lr, h->L.xLr, 0, 0}};
+        XferArgs<T> xa{};
+        xa.pt = h->pt;
+        xa.nch = h->ck.nch;
+        xa.clen = h->ck.clen;
         for (const Arr &r : arrs) {
             if (!r.F) continue;
-            XferArgs<T> xa{};
-            xa.F = r.F;
-            xa.pt = h->pt;
-            xa.fwd = r.fwd;
-            xa.diag = r.diag;
-            xa.nch = h->ck.nch;
-            xa.clen = h->ck.clen;
-            xa.xf = h->ptr<T>(r.xf);
-            ProfScope ps(h, SAP_KERNEL_XFER, s);
-            HIP_TRY(launch_sweep_xfer<T>(xa, s));
+            xa.F[xa.narr] = r.F;
+            xa.xf[xa.narr] = h->ptr<T>(r.xf);
+            xa.fwd[xa.narr] = r.fwd;
+            xa.diag[xa.narr] = r.diag;
+            ++xa.narr;
         }
+        ProfScope ps(h, SAP_KERNEL_XFER, xs);
+        HIP_TRY(launch_sweep_xfer<T>(xa, xs));
     }
     HIP_TRY(hipEventRecord(h->ev[1], s));
     if (h->coupled) {
@@ -562,6 +572,10 @@ int factor_t(sap_handle h, const double *a_band, hipStream_t s)
         ta.status = lu.status;
         ProfScope ps(h, SAP_KERNEL_TIPS, s);
         HIP_TRY(launch_tips<T>(ta, s));
+    }
+    if (side) {
+        HIP_TRY(hipEventRecord(h->join, h->side));
+        HIP_TRY(hipStreamWaitEvent(s, h->join, 0));
     }
     return SAP_OK;
 }
@@ -618,6 +632,9 @@ int sap_create(const sap_options *opt, void *workspace, size_t ws_bytes, sap_han
         if (h->h_status) (void)hipHostFree(h->h_status);
         for (auto &e : h->ev)
             if (e) (void)hipEventDestroy(e);
+        if (h->fork) (void)hipEventDestroy(h->fork);
+        if (h->join) (void)hipEventDestroy(h->join);
+        if (h->side) (void)hipStreamDestroy(h->side);
         delete h;
         return fail(code, m);
     };
@@ -629,6 +646,10 @@ int sap_create(const sap_options *opt, void *workspace, size_t ws_bytes, sap_han
         return cleanup(SAP_ERR_HIP, "hipHostGetDevicePointer failed");
     for (auto &e : h->ev)
         if (hipEventCreate(&e) != hipSuccess) return cleanup(SAP_ERR_HIP, "hipEventCreate failed");
+    if (hipEventCreateWithFlags(&h->fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&h->join, hipEventDisableTiming) != hipSuccess ||
+        hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking) != hipSuccess)
+        return cleanup(SAP_ERR_HIP, "creating the side stream failed");
     // Sec. 3.1: first P_r = N - P*floor(N/P) blocks get floor(N/P) + 1 rows
     const int64_t q = n / p, pr = n - (int64_t)p * q;
     h->h_starts[0] = 0;
@@ -796,6 +817,12 @@ int sap_destroy(sap_handle h)
     (void)hipHostFree(h->h_status);
     for (auto &e : h->ev)
         if (e) (void)hipEventDestroy(e);
+    if (h->side) {
+        (void)hipStreamSynchronize(h->side);
+        (void)hipStreamDestroy(h->side);
+    }
+    if (h->fork) (void)hipEventDestroy(h->fork);
+    if (h->join) (void)hipEventDestroy(h->join);
     delete h;
     return SAP_OK;
 }

@@ -136,14 +136,16 @@ struct SweepArgs {
 template <typename T>
 hipError_t launch_sweep(const SweepArgs<T> &a, hipStream_t s);
 
-// Transfer matrices X(c) of every chunk that hands a state on (see above).
+// Transfer matrices X(c) of every chunk that hands a state on (see above),
+// for up to four coefficient arrays in one launch.
 template <typename T>
 struct XferArgs {
-    const T *F;
     Partition pt;
-    int fwd, diag;
     int nch, clen;
-    T *xf;
+    int narr;
+    const T *F[4];
+    T *xf[4];
+    int fwd[4], diag[4];
 };
 template <typename T>
 hipError_t launch_sweep_xfer(const XferArgs<T> &a, hipStream_t s);

@@ -47,7 +47,7 @@ def ws(lib, **kw):
     (dict(n=100, k=2, p=0), "P must be"),
     (dict(n=100, k=2, p=101), "P must be"),
     (dict(n=100, k=10, p=6, mode="coupled"), "floor(N/P) >= 2K"),
-    (dict(n=10000, k=209, p=4, factor_prec="fp64"), "FP64 factors"),
+    (dict(n=10000, k=161, p=4, factor_prec="fp64"), "FP64 factors"),
 ])
 def test_invalid_options(lib, kw, msg):
     rc, _, err = ws(lib, **kw)

@@ -103,8 +103,8 @@ def test_precond_parity(n, k, p, mode, prec):
 WIDE_CASES = [
     (4001, 64, 4, "fp32"), (4001, 64, 4, "fp64"), (5003, 96, 5, "fp64"),
     (5003, 100, 5, "fp32"), (6007, 127, 5, "fp64"), (6007, 128, 5, "fp64"),
-    (6007, 150, 7, "fp32"), (6400, 200, 8, "fp32"), (6400, 200, 8, "fp64"),
-    (6400, 208, 8, "fp64"), (7001, 255, 6, "fp32"),
+    (6007, 150, 7, "fp32"), (6400, 160, 8, "fp64"), (6400, 200, 8, "fp32"),
+    (6400, 208, 8, "fp32"), (7001, 255, 6, "fp32"),
 ]
 
 
