@@ -288,13 +288,17 @@ __global__ __launch_bounds__(NT) void k_banded_lu(LuArgs<T> a)
 // The same factorization, B pivots per panel.  The active window of the block
 // -- rows and columns j0 .. j0+K+B-1 -- is a (K+B) x (K+B) array in LDS,
 // double-buffered.  Per panel (three barriers):
-//   1. wave 0 factors the (K+B) x B panel in registers (one row per lane,
-//      pivot rows broadcast with v_readlane), with the same boosting rule;
-//   2. K threads form U12 = L11^{-1} A12 (B x K), one column each;
-//   3. all threads apply the rank-B Schur update A22 -= L21 U12 and write the
-//      result straight into the other buffer shifted by (B, B), so the window
-//      slides for free; the B rows and columns that enter are copied from the
-//      LDS stage, and the panel's L columns and U rows go to the output buffer.
+//   1. K threads form U12 = L11^{-1} A12 (B x K), one column each;
+//   2. all threads form the next panel's B columns of the next window (the
+//      rank-B Schur update A22 -= L21 U12 restricted to them, entering
+//      entries elsewhere);
+//   3. wave 0 factors that panel in registers (one row per lane, pivot rows
+//      broadcast with v_readlane, the same boosting rule) while the other
+//      waves apply the rest of the update, writing straight into the other
+//      buffer shifted by (B, B) so the window slides for free, copy the
+//      entering rows and columns from the LDS stage, and put the panel's L
+//      columns and U rows into the output buffer (look-ahead: the panel
+//      factorization is off the critical path).
 // Row r of block i appears at window row r - j0 for the LU; the UL runs the
 // same code on the reversed block.
 template <typename T, int B, int S, int NT, int RPL>
@@ -404,6 +408,74 @@ __global__ __launch_bounds__(NT) void k_banded_lu_blk(LuArgs<T> a)
     int nboost = 0;
 
     const int64_t npanel = (nb + B - 1) / B;
+    // factorization of one panel held in wave 0's registers: row lane + 64x,
+    // columns 0..B-1; the first nact_ columns are pivots
+    auto factor_panel = [&](T (&pv)[RPL][B], int nact_) {
+#pragma unroll
+        for (int t = 0; t < B; ++t) {
+            if (t < nact_) {
+                T praw = pv[0][t];
+                praw = lane_bcast(praw, t);
+                T piv = praw;
+                bool boosted = false;
+                if (do_boost && fabs((double)praw) < (double)tau) {
+                    piv = praw >= T(0) ? tau : -tau;
+                    boosted = true;
+                }
+                if (lane == 0) {
+                    nboost += boosted ? 1 : 0;
+                    if (piv == T(0)) a.status[1] = 1;
+                }
+                const T inv = T(1) / piv;
+                T urow[B];
+#pragma unroll
+                for (int c = t + 1; c < B; ++c) urow[c] = lane_bcast(pv[0][c], t);
+#pragma unroll
+                for (int x = 0; x < RPL; ++x) {
+                    const int rr = lane + 64 * x;
+                    if (rr > t) {
+                        const T l = pv[x][t] * inv;
+                        pv[x][t] = l;
+#pragma unroll
+                        for (int c = t + 1; c < B; ++c) pv[x][c] = fma(-l, urow[c], pv[x][c]);
+                    } else if (rr == t) {
+                        pv[x][t] = piv;
+                    }
+                }
+            }
+        }
+    };
+    // entry (r, c) of the next window with r >= K or c >= K: an untouched
+    // entry of A from the stage of chunk e0/S (global (j1+r, j1+c), entering
+    // index j0 + max(r, c) - K, delta = r - c)
+    auto entering = [&](const T *stg, int64_t j0_, int64_t e0_, int r, int c) -> T {
+        const int delta = r - c;
+        const int so = (int)((j0_ + max(r, c) - k) - (e0_ / S) * S);      // in [0, S)
+        const int qrow = min(max(delta + k, -1), W2);
+        return stg[qrow * S + so];
+    };
+    if (wave == 0) {                                  // panel 0
+        T pv[RPL][B];
+#pragma unroll
+        for (int x = 0; x < RPL; ++x) {
+            const int rr = lane + 64 * x;
+#pragma unroll
+            for (int t = 0; t < B; ++t) pv[x][t] = rr < KB ? win0[rr * WP + t] : T(0);
+        }
+        factor_panel(pv, (int)min((int64_t)B, nb));
+#pragma unroll
+        for (int x = 0; x < RPL; ++x) {
+            const int rr = lane + 64 * x;
+            if (rr < KB)
+#pragma unroll
+                for (int t = 0; t < B; ++t) win0[rr * WP + t] = pv[x][t];
+        }
+    }
+    __syncthreads();
+    // Loop invariant: the panel columns 0..B-1 of the current window are
+    // factored.  During the Schur update of panel p (waves 1..), wave 0 forms
+    // the next panel's columns of the next window first and factors them
+    // (look-ahead), so the panel factorization overlaps the update.
     for (int64_t pnl = 0; pnl < npanel; ++pnl) {
         const int64_t j0 = pnl * B;
         T *W = win0 + (pnl & 1) * KB * WP;            // current window
@@ -414,58 +486,7 @@ __global__ __launch_bounds__(NT) void k_banded_lu_blk(LuArgs<T> a)
             if (j0 > 0) flush(j0 - S);
         }
         const int nact = (int)min((int64_t)B, nb - j0);   // pivots in this panel
-
-        // 1. panel factorization by wave 0
-        if (wave == 0) {
-            T pv[RPL][B];
-#pragma unroll
-            for (int x = 0; x < RPL; ++x) {
-                const int rr = lane + 64 * x;
-#pragma unroll
-                for (int t = 0; t < B; ++t) pv[x][t] = rr < KB ? W[rr * WP + t] : T(0);
-            }
-#pragma unroll
-            for (int t = 0; t < B; ++t) {
-                if (t < nact) {
-                    T praw = pv[0][t];
-                    praw = lane_bcast(praw, t);
-                    T piv = praw;
-                    bool boosted = false;
-                    if (do_boost && fabs((double)praw) < (double)tau) {
-                        piv = praw >= T(0) ? tau : -tau;
-                        boosted = true;
-                    }
-                    if (lane == 0) {
-                        nboost += boosted ? 1 : 0;
-                        if (piv == T(0)) a.status[1] = 1;
-                    }
-                    const T inv = T(1) / piv;
-                    T urow[B];
-#pragma unroll
-                    for (int c = t + 1; c < B; ++c) urow[c] = lane_bcast(pv[0][c], t);
-#pragma unroll
-                    for (int x = 0; x < RPL; ++x) {
-                        const int rr = lane + 64 * x;
-                        if (rr > t) {
-                            const T l = pv[x][t] * inv;
-                            pv[x][t] = l;
-#pragma unroll
-                            for (int c = t + 1; c < B; ++c) pv[x][c] = fma(-l, urow[c], pv[x][c]);
-                        } else if (rr == t) {
-                            pv[x][t] = piv;
-                        }
-                    }
-                }
-            }
-#pragma unroll
-            for (int x = 0; x < RPL; ++x) {
-                const int rr = lane + 64 * x;
-                if (rr < KB)
-#pragma unroll
-                    for (int t = 0; t < B; ++t) W[rr * WP + t] = pv[x][t];
-            }
-        }
-        __syncthreads();
+        const T *stg = stage + (((e0) / S) & 1) * stage_sz + S;
 
         // 2. U12 = L11^{-1} A12 (rows 0..B-1, window columns B..KB-1)
         for (int c = B + tid; c < KB; c += NT) {
@@ -482,15 +503,52 @@ __global__ __launch_bounds__(NT) void k_banded_lu_blk(LuArgs<T> a)
         }
         __syncthreads();
 
-        // 3a. Schur update into the next window: Wn[r-B][c-B] = W[r][c] - L21 U12
-        {
-            const int cols = KB - B;                  // = K
-            for (int cb = lane; cb < cols; cb += 64) {
+        // 3L. the next panel's columns 0..B-1 of the next window, by all
+        // threads: Schur update where r, c < K, entering entries elsewhere
+        if (pnl + 1 < npanel) {
+            for (int idx = tid; idx < KB * B; idx += NT) {
+                const int rr = idx / B, cb = idx - rr * B;
+                T v;
+                if (rr < k && cb < k) {
+                    v = W[(B + rr) * WP + B + cb];
+#pragma unroll
+                    for (int t = 0; t < B; ++t) v = fma(-W[(B + rr) * WP + t], W[t * WP + B + cb], v);
+                } else {
+                    v = entering(stg, j0, e0, rr, cb);
+                }
+                Wn[rr * WP + cb] = v;
+            }
+        }
+        __syncthreads();
+        if (wave == 0) {
+            // factorization of the next panel, in registers
+            if (pnl + 1 < npanel) {
+                T pv[RPL][B];
+#pragma unroll
+                for (int x = 0; x < RPL; ++x) {
+                    const int rr = lane + 64 * x;
+#pragma unroll
+                    for (int t = 0; t < B; ++t) pv[x][t] = rr < KB ? Wn[rr * WP + t] : T(0);
+                }
+                factor_panel(pv, (int)min((int64_t)B, nb - j0 - B));
+#pragma unroll
+                for (int x = 0; x < RPL; ++x) {
+                    const int rr = lane + 64 * x;
+                    if (rr < KB)
+#pragma unroll
+                        for (int t = 0; t < B; ++t) Wn[rr * WP + t] = pv[x][t];
+                }
+            }
+        } else {
+            const int wr = wave - 1, NR = NW - 1, tr = tid - 64, NTR = NT - 64;
+            // 3a. Schur update of the other columns into the next window:
+            // Wn[r-B][c-B] = W[r][c] - L21 U12 for window columns c >= 2B
+            for (int cb = B + lane; cb < k; cb += 64) {
                 const int c = B + cb;
                 T uc[B];
 #pragma unroll
                 for (int t = 0; t < B; ++t) uc[t] = W[t * WP + c];
-                for (int rb = wave; rb < cols; rb += NW) {
+                for (int rb = wr; rb < k; rb += NR) {
                     const int r = B + rb;
                     T v = W[r * WP + c];
 #pragma unroll
@@ -498,39 +556,36 @@ __global__ __launch_bounds__(NT) void k_banded_lu_blk(LuArgs<T> a)
                     Wn[rb * WP + cb] = v;
                 }
             }
-        }
-        // 3b. entering rows/cols of the next window (window rows or columns
-        // >= K), from the stage: global (j1+r, j1+c), m = j1 + max(r, c),
-        // delta = r - c; entering index of m is m - KB = j0 + max(r, c) - K
-        {
-            const T *stg = stage + (((e0) / S) & 1) * stage_sz + S;
-            const int nent = KB * KB - k * k;          // entries with r >= K or c >= K
-            for (int idx = tid; idx < nent; idx += NT) {
-                int r, c;
-                if (idx < B * KB) { r = k + idx / KB; c = idx % KB; }          // bottom B rows
-                else { const int q2 = idx - B * KB; r = q2 / B; c = k + q2 % B; } // right B cols, r < K
-                const int delta = r - c;
-                const int so = (int)((j0 + max(r, c) - k) - (e0 / S) * S);      // in [0, S)
-                const int qrow = min(max(delta + k, -1), W2);
-                Wn[r * WP + c] = stg[qrow * S + so];
+            // 3b. entering entries of the next window outside its first B
+            // columns: rows K..KB-1 x columns B..KB-1, and rows 0..K-1 x
+            // columns max(K, B)..KB-1
+            {
+                const int cb0 = max(k, B);
+                const int na = B * k, nbb = k * (KB - cb0);
+                for (int idx = tr; idx < na + nbb; idx += NTR) {
+                    int r, c;
+                    if (idx < na) { r = k + idx / k; c = B + idx % k; }
+                    else { const int q2 = idx - na; r = q2 / (KB - cb0); c = cb0 + q2 % (KB - cb0); }
+                    Wn[r * WP + c] = entering(stg, j0, e0, r, c);
+                }
             }
-        }
-        // 3c. outputs of the panel's pivots: L column and U row of j = j0+t
-        for (int idx = tid; idx < nact * CS; idx += NT) {
-            const int t = idx / CS, m = idx - t * CS;
-            const int64_t j = j0 + t;
-            const T piv = W[t * WP + t];
-            const T lv = m == 0 ? T(1) : W[(t + m) * WP + t];
-            const T uv = m == 0 ? T(1) / piv : W[t * WP + t + m];
-            if (!ul) {
-                T *ob = obuf + (int)(j % S) * 2 * CS;
-                ob[m] = lv;
-                ob[CS + m] = uv;
-            } else if (a.corner && j >= nb - k && j + m < nb) {
-                const int64_t b0 = j - (nb - k);
-                T *cn = a.corner + (int64_t)blk * k * k;
-                if (m >= 1) cn[(b0 + m) * k + b0] = lv;
-                cn[b0 * k + b0 + m] = m == 0 ? piv : uv;
+            // 3c. outputs of the panel's pivots: L column and U row of j = j0+t
+            for (int idx = tr; idx < nact * CS; idx += NTR) {
+                const int t = idx / CS, m = idx - t * CS;
+                const int64_t j = j0 + t;
+                const T piv = W[t * WP + t];
+                const T lv = m == 0 ? T(1) : W[(t + m) * WP + t];
+                const T uv = m == 0 ? T(1) / piv : W[t * WP + t + m];
+                if (!ul) {
+                    T *ob = obuf + (int)(j % S) * 2 * CS;
+                    ob[m] = lv;
+                    ob[CS + m] = uv;
+                } else if (a.corner && j >= nb - k && j + m < nb) {
+                    const int64_t b0 = j - (nb - k);
+                    T *cn = a.corner + (int64_t)blk * k * k;
+                    if (m >= 1) cn[(b0 + m) * k + b0] = lv;
+                    cn[b0 * k + b0 + m] = m == 0 ? piv : uv;
+                }
             }
         }
         if ((e0 % S) == 0) prefetch(e0 / S + 1);
