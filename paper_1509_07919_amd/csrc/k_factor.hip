@@ -629,12 +629,11 @@ template <>
 hipError_t launch_banded_lu<double>(const LuArgs<double> &a, hipStream_t s)
 {
     const int k = a.pt.k;
-    // blocked kernel: panel width B with K + B <= 64 (one panel row per lane)
-    // when possible, else two rows per lane
-    if (k + 16 <= 64) return launch_lu_blk<double, 16, 32, 512, 1>(a, s);
-    if (k + 14 <= 64) return launch_lu_blk<double, 14, 28, 512, 1>(a, s);
-    if (k + 12 <= 64) return launch_lu_blk<double, 12, 24, 512, 1>(a, s);
+    // blocked kernel: panel width 8 (the fastest measured at K = 10..50), or 4,
+    // with K + B <= 64 (one panel row per lane)
     if (k + 8 <= 64) return launch_lu_blk<double, 8, 32, 512, 1>(a, s);
+    if (k + 4 <= 64) return launch_lu_blk<double, 4, 32, 512, 1>(a, s);
+    if (k < 64 && lu_mfma_supported(k, false)) return launch_lu_mfma<double>(a, s);
     // matrix-core kernel where its register window fits without spilling
     // (K <= 96), the register ring up to K = 127, then the matrix-core kernel
     // again (its larger windows spill part of the registers)
@@ -651,12 +650,11 @@ template <>
 hipError_t launch_banded_lu<float>(const LuArgs<float> &a, hipStream_t s)
 {
     const int k = a.pt.k;
-    // blocked kernel: panel width B with K + B <= 64 (one panel row per lane)
-    // when possible, else two rows per lane
-    if (k + 16 <= 64) return launch_lu_blk<float, 16, 32, 512, 1>(a, s);
-    if (k + 14 <= 64) return launch_lu_blk<float, 14, 28, 512, 1>(a, s);
-    if (k + 12 <= 64) return launch_lu_blk<float, 12, 24, 512, 1>(a, s);
+    // blocked kernel: panel width 8 (the fastest measured at K = 10..50), or 4,
+    // with K + B <= 64 (one panel row per lane)
     if (k + 8 <= 64) return launch_lu_blk<float, 8, 32, 512, 1>(a, s);
+    if (k + 4 <= 64) return launch_lu_blk<float, 4, 32, 512, 1>(a, s);
+    if (k < 64 && lu_mfma_supported(k, true)) return launch_lu_mfma<float>(a, s);
     if (k >= 64 && lu_mfma_supported(k, true)) return launch_lu_mfma<float>(a, s);
     if (k < 16) return launch_lu_cfg<float, 16, 16, 256>(a, s);
     if (k < 32) return launch_lu_cfg<float, 32, 32, 256>(a, s);

@@ -55,7 +55,9 @@ __device__ void chain_states(const SweepArgs<T> &a, int blk, int nchb, T *sh)
         cur[tid] = v;
         a.st[(base + c0 + dir) * k + tid] = v;
     }
-    T xr[16], xn[16];
+    // the transfer matrices of NG links are loaded at once, so their
+    // latencies overlap; the links are then chained one after the other
+    constexpr int NG = sizeof(T) == 8 ? 2 : 4;
     auto load_x = [&](int c, T *dst) {
         const T *x = a.xf + (base + c) * k * k;
 #pragma unroll
@@ -64,28 +66,37 @@ __device__ void chain_states(const SweepArgs<T> &a, int blk, int nchb, T *sh)
             dst[e] = (i < k && lane < k) ? x[i * k + lane] : T(0);
         }
     };
-    if (nlink > 0) load_x(c0 + dir, xr);
     __syncthreads();
-    for (int l = 0; l < nlink; ++l) {
-        const int c = c0 + dir * (1 + l);           // chunk of this link
-        if (l + 1 < nlink) load_x(c + dir, xn);
-        const T qm = (wave == 0 && lane < k) ? a.q[(base + c) * k + lane] : T(0);
-        T s0 = T(0), s1 = T(0);
+    for (int g = 0; g < nlink; g += NG) {
+        T xg[NG][16], qg[NG];
 #pragma unroll
-        for (int e = 0; e < 16; e += 2) {
-            s0 = fma(xr[e], cur[16 * wave + e], s0);
-            s1 = fma(xr[e + 1], cur[16 * wave + e + 1], s1);
+        for (int j = 0; j < NG; ++j) {
+            const int c = c0 + dir * (1 + g + j);
+            if (g + j < nlink) {
+                load_x(c, xg[j]);
+                qg[j] = (wave == 0 && lane < k) ? a.q[(base + c) * k + lane] : T(0);
+            }
         }
-        part[wave * 64 + lane] = s0 + s1;
-        __syncthreads();
-        if (wave == 0) {
-            const T v = qm + ((part[lane] + part[64 + lane]) + (part[128 + lane] + part[192 + lane]));
-            cur[lane] = lane < k ? v : T(0);
-            if (lane < k) a.st[(base + c + dir) * k + lane] = v;
-        }
-        __syncthreads();
 #pragma unroll
-        for (int e = 0; e < 16; ++e) xr[e] = xn[e];
+        for (int j = 0; j < NG; ++j) {
+            if (g + j < nlink) {
+                const int c = c0 + dir * (1 + g + j);       // chunk of this link
+                T s0 = T(0), s1 = T(0);
+#pragma unroll
+                for (int e = 0; e < 16; e += 2) {
+                    s0 = fma(xg[j][e], cur[16 * wave + e], s0);
+                    s1 = fma(xg[j][e + 1], cur[16 * wave + e + 1], s1);
+                }
+                part[wave * 64 + lane] = s0 + s1;
+                __syncthreads();
+                if (wave == 0) {
+                    const T v = qg[j] + ((part[lane] + part[64 + lane]) + (part[128 + lane] + part[192 + lane]));
+                    cur[lane] = lane < k ? v : T(0);
+                    if (lane < k) a.st[(base + c + dir) * k + lane] = v;
+                }
+                __syncthreads();
+            }
+        }
     }
 }
 
