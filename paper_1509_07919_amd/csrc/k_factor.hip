@@ -102,6 +102,7 @@ __global__ __launch_bounds__(NT) void k_banded_lu(LuArgs<T> a)
     const int sc = tid % WC;
     const int rs = tid / WC;
     const int CS = k + 1;
+    const int CP = coef_pitch(k, (int)sizeof(T));   // row pitch in HBM
     const int W2 = 2 * k + 1;
     const int stage_sz = (W2 + 2) * S;
 
@@ -117,8 +118,8 @@ __global__ __launch_bounds__(NT) void k_banded_lu(LuArgs<T> a)
         for (int idx = tid; idx < k * CS; idx += NT) {
             const int c = idx / CS, m = idx % CS;       // column c < K, slot m
             if (c < nb && m > c) {
-                a.Uc[(s0 + c) * CS + m] = T(0);
-                if (a.Lr) a.Lr[(s0 + c) * CS + m] = T(0);
+                a.Uc[(s0 + c) * CP + m] = T(0);
+                if (a.Lr) a.Lr[(s0 + c) * CP + m] = T(0);
             }
         }
     }
@@ -176,10 +177,10 @@ __global__ __launch_bounds__(NT) void k_banded_lu(LuArgs<T> a)
             const T lv = obuf[jj * 2 * CS + m];
             const T uv = obuf[jj * 2 * CS + CS + m];
             const bool in = j + m < nb;
-            a.Lc[(s0 + j) * CS + m] = lv;
-            if (in) a.Uc[(s0 + j + m) * CS + m] = uv;
-            if (a.Ur) a.Ur[(s0 + j) * CS + m] = in ? uv : T(0);
-            if (a.Lr && in) a.Lr[(s0 + j + m) * CS + m] = lv;
+            a.Lc[(s0 + j) * CP + m] = lv;
+            if (in) a.Uc[(s0 + j + m) * CP + m] = uv;
+            if (a.Ur) a.Ur[(s0 + j) * CP + m] = in ? uv : T(0);
+            if (a.Lr && in) a.Lr[(s0 + j + m) * CP + m] = lv;
         }
     };
     prefetch(0);
@@ -320,6 +321,7 @@ __global__ __launch_bounds__(NT) void k_banded_lu_blk(LuArgs<T> a)
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int CS = k + 1;
+    const int CP = coef_pitch(k, (int)sizeof(T));   // row pitch in HBM
     const int KB = k + B;                       // window size
     const int WP = KB + 1;                      // LDS pitch (odd: no bank conflicts on columns)
     const int W2 = 2 * k + 1;
@@ -338,8 +340,8 @@ __global__ __launch_bounds__(NT) void k_banded_lu_blk(LuArgs<T> a)
         for (int idx = tid; idx < k * CS; idx += NT) {
             const int c = idx / CS, m = idx % CS;
             if (c < nb && m > c) {
-                a.Uc[(s0 + c) * CS + m] = T(0);
-                if (a.Lr) a.Lr[(s0 + c) * CS + m] = T(0);
+                a.Uc[(s0 + c) * CP + m] = T(0);
+                if (a.Lr) a.Lr[(s0 + c) * CP + m] = T(0);
             }
         }
     }
@@ -393,10 +395,10 @@ __global__ __launch_bounds__(NT) void k_banded_lu_blk(LuArgs<T> a)
             const T lv = obuf[jj * 2 * CS + m];
             const T uv = obuf[jj * 2 * CS + CS + m];
             const bool in = j + m < nb;
-            a.Lc[(s0 + j) * CS + m] = lv;
-            if (in) a.Uc[(s0 + j + m) * CS + m] = uv;
-            if (a.Ur) a.Ur[(s0 + j) * CS + m] = in ? uv : T(0);
-            if (a.Lr && in) a.Lr[(s0 + j + m) * CS + m] = lv;
+            a.Lc[(s0 + j) * CP + m] = lv;
+            if (in) a.Uc[(s0 + j + m) * CP + m] = uv;
+            if (a.Ur) a.Ur[(s0 + j) * CP + m] = in ? uv : T(0);
+            if (a.Lr && in) a.Lr[(s0 + j + m) * CP + m] = lv;
         }
     };
     prefetch(0);

@@ -96,6 +96,7 @@ __global__ __launch_bounds__(kMfmaWaves * 64) void k_lu_mfma(LuArgs<T> a)
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int lr = lane & 15, lq = lane >> 4;
     const int CS = k + 1;
+    const int CP = coef_pitch(k, (int)sizeof(T));   // row pitch in HBM
     const int W2 = 2 * k + 1;
 
     double *stage = reinterpret_cast<double *>(smem_raw);
@@ -113,8 +114,8 @@ __global__ __launch_bounds__(kMfmaWaves * 64) void k_lu_mfma(LuArgs<T> a)
         for (int idx = tid; idx < k * CS; idx += NT) {
             const int c = idx / CS, m = idx % CS;
             if (c < nb && m > c) {
-                a.Uc[(s0 + c) * CS + m] = T(0);
-                if (a.Lr) a.Lr[(s0 + c) * CS + m] = T(0);
+                a.Uc[(s0 + c) * CP + m] = T(0);
+                if (a.Lr) a.Lr[(s0 + c) * CP + m] = T(0);
             }
         }
     }
@@ -297,10 +298,10 @@ __global__ __launch_bounds__(kMfmaWaves * 64) void k_lu_mfma(LuArgs<T> a)
                 const T uv = m == 0 ? T(1) / piv : uo;
                 const bool in = j + m < nb;
                 if (!ul) {
-                    a.Lc[(s0 + j) * CS + m] = lv;
-                    if (in) a.Uc[(s0 + j + m) * CS + m] = uv;
-                    if (a.Ur) a.Ur[(s0 + j) * CS + m] = in ? uv : T(0);
-                    if (a.Lr && in) a.Lr[(s0 + j + m) * CS + m] = lv;
+                    a.Lc[(s0 + j) * CP + m] = lv;
+                    if (in) a.Uc[(s0 + j + m) * CP + m] = uv;
+                    if (a.Ur) a.Ur[(s0 + j) * CP + m] = in ? uv : T(0);
+                    if (a.Lr && in) a.Lr[(s0 + j + m) * CP + m] = lv;
                 } else if (a.corner && j >= nb - k && in) {
                     const int64_t b0 = j - (nb - k);
                     T *cn = a.corner + (int64_t)blk * k * k;

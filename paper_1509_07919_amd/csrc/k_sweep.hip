@@ -10,17 +10,21 @@
 // L (forward, unit), U (backward), U^T (forward) and L^T (backward) differ
 // only in the array and the direction.
 //
-// MI355X design.  One workgroup per block: wave 0 runs the dependent chain,
-// waves 1-3 stream the coefficient rows and the input vector of the next
-// chunk of S steps from HBM into double-buffered LDS (a contiguous S*(K+1)
-// run per chunk).  The pending sums acc_{j+1..j+K} live in wave 0's VGPRs:
-// register s, lane l holds the step 64*s + l counted from the start of the
-// current 64-step block; KR = 1 + ceil(K/64) registers cover the reach of
-// step 63 of the block (63 + K), and the registers shift down by one every
-// 64 steps, so register indices stay static for any K <= 255.
-// Per step: one FMA for x_j in lane u, a v_readlane broadcast (lane index in
-// an SGPR), and one FMA per register in every lane.  Outputs are gathered in a register and
-// written 64 at a time, coalesced.
+// MI355X design.  One workgroup per block (or per row chunk of a block, see
+// below): wave 0 runs the dependent chain, waves 1-3 stage the coefficient
+// rows and the inputs of the coming chunks of 32 steps in LDS.  A chunk's
+// rows are one contiguous, 16-byte aligned run in HBM (row pitch CP), so it
+// is copied with 16-byte global_load_lds, 1 KiB per instruction, into one of
+// 2-4 LDS buffers (as many as fit two workgroups per CU); each loader wave
+// owns every third chunk and waits only for its own copies.  The pending sums
+// acc_{j+1..j+K} live in wave 0's VGPRs: register s, lane l holds the step
+// 64*s + l counted from the start of the current 64-step block; KR = 1 +
+// ceil(K/64) registers cover the reach of step 63 of the block (63 + K), and
+// the registers shift down by one every 64 steps, so register indices stay
+// static for any K <= 255.
+// Per step: one FMA for x_j (lane u holds the result), a v_readlane
+// broadcast (lane index in an SGPR), and one FMA per register in every lane.
+// Outputs are gathered in a register and written 64 at a time, coalesced.
 //
 // Chunked form (sap_internal.h): the same chain runs over one row chunk per
 // workgroup, so a block's sweep has nch chains in flight instead of one.  The
@@ -100,21 +104,29 @@ __device__ void chain_states(const SweepArgs<T> &a, int blk, int nchb, T *sh)
     }
 }
 
-template <typename T, int KR, int S, bool FWD, bool DIAG, int PH>
-__global__ __launch_bounds__(256, 2) void k_sweep(SweepArgs<T> a)
+// Rows of one staged chunk, and the LDS of a sweep workgroup: nbuf staging
+// buffers of S coefficient rows (pitch CP, the HBM layout) and nbuf buffers
+// of S prescaled inputs v*d.
+constexpr int kSweepRows = 32;
+template <typename T>
+static size_t sweep_lds_bytes(int cp, int nbuf)
 {
-    static_assert(S == 32 || S == 64, "a chunk is one or half a 64-step block");
+    const size_t b = ((size_t)nbuf * kSweepRows * cp + (size_t)nbuf * kSweepRows) * sizeof(T);
+    return b > 320 * sizeof(T) ? b : 320 * sizeof(T);   // chain_states scratch
+}
+
+template <typename T, int KR, bool FWD, bool DIAG, int PH>
+__global__ __launch_bounds__(256, 2) void k_sweep(SweepArgs<T> a, int nbuf)
+{
+    constexpr int S = kSweepRows;
+    static_assert(S == 32, "a chunk is half a 64-step block");
     static_assert(KR >= 2, "ring must cover 64 + K slots");
-    // LDS row pitch: slots 0..K hold a coefficient row, slots K+1..PITCH-1
-    // are zero (at least 8 of them), so a clamped offset needs no mask
-    constexpr int PITCH = 64 * (KR - 1) + 8;
-
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    T *cst = reinterpret_cast<T *>(smem_raw);         // [2][S][PITCH]
-    T *vst = cst + 2 * S * PITCH;                     // [2][S]
-
     const int k = a.pt.k;
-    const int CS = k + 1;
+    const int CP = coef_pitch(k, (int)sizeof(T));
+    T *stage = reinterpret_cast<T *>(smem_raw);       // [nbuf][S][CP]
+    T *vst = stage + (size_t)nbuf * S * CP;           // [nbuf][S]
+
     const int blk = PH == SWEEP_WHOLE ? (int)blockIdx.x : (int)(blockIdx.x % a.pt.p);
     const int ch = PH == SWEEP_WHOLE ? 0 : (int)(blockIdx.x / a.pt.p);
     const int64_t s0 = a.pt.starts[blk];
@@ -133,97 +145,95 @@ __global__ __launch_bounds__(256, 2) void k_sweep(SweepArgs<T> a)
     if (PH == SWEEP_FROM_STATE && ch >= nchb) return;      // empty chunk
     // the zero-state pass has nothing to run for the last chunk of a sweep,
     // but its workgroup still takes part in the block's ticket
-    const int64_t nchunks = (PH == SWEEP_ZERO_STATE && !passes) ? 0 : (nst + S - 1) / S;
+    const int nchunks = (PH == SWEEP_ZERO_STATE && !passes) ? 0 : (int)((nst + S - 1) / S);
+    // chunks staged ahead of the one being swept (nbuf is 2..4)
+    const int depth = nbuf - 1;
     const T *dtop = (a.dtop && blk > 0) ? a.dtop + (int64_t)blk * k : nullptr;
     const T *dbot = (a.dbot && blk < a.pt.p - 1) ? a.dbot + (int64_t)blk * k : nullptr;
 
-    // slots K+1 .. PITCH-1 of every staged row stay zero: the copies below
-    // write slots 0..K only
-    for (int idx = tid; idx < 2 * S * (PITCH - CS); idx += 256) {
-        const int row = idx / (PITCH - CS), m = CS + idx % (PITCH - CS);
-        cst[row * PITCH + m] = T(0);
-    }
-
-    // row of the block handled at step t
+    // row of the block handled at step t, and the staged row of step uc of a
+    // chunk (a backward chunk is staged in row order, so its steps run from
+    // the last staged row up)
     auto row_of = [&](int64_t t) -> int64_t { return FWD ? r0 + t : r1 - 1 - t; };
+    auto ridx = [&](int uc) { return FWD ? uc : S - 1 - uc; };
+    auto count = [&](int t) { return (int)min((int64_t)S, nst - (int64_t)t * S); };
 
     if (wave != 0) {
         // ------------------------------------------------------ loaders
-        // loader wave lw (0..2) copies chunk rows lw, lw+3, ... from HBM
-        // straight into LDS (global_load_lds: lane l moves dword l + 64x of
-        // the row, lanes past the row end are masked off), and the input
-        // values of the chunk are spread over all loader threads
+        // Loader wave lw owns the chunks t = lw (mod 3).  A chunk is one
+        // contiguous, 16-byte aligned run of cnt*CP entries in HBM, copied
+        // straight into LDS with 16-byte global_load_lds (1 KiB per
+        // instruction), together with its inputs.  The owner waits for its
+        // own copies only (it has no others in flight), zeroes the staged rows
+        // past the chunk's end (their steps then push nothing), stores v*d,
+        // and meets the compute wave at the barrier before that chunk.
         const int lw = __builtin_amdgcn_readfirstlane(wave - 1);
-        constexpr int RPW = (S + 2) / 3;              // rows per loader wave
-        const int ndw = CS * (int)(sizeof(T) / 4);    // dwords per row
         T vin = T(0);
-        auto copy_rows = [&](int64_t t) {
-            T *c = cst + (t & 1) * S * PITCH;
-            for (int y = 0; y < RPW; ++y) {
-                const int rr = lw + 3 * y;                    // row inside the chunk
-                const int64_t st = t * S + rr;
-                if (rr >= S || st >= nst) break;
-                const unsigned *src =
-                    reinterpret_cast<const unsigned *>(a.F + (s0 + row_of(st)) * CS);
-                for (int x = 0; 64 * x < ndw; ++x) {
-                    const int dw = lane + 64 * x;
-                    if (dw < ndw)
-                        __builtin_amdgcn_global_load_lds(
-                            (const void *)(src + dw),
-                            (__attribute__((address_space(3))) void *)(c + rr * PITCH + (64 * x * 4) / (int)sizeof(T)),
-                            4, 0, 0);
-                }
+        auto issue = [&](int t) {
+            const int cnt = count(t);
+            const int64_t rlo = FWD ? r0 + (int64_t)t * S : r1 - (int64_t)t * S - cnt;
+            const unsigned char *src =
+                reinterpret_cast<const unsigned char *>(a.F + (s0 + rlo) * CP);
+            unsigned char *dst = reinterpret_cast<unsigned char *>(
+                stage + ((size_t)(t % nbuf) * S + (FWD ? 0 : S - cnt)) * CP);
+            const int nbytes = cnt * CP * (int)sizeof(T);
+            for (int q = 0; q * 1024 < nbytes; ++q) {
+                const int off = q * 1024 + lane * 16;
+                if (off < nbytes)
+                    __builtin_amdgcn_global_load_lds(
+                        (const void *)(src + off),
+                        (__attribute__((address_space(3))) void *)(dst + q * 1024), 16, 0, 0);
             }
-        };
-        auto load_in = [&](int64_t t) {
-            const int f = tid - 64;
             vin = T(0);
-            if (f < S) {
-                const int64_t st = t * S + f;
-                if (st < nst) {
-                    const int64_t r = row_of(st);
-                    if (a.xin) {
-                        double x = a.xin[s0 + r];
-                        if (dtop && r < k) x += (double)dtop[r];
-                        if (dbot && r >= nb - k) x += (double)dbot[r - (nb - k)];
-                        vin = (T)x;
-                    } else {
-                        T x = a.tin[s0 + r];
-                        if (dtop && r < k) x += dtop[r];
-                        if (dbot && r >= nb - k) x += dbot[r - (nb - k)];
-                        vin = x;
-                    }
+            if (lane < cnt) {
+                const int64_t r = row_of((int64_t)t * S + lane);
+                if (a.xin) {
+                    double x = a.xin[s0 + r];
+                    if (dtop && r < k) x += (double)dtop[r];
+                    if (dbot && r >= nb - k) x += (double)dbot[r - (nb - k)];
+                    vin = (T)x;
+                } else {
+                    T x = a.tin[s0 + r];
+                    if (dtop && r < k) x += dtop[r];
+                    if (dbot && r >= nb - k) x += dbot[r - (nb - k)];
+                    vin = x;
                 }
             }
         };
-        auto commit_in = [&](int64_t t) {
-            const int f = tid - 64;
-            if (f < S) vst[(t & 1) * S + f] = vin;
+        auto finish = [&](int t) {
+            const int cnt = count(t);
+            T *buf = stage + (size_t)(t % nbuf) * S * CP;
+            if (cnt < S) {
+                T *z = buf + (FWD ? cnt : 0) * CP;
+                for (int i = lane; i < (S - cnt) * CP; i += 64) z[i] = T(0);
+            }
+            if (lane < S) {
+                T d = T(1);
+                if (DIAG && lane < cnt) d = buf[ridx(lane) * CP];
+                vst[(t % nbuf) * S + lane] = lane < cnt ? vin * d : T(0);
+            }
         };
-        copy_rows(0);
-        load_in(0);
-        __builtin_amdgcn_s_waitcnt(0);
-        commit_in(0);
-        copy_rows(1);
-        load_in(1);
-        __syncthreads();
-        for (int64_t t = 0; t < nchunks; ++t) {
-            __builtin_amdgcn_s_waitcnt(0);            // copies of chunk t+1 landed
-            commit_in(t + 1);
-            __syncthreads();
-            copy_rows(t + 2);
-            load_in(t + 2);
+        if (lw < depth && lw < nchunks) issue(lw);
+        for (int t = 0; t < nchunks; ++t) {
+            if (t % 3 == lw) {
+                __builtin_amdgcn_s_waitcnt(0);        // this wave's copies of chunk t
+                finish(t);
+            }
+            __syncthreads();                          // chunk t staged; chunk t-1 swept
+            const int tn = t + depth;                 // goes to the buffer of chunk t-1
+            if (tn < nchunks && tn % 3 == lw) issue(tn);
         }
     } else {
         // ------------------------------------------------------- compute wave
         // Steps run in groups of G; the LDS operands of group g+1 (diagonal
-        // factor, input, and the KR coefficients each lane pushes) are read while
-        // the dependent chain of group g runs.
+        // factor, prescaled input, and the KR coefficients each lane pushes)
+        // are read while the dependent chain of group g runs.  Rows past the
+        // chunk's end are zero, so groups run whole.
         constexpr int G = 4;
+        static_assert(S % (2 * G) == 0, "groups tile the chunk");
         struct Grp {
             T d[G], vd[G], cf[G][KR];
         };
-        __syncthreads();
         T acc[KR];
 #pragma unroll
         for (int s = 0; s < KR; ++s) {
@@ -234,44 +244,44 @@ __global__ __launch_bounds__(256, 2) void k_sweep(SweepArgs<T> a)
         }
 
         T ov = T(0);                                  // outputs of the current 64-block
-        for (int64_t t = 0; t < nchunks; ++t) {
-            const T *c = cst + (t & 1) * S * PITCH;
-            const T *vv = vst + (t & 1) * S;
+        for (int t = 0; t < nchunks; ++t) {
+            __syncthreads();                          // chunk t staged
+            const T *buf = stage + (size_t)(t % nbuf) * S * CP;
+            const T *vv = vst + (t % nbuf) * S;
             // the staged steps t*S .. t*S+cnt-1 are steps ub .. ub+cnt-1 of the
-            // 64-step block that starts at step jb (S = 32: two chunks per block)
-            const int ub = (int)((t * S) & 63);
-            const int64_t jb = t * S - ub;
-            const int cnt = (int)min((int64_t)S, nst - t * S);
+            // 64-step block that starts at step jb
+            const int ub = (t * S) & 63;
+            const int64_t jb = (int64_t)t * S - ub;
+            const int cnt = count(t);
             const int ulim = ub + cnt;
             auto load = [&](int u0, Grp &q) {
 #pragma unroll
                 for (int e = 0; e < G; ++e) {
-                    const int uc = min(u0 + e, S - 1);       // staged row
+                    const int uc = min(u0 + e, S - 1);       // staged step
                     const int u = ub + uc;                    // step in the 64-block
-                    const T *crow = c + uc * PITCH;
+                    const T *crow = buf + ridx(uc) * CP;
                     q.d[e] = DIAG ? crow[0] : T(1);
-                    q.vd[e] = vv[uc] * q.d[e];
+                    q.vd[e] = vv[uc];
 #pragma unroll
                     for (int s = 0; s < KR; ++s) {
-                        // step offset of slot (s, lane).  Offsets > K read a
-                        // zero slot; offsets <= 0 occur only for s = 0 in lanes
-                        // whose step is already done, where the value is unused.
+                        // step offset of slot (s, lane).  Offsets > K read the
+                        // zero slot K+1; offsets <= 0 occur only for s = 0 in
+                        // lanes whose step is already done, where the value is
+                        // unused.
                         const int m = 64 * s + lane - u;
-                        q.cf[e][s] = crow[min(max(m, 0), PITCH - 1)];
+                        q.cf[e][s] = crow[min(max(m, 0), k + 1)];
                     }
                 }
             };
             auto run = [&](int u0, const Grp &q) {
 #pragma unroll
                 for (int e = 0; e < G; ++e) {
-                    if (u0 + e < cnt) {
-                        const int u = ub + u0 + e;
-                        const T x = fma(acc[0], q.d[e], q.vd[e]);   // acc = -pending
-                        const T xb = lane_bcast(x, u);
+                    const int u = ub + u0 + e;
+                    const T x = fma(acc[0], q.d[e], q.vd[e]);   // acc = -pending
+                    const T xb = lane_bcast(x, u);
 #pragma unroll
-                        for (int s = 0; s < KR; ++s) acc[s] = fma(-q.cf[e][s], xb, acc[s]);
-                        ov = lane == u ? xb : ov;
-                    }
+                    for (int s = 0; s < KR; ++s) acc[s] = fma(-q.cf[e][s], xb, acc[s]);
+                    ov = lane == u ? x : ov;
                 }
             };
             Grp ga, gb;
@@ -282,7 +292,7 @@ __global__ __launch_bounds__(256, 2) void k_sweep(SweepArgs<T> a)
                 load(u0 + 2 * G, ga);
                 run(u0 + G, gb);
             }
-            const bool last = t * S + cnt == nst;
+            const bool last = (int64_t)t * S + cnt == nst;
             if (ulim == 64 || last) {
                 const int64_t st = jb + lane;
                 if (PH != SWEEP_ZERO_STATE && lane < ulim) {
@@ -304,7 +314,6 @@ __global__ __launch_bounds__(256, 2) void k_sweep(SweepArgs<T> a)
                 acc[KR - 1] = T(0);
                 ov = T(0);
             }
-            __syncthreads();
         }
     }
     if (PH != SWEEP_ZERO_STATE) return;
@@ -319,48 +328,52 @@ __global__ __launch_bounds__(256, 2) void k_sweep(SweepArgs<T> a)
     __syncthreads();
     if (!last_sh) return;
     __threadfence();                            // see every chunk's q
-    chain_states<T, FWD>(a, blk, nchb, cst);
+    chain_states<T, FWD>(a, blk, nchb, stage);
     if (tid == 0) a.ticket[blk] = 0u;           // ready for the next sweep
 }
 
-template <typename T, int KR, int S, bool FWD, bool DIAG, int PH>
+template <typename T, int KR, bool FWD, bool DIAG, int PH>
 static hipError_t launch_sweep_ph(const SweepArgs<T> &a, hipStream_t s)
 {
-    const size_t lds = (2 * (size_t)S * (64 * (KR - 1) + 8) + 2 * S) * sizeof(T);
+    const int cp = coef_pitch(a.pt.k, (int)sizeof(T));
+    const unsigned grid = PH == SWEEP_WHOLE ? a.pt.p : a.pt.p * a.nch;
+    // deepest staging (2..4 buffers) that keeps two workgroups per CU when
+    // the grid has more than one workgroup per CU
+    const size_t cap = grid > 256 ? kMaxLds / 2 : kMaxLds;
+    int nbuf = 4;
+    while (nbuf > 2 && sweep_lds_bytes<T>(cp, nbuf) > cap) --nbuf;
+    const size_t lds = sweep_lds_bytes<T>(cp, nbuf);
     if (lds > kMaxLds) return hipErrorInvalidValue;
-    auto kern = k_sweep<T, KR, S, FWD, DIAG, PH>;
+    auto kern = k_sweep<T, KR, FWD, DIAG, PH>;
     hipError_t e = hipFuncSetAttribute((const void *)kern,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    const unsigned grid = PH == SWEEP_WHOLE ? a.pt.p : a.pt.p * a.nch;
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(256), lds, s, a);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(256), lds, s, a, nbuf);
     return hipGetLastError();
 }
 
-template <typename T, int KR, int S, bool FWD, bool DIAG>
+template <typename T, int KR, bool FWD, bool DIAG>
 static hipError_t launch_sweep_cfg(const SweepArgs<T> &a, hipStream_t s)
 {
     if constexpr (KR == 2) {                   // chained states need K < 64
         if (a.phase == SWEEP_ZERO_STATE)
-            return launch_sweep_ph<T, KR, S, FWD, DIAG, SWEEP_ZERO_STATE>(a, s);
+            return launch_sweep_ph<T, KR, FWD, DIAG, SWEEP_ZERO_STATE>(a, s);
         if (a.phase == SWEEP_FROM_STATE)
-            return launch_sweep_ph<T, KR, S, FWD, DIAG, SWEEP_FROM_STATE>(a, s);
+            return launch_sweep_ph<T, KR, FWD, DIAG, SWEEP_FROM_STATE>(a, s);
     }
     if (a.phase != SWEEP_WHOLE) return hipErrorInvalidValue;
-    return launch_sweep_ph<T, KR, S, FWD, DIAG, SWEEP_WHOLE>(a, s);
+    return launch_sweep_ph<T, KR, FWD, DIAG, SWEEP_WHOLE>(a, s);
 }
-// two LDS buffers of S rows of pitch 64*(KR-1)+8: S = 64, or 32 where that
-// would not fit (FP64 with K >= 128)
+
 template <typename T, int KR>
 static hipError_t launch_sweep_kr(const SweepArgs<T> &a, hipStream_t s)
 {
-    constexpr int S = (sizeof(T) == 8 && KR >= 4) ? 32 : 64;
     if (a.fwd) {
-        if (a.diag) return launch_sweep_cfg<T, KR, S, true, true>(a, s);
-        return launch_sweep_cfg<T, KR, S, true, false>(a, s);
+        if (a.diag) return launch_sweep_cfg<T, KR, true, true>(a, s);
+        return launch_sweep_cfg<T, KR, true, false>(a, s);
     }
-    if (a.diag) return launch_sweep_cfg<T, KR, S, false, true>(a, s);
-    return launch_sweep_cfg<T, KR, S, false, false>(a, s);
+    if (a.diag) return launch_sweep_cfg<T, KR, false, true>(a, s);
+    return launch_sweep_cfg<T, KR, false, false>(a, s);
 }
 
 template <>
@@ -402,7 +415,7 @@ __global__ __launch_bounds__(256) void k_sweep_xfer(XferArgs<T> a)
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *Xs = reinterpret_cast<T *>(smem_raw);   // [4][K][K]
     const int k = a.pt.k;
-    const int CS = k + 1;
+    const int CP = coef_pitch(k, (int)sizeof(T));   // row pitch in HBM
     const int kk = k * k;
     const int arr = blockIdx.y;
     const T *F = a.F[arr];
@@ -428,7 +441,7 @@ __global__ __launch_bounds__(256) void k_sweep_xfer(XferArgs<T> a)
         for (int e = 0; e < D; ++e) {
             const int64_t t = t0 + e;
             const int64_t row = fwd ? r0 + t : r1 - 1 - t;
-            dst[e] = (t < t_hi && lane <= k) ? F[(s0 + row) * CS + lane] : T(0);
+            dst[e] = (t < t_hi && lane <= k) ? F[(s0 + row) * CP + lane] : T(0);
         }
     };
     load(t_lo, fr);

@@ -63,6 +63,7 @@ __global__ __launch_bounds__(256) void k_tips(TipsArgs<T> a)
     const int k = a.pt.k;
     const int64_t n = a.pt.n;
     const int CS = k + 1;
+    const int CP = coef_pitch(k, (int)sizeof(T));   // row pitch in HBM
     const int64_t s1 = a.pt.starts[i + 1];      // first row of block i+1
     const int64_t kk = (int64_t)k * k;
     T *B = a.B + i * kk, *C = a.C + i * kk, *V = a.V + i * kk, *W = a.W + i * kk;
@@ -97,8 +98,8 @@ __global__ __launch_bounds__(256) void k_tips(TipsArgs<T> a)
         C[e] = cv;
         X[e] = bv;
         Y[e] = cv;
-        F[e] = (r > c) ? a.Lc[(base + c) * CS + (r - c)]
-                       : a.Uc[(base + c) * CS + (c - r)];    // c == r: 1/u_rr
+        F[e] = (r > c) ? a.Lc[(base + c) * CP + (r - c)]
+                       : a.Uc[(base + c) * CP + (c - r)];    // c == r: 1/u_rr
         if (LDS) G[e] = cn[(int64_t)(k - 1 - r) * k + (k - 1 - c)];
     }
     if (tid == 0) zero_sh = T(0);

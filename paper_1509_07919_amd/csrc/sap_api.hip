@@ -104,10 +104,11 @@ Layout layout_for(const sap_options &o)
     L.starts = take(sizeof(int64_t) * (p + 1));
     L.partial = take(sizeof(double) * (size_t)p * nchunk);
     L.status = take(64);
-    L.Lc = take(sf * n * (k + 1));
-    L.Uc = take(sf * n * (k + 1));
-    L.Lr = o.adjoint ? take(sf * n * (k + 1)) : 0;
-    L.Ur = o.adjoint ? take(sf * n * (k + 1)) : 0;
+    const size_t fb = sf * n * coef_pitch(k, (int)sf);   // one factor array
+    L.Lc = take(fb);
+    L.Uc = take(fb);
+    L.Lr = o.adjoint ? take(fb) : 0;
+    L.Ur = o.adjoint ? take(fb) : 0;
     const size_t ni = cpl ? (size_t)(p - 1) : 0;
     L.corner = cpl ? take(sf * p * kk) : 0;
     L.B = cpl ? take(sf * ni * kk) : 0;
@@ -667,6 +668,11 @@ int sap_factor(sap_handle h, const double *a_band, void *stream)
         HIP_TRY(hipMemcpyAsync(h->ptr<int64_t>(h->L.starts), h->h_starts,
                                sizeof(int64_t) * (h->opt.p + 1), hipMemcpyHostToDevice, s));
         HIP_TRY(hipMemsetAsync(h->ptr<unsigned>(h->L.counter), 0, 64, s));
+        // the zero slots after each factor row are never written by a kernel
+        const size_t fb = (h->fp32 ? 4 : 8) * (size_t)h->opt.n *
+                          coef_pitch(h->opt.k, h->fp32 ? 4 : 8);
+        for (size_t off : {h->L.Lc, h->L.Uc, h->L.Lr, h->L.Ur})
+            if (off) HIP_TRY(hipMemsetAsync(h->ws + off, 0, fb, s));
         h->starts_uploaded = true;
     }
     HIP_TRY(hipMemsetAsync(h->ptr<int>(h->L.status), 0, 64, s));

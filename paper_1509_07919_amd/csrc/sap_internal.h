@@ -2,17 +2,20 @@
 //
 // Device data layout (all arrays live in the caller's workspace):
 //
-//   factor coefficient arrays, one row of CS = K+1 entries per matrix
-//   column/row j (global index), type T = float or double:
-//     Lc[j*CS + 0] = 1,        Lc[j*CS + m] = l(j+m, j)   (column j of L)
-//     Uc[j*CS + 0] = 1/u(j,j), Uc[j*CS + m] = u(j-m, j)   (column j of U)
-//     Ur[j*CS + 0] = 1/u(j,j), Ur[j*CS + m] = u(j, j+m)   (row j of U)
-//     Lr[j*CS + 0] = 1,        Lr[j*CS + m] = l(j, j-m)   (row j of L)
-//   for m = 1..K, with 0 wherever j+m or j-m leaves the diagonal block.
-//   Each row holds exactly the coefficients one step of a forward or
-//   backward sweep pushes to its K successors, so every sweep streams one
-//   contiguous row per step.  Ur/Lr exist only when the handle keeps the
-//   transposed factors for the adjoint solve.
+//   factor coefficient arrays, one row of CP entries per matrix column/row
+//   j (global index), type T = float or double, CP = coef_pitch(K, sizeof T):
+//     Lc[j*CP + 0] = 1,        Lc[j*CP + m] = l(j+m, j)   (column j of L)
+//     Uc[j*CP + 0] = 1/u(j,j), Uc[j*CP + m] = u(j-m, j)   (column j of U)
+//     Ur[j*CP + 0] = 1/u(j,j), Ur[j*CP + m] = u(j, j+m)   (row j of U)
+//     Lr[j*CP + 0] = 1,        Lr[j*CP + m] = l(j, j-m)   (row j of L)
+//   for m = 1..K, with 0 wherever j+m or j-m leaves the diagonal block, and
+//   slots K+1..CP-1 zero (cleared when the handle first factors, never
+//   written again).  Each row holds exactly the coefficients one step of a
+//   forward or backward sweep pushes to its K successors, so every sweep
+//   streams one contiguous run of rows; CP makes every row start on a
+//   16-byte boundary and leaves at least one zero slot after the K
+//   coefficients.  Ur/Lr exist only when the handle keeps the transposed
+//   factors for the adjoint solve.
 //
 //   ULcorner[i*K*K + a*K + b]: bottom-right K x K corner of LU(J A_i J)
 //   (unit-lower part below the diagonal, upper part with the pivots on and
@@ -31,6 +34,14 @@ namespace sap {
 constexpr int kMaxK = 255;
 constexpr size_t kMaxLds = 160 * 1024;    // LDS bytes per workgroup on gfx950
 constexpr int kDotBlocks = 512;   // fixed grid of the reduction kernels
+
+// row pitch (entries) of the factor coefficient arrays: K + 1 coefficients,
+// at least one zero, rounded up to a multiple of 16 bytes
+__host__ __device__ inline int coef_pitch(int k, int tsize)
+{
+    const int per16 = 16 / tsize;
+    return (k + 2 + per16 - 1) / per16 * per16;
+}
 
 enum KrylovOp : int {
     OP_INIT = 0,   // d0=(r0,rt) d1=(r0,r0): rho=1,alpha=0,omega=1 then j=0 prep
