@@ -18,6 +18,25 @@ __device__ __forceinline__ float lane_bcast(float x, int l)
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
 }
 
+// 1/p: the hardware reciprocal estimate refined by Newton-Raphson steps
+// r <- r + r (1 - p r), each of which squares the relative error (two for
+// FP64, one for FP32, reaching the format's precision to within an ulp).
+// 0 maps to inf, then NaN; callers flag zero pivots themselves.
+__device__ __forceinline__ double fast_recip(double p)
+{
+    double r = __builtin_amdgcn_rcp(p);
+    double e = fma(-p, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-p, r, 1.0);
+    return fma(r, e, r);
+}
+__device__ __forceinline__ float fast_recip(float p)
+{
+    const float r = __builtin_amdgcn_rcpf(p);
+    const float e = fmaf(-p, r, 1.0f);
+    return fmaf(r, e, r);
+}
+
 // Entry (r, c) of diagonal block [s0, s0+nb) in band storage (band[q*n + c]
 // holds a(c+q-K, c)); ul != 0 reads the block with rows and columns reversed
 // (J A_i J).  Zero outside the block or the band.

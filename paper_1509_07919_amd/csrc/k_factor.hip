@@ -134,7 +134,7 @@ __global__ __launch_bounds__(NT) void k_banded_lu(LuArgs<T> a)
     // q = delta + K; delta >= 0 -> entry (m, m-delta), delta < 0 -> (m+delta, m).
     // For a fixed q the S entries are consecutive band elements (ascending
     // for the LU, descending for the UL): a coalesced run.
-    T pre[PR];
+    double pre[PR];                 // raw band values (converted at commit)
     auto prefetch = [&](int64_t t) {
 #pragma unroll
         for (int i = 0; i < PR; ++i) {
@@ -142,12 +142,12 @@ __global__ __launch_bounds__(NT) void k_banded_lu(LuArgs<T> a)
             const int q = f / S, ss = f % S;              // S is a power of two
             const int delta = q - k;
             const int64_t m = WC + t * S + ss;
-            T v = T(0);
+            double v = 0.0;
             if (f < W2 * S && m < nb) {  // m > K >= |delta|: other index >= 0
                 const int64_t base = (int64_t)(ul ? (k - delta) : (k + delta)) * n;
                 const int64_t col = ul ? (s0 + nb - 1 - m + (delta > 0 ? delta : 0))
                                        : (s0 + m - (delta > 0 ? delta : 0));
-                v = (T)a.band[base + col];
+                v = a.band[base + col];
             }
             pre[i] = v;
         }
@@ -157,7 +157,7 @@ __global__ __launch_bounds__(NT) void k_banded_lu(LuArgs<T> a)
 #pragma unroll
         for (int i = 0; i < PR; ++i) {
             const int f = tid + NT * i;
-            if (f < W2 * S) dst[f] = pre[i];
+            if (f < W2 * S) dst[f] = (T)pre[i];
         }
     };
     for (int idx = tid; idx < 4 * S; idx += NT) {          // the zero rows
@@ -297,9 +297,9 @@ __global__ __launch_bounds__(NT) void k_banded_lu(LuArgs<T> a)
 //      broadcast with v_readlane, the same boosting rule) while the other
 //      waves apply the rest of the update, writing straight into the other
 //      buffer shifted by (B, B) so the window slides for free, copy the
-//      entering rows and columns from the LDS stage, and put the panel's L
-//      columns and U rows into the output buffer (look-ahead: the panel
-//      factorization is off the critical path).
+//      entering rows and columns from the LDS stage, and write the panel's L
+//      columns and U rows to HBM (look-ahead: the panel factorization is off
+//      the critical path).
 // Row r of block i appears at window row r - j0 for the LU; the UL runs the
 // same code on the reversed block.
 template <typename T, int B, int S, int NT, int RPL>
@@ -329,7 +329,7 @@ __global__ __launch_bounds__(NT) void k_banded_lu_blk(LuArgs<T> a)
 
     T *win0 = reinterpret_cast<T *>(smem_raw);  // [2][KB][WP]
     T *stage = win0 + 2 * KB * WP;              // [2][(2K+3)][S], zero rows at q = -1, 2K+1
-    T *obuf = stage + 2 * stage_sz;             // [S][2][K+1]
+    T *uiw = stage + 2 * stage_sz;              // [2][B] 1/pivot of each window's panel
 
     if (tid == 0) {
         double m = 0.0;
@@ -355,7 +355,7 @@ __global__ __launch_bounds__(NT) void k_banded_lu_blk(LuArgs<T> a)
     // or (m+delta, m) for delta < 0, delta = q - K
     constexpr int PR = ((2 * KMAX + 1) * S + NT - 1) / NT;
     const int nitems = W2 * S;
-    T pre[PR];
+    double pre[PR];                 // raw band values (converted at commit)
     auto prefetch = [&](int64_t t) {
 #pragma unroll
         for (int i = 0; i < PR; ++i) {
@@ -363,12 +363,12 @@ __global__ __launch_bounds__(NT) void k_banded_lu_blk(LuArgs<T> a)
             const int q = f / S, ss = f % S;
             const int delta = q - k;
             const int64_t m = KB + t * S + ss;
-            T v = T(0);
+            double v = 0.0;
             if (f < nitems && m < nb) {       // m >= KB > K >= |delta|
                 const int64_t base = (int64_t)(ul ? (k - delta) : (k + delta)) * n;
                 const int64_t col = ul ? (s0 + nb - 1 - m + (delta > 0 ? delta : 0))
                                        : (s0 + m - (delta > 0 ? delta : 0));
-                v = (T)a.band[base + col];
+                v = a.band[base + col];
             }
             pre[i] = v;
         }
@@ -378,29 +378,13 @@ __global__ __launch_bounds__(NT) void k_banded_lu_blk(LuArgs<T> a)
 #pragma unroll
         for (int i = 0; i < PR; ++i) {
             const int f = tid + NT * i;
-            if (f < nitems) dst[f] = pre[i];
+            if (f < nitems) dst[f] = (T)pre[i];
         }
     };
     for (int idx = tid; idx < 4 * S; idx += NT) {
         const int bsel = idx / (2 * S), r = (idx / S) & 1, c = idx % S;
         stage[bsel * stage_sz + (r ? (W2 + 1) * S : 0) + c] = T(0);
     }
-    auto flush = [&](int64_t j0f) {
-        if (ul) return;
-        const int tot = S * CS;
-        for (int idx = tid; idx < tot; idx += NT) {
-            const int jj = idx / CS, m = idx - jj * CS;
-            const int64_t j = j0f + jj;
-            if (j >= nb) continue;
-            const T lv = obuf[jj * 2 * CS + m];
-            const T uv = obuf[jj * 2 * CS + CS + m];
-            const bool in = j + m < nb;
-            a.Lc[(s0 + j) * CP + m] = lv;
-            if (in) a.Uc[(s0 + j + m) * CP + m] = uv;
-            if (a.Ur) a.Ur[(s0 + j) * CP + m] = in ? uv : T(0);
-            if (a.Lr && in) a.Lr[(s0 + j + m) * CP + m] = lv;
-        }
-    };
     prefetch(0);
     __syncthreads();
     __builtin_amdgcn_s_waitcnt(0);
@@ -410,40 +394,36 @@ __global__ __launch_bounds__(NT) void k_banded_lu_blk(LuArgs<T> a)
     int nboost = 0;
 
     const int64_t npanel = (nb + B - 1) / B;
+    bool zero_piv = false;
     // factorization of one panel held in wave 0's registers: row lane + 64x,
-    // columns 0..B-1; the first nact_ columns are pivots
-    auto factor_panel = [&](T (&pv)[RPL][B], int nact_) {
+    // columns 0..B-1; the first nact_ columns are pivots.  Per pivot t the
+    // pivot row is broadcast first (v_readlane; it is final once pivot t-1
+    // is applied), the reciprocal comes from fast_recip, and lanes at or above
+    // the pivot row take a zero multiplier instead of a branch.  ui[t]
+    // receives 1/pivot.
+    auto factor_panel = [&](T (&pv)[RPL][B], int nact_, T *ui) {
 #pragma unroll
         for (int t = 0; t < B; ++t) {
             if (t < nact_) {
-                T praw = pv[0][t];
-                praw = lane_bcast(praw, t);
-                T piv = praw;
-                bool boosted = false;
-                if (do_boost && fabs((double)praw) < (double)tau) {
-                    piv = praw >= T(0) ? tau : -tau;
-                    boosted = true;
-                }
-                if (lane == 0) {
-                    nboost += boosted ? 1 : 0;
-                    if (piv == T(0)) a.status[1] = 1;
-                }
-                const T inv = T(1) / piv;
                 T urow[B];
 #pragma unroll
-                for (int c = t + 1; c < B; ++c) urow[c] = lane_bcast(pv[0][c], t);
+                for (int c = t; c < B; ++c) urow[c] = lane_bcast(pv[0][c], t);
+                const T praw = urow[t];
+                const bool boosted = do_boost && fabs((double)praw) < (double)tau;
+                const T piv = boosted ? (praw >= T(0) ? tau : -tau) : praw;
+                nboost += boosted ? 1 : 0;
+                zero_piv = zero_piv || piv == T(0);
+                const T inv = fast_recip(piv);
 #pragma unroll
                 for (int x = 0; x < RPL; ++x) {
                     const int rr = lane + 64 * x;
-                    if (rr > t) {
-                        const T l = pv[x][t] * inv;
-                        pv[x][t] = l;
+                    const T l = pv[x][t] * inv;
+                    const T lm = rr > t ? l : T(0);
 #pragma unroll
-                        for (int c = t + 1; c < B; ++c) pv[x][c] = fma(-l, urow[c], pv[x][c]);
-                    } else if (rr == t) {
-                        pv[x][t] = piv;
-                    }
+                    for (int c = t + 1; c < B; ++c) pv[x][c] = fma(-lm, urow[c], pv[x][c]);
+                    pv[x][t] = rr > t ? l : (rr == t ? piv : pv[x][t]);
                 }
+                if (lane == t) ui[t] = inv;
             }
         }
     };
@@ -456,6 +436,41 @@ __global__ __launch_bounds__(NT) void k_banded_lu_blk(LuArgs<T> a)
         const int qrow = min(max(delta + k, -1), W2);
         return stg[qrow * S + so];
     };
+    // Per-thread work items of the update waves that are the same for every
+    // panel.  3b: entering entries of the next window outside its first B
+    // columns -- rows K..KB-1 x columns B..KB-1, and rows 0..K-1 x columns
+    // max(K, B)..KB-1 -- as (window offset, stage offset less the panel's
+    // offset inside its chunk).  3c: (pivot t, offset m) of the outputs.
+    constexpr int NTR_ = NT - 64;
+    constexpr int NIB = (2 * B * KMAX + NTR_ - 1) / NTR_;
+    constexpr int NIC = (B * (KMAX + 1) + NTR_ - 1) / NTR_;
+    int eb_dst[NIB], eb_src[NIB], oc_t[NIC], oc_m[NIC];
+    {
+        const int tr = tid - 64;
+        const int cb0 = max(k, B);
+        const int na = B * k, nbb = k * (KB - cb0);
+#pragma unroll
+        for (int i = 0; i < NIB; ++i) {
+            const int idx = tr + NTR_ * i;
+            eb_dst[i] = -1;
+            eb_src[i] = 0;
+            if (tr >= 0 && idx < na + nbb) {
+                int r, c;
+                if (idx < na) { r = k + idx / k; c = B + idx % k; }
+                else { const int q2 = idx - na; r = q2 / (KB - cb0); c = cb0 + q2 % (KB - cb0); }
+                const int qrow = min(max(r - c + k, -1), W2);
+                eb_dst[i] = r * WP + c;
+                eb_src[i] = qrow * S + max(r, c) - k;
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < NIC; ++i) {
+            const int idx = tr + NTR_ * i;
+            const bool ok = tr >= 0 && idx < B * CS;
+            oc_t[i] = ok ? idx / CS : B;      // t = B: never a pivot
+            oc_m[i] = ok ? idx % CS : 0;
+        }
+    }
     if (wave == 0) {                                  // panel 0
         T pv[RPL][B];
 #pragma unroll
@@ -464,7 +479,7 @@ __global__ __launch_bounds__(NT) void k_banded_lu_blk(LuArgs<T> a)
 #pragma unroll
             for (int t = 0; t < B; ++t) pv[x][t] = rr < KB ? win0[rr * WP + t] : T(0);
         }
-        factor_panel(pv, (int)min((int64_t)B, nb));
+        factor_panel(pv, (int)min((int64_t)B, nb), uiw);
 #pragma unroll
         for (int x = 0; x < RPL; ++x) {
             const int rr = lane + 64 * x;
@@ -483,23 +498,25 @@ __global__ __launch_bounds__(NT) void k_banded_lu_blk(LuArgs<T> a)
         T *W = win0 + (pnl & 1) * KB * WP;            // current window
         T *Wn = win0 + ((pnl + 1) & 1) * KB * WP;     // next window
         const int64_t e0 = j0;                        // entering indices of this panel
-        if ((e0 % S) == 0) {
-            commit(e0 / S);
-            if (j0 > 0) flush(j0 - S);
-        }
+        if ((e0 % S) == 0) commit(e0 / S);
         const int nact = (int)min((int64_t)B, nb - j0);   // pivots in this panel
         const T *stg = stage + (((e0) / S) & 1) * stage_sz + S;
 
-        // 2. U12 = L11^{-1} A12 (rows 0..B-1, window columns B..KB-1)
+        // 2. U12 = L11^{-1} A12 (rows 0..B-1, window columns B..KB-1); the
+        // unit lower triangle L11 and the column are read before the
+        // substitution starts
         for (int c = B + tid; c < KB; c += NT) {
-            T u[B];
+            T u[B], l11[B][B];
 #pragma unroll
             for (int t = 0; t < B; ++t) {
-                T v = W[t * WP + c];
+                u[t] = W[t * WP + c];
 #pragma unroll
-                for (int s2 = 0; s2 < t; ++s2) v = fma(-W[t * WP + s2], u[s2], v);
-                u[t] = v;
+                for (int s2 = 0; s2 < t; ++s2) l11[t][s2] = W[t * WP + s2];
             }
+#pragma unroll
+            for (int t = 1; t < B; ++t)
+#pragma unroll
+                for (int s2 = 0; s2 < t; ++s2) u[t] = fma(-l11[t][s2], u[s2], u[t]);
 #pragma unroll
             for (int t = 0; t < B; ++t) W[t * WP + c] = u[t];
         }
@@ -512,9 +529,18 @@ __global__ __launch_bounds__(NT) void k_banded_lu_blk(LuArgs<T> a)
                 const int rr = idx / B, cb = idx - rr * B;
                 T v;
                 if (rr < k && cb < k) {
+                    // all operands are read before the first FMA (the
+                    // scheduler would otherwise wait on each read in turn)
+                    T lr[B], uc[B];
                     v = W[(B + rr) * WP + B + cb];
 #pragma unroll
-                    for (int t = 0; t < B; ++t) v = fma(-W[(B + rr) * WP + t], W[t * WP + B + cb], v);
+                    for (int t = 0; t < B; ++t) {
+                        lr[t] = W[(B + rr) * WP + t];
+                        uc[t] = W[t * WP + B + cb];
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                    for (int t = 0; t < B; ++t) v = fma(-lr[t], uc[t], v);
                 } else {
                     v = entering(stg, j0, e0, rr, cb);
                 }
@@ -532,7 +558,7 @@ __global__ __launch_bounds__(NT) void k_banded_lu_blk(LuArgs<T> a)
 #pragma unroll
                     for (int t = 0; t < B; ++t) pv[x][t] = rr < KB ? Wn[rr * WP + t] : T(0);
                 }
-                factor_panel(pv, (int)min((int64_t)B, nb - j0 - B));
+                factor_panel(pv, (int)min((int64_t)B, nb - j0 - B), uiw + ((pnl + 1) & 1) * B);
 #pragma unroll
                 for (int x = 0; x < RPL; ++x) {
                     const int rr = lane + 64 * x;
@@ -545,43 +571,63 @@ __global__ __launch_bounds__(NT) void k_banded_lu_blk(LuArgs<T> a)
             const int wr = wave - 1, NR = NW - 1, tr = tid - 64, NTR = NT - 64;
             // 3a. Schur update of the other columns into the next window:
             // Wn[r-B][c-B] = W[r][c] - L21 U12 for window columns c >= 2B
+            // (rows four at a time, so the LDS reads of four rows are in
+            // flight together)
             for (int cb = B + lane; cb < k; cb += 64) {
                 const int c = B + cb;
                 T uc[B];
 #pragma unroll
                 for (int t = 0; t < B; ++t) uc[t] = W[t * WP + c];
-                for (int rb = wr; rb < k; rb += NR) {
-                    const int r = B + rb;
-                    T v = W[r * WP + c];
+                int rb = wr;
+                for (; rb + 3 * NR < k; rb += 4 * NR) {
+                    T v[4], lr[4][B];
 #pragma unroll
-                    for (int t = 0; t < B; ++t) v = fma(-W[r * WP + t], uc[t], v);
+                    for (int q = 0; q < 4; ++q) {
+                        const int r = B + rb + q * NR;
+                        v[q] = W[r * WP + c];
+#pragma unroll
+                        for (int t = 0; t < B; ++t) lr[q][t] = W[r * WP + t];
+                    }
+                    __builtin_amdgcn_sched_barrier(0);      // reads first, as above
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+#pragma unroll
+                        for (int t = 0; t < B; ++t) v[q] = fma(-lr[q][t], uc[t], v[q]);
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) Wn[(rb + q * NR) * WP + cb] = v[q];
+                }
+                for (; rb < k; rb += NR) {
+                    const int r = B + rb;
+                    T v = W[r * WP + c], lr[B];
+#pragma unroll
+                    for (int t = 0; t < B; ++t) lr[t] = W[r * WP + t];
+                    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                    for (int t = 0; t < B; ++t) v = fma(-lr[t], uc[t], v);
                     Wn[rb * WP + cb] = v;
                 }
             }
             // 3b. entering entries of the next window outside its first B
-            // columns: rows K..KB-1 x columns B..KB-1, and rows 0..K-1 x
-            // columns max(K, B)..KB-1
-            {
-                const int cb0 = max(k, B);
-                const int na = B * k, nbb = k * (KB - cb0);
-                for (int idx = tr; idx < na + nbb; idx += NTR) {
-                    int r, c;
-                    if (idx < na) { r = k + idx / k; c = B + idx % k; }
-                    else { const int q2 = idx - na; r = q2 / (KB - cb0); c = cb0 + q2 % (KB - cb0); }
-                    Wn[r * WP + c] = entering(stg, j0, e0, r, c);
-                }
-            }
+            // columns (items fixed per thread, set up before the loop)
+            const int pofs = (int)((pnl * B) % S);
+#pragma unroll
+            for (int i = 0; i < NIB; ++i)
+                if (eb_dst[i] >= 0) Wn[eb_dst[i]] = stg[eb_src[i] + pofs];
             // 3c. outputs of the panel's pivots: L column and U row of j = j0+t
-            for (int idx = tr; idx < nact * CS; idx += NTR) {
-                const int t = idx / CS, m = idx - t * CS;
+#pragma unroll
+            for (int i = 0; i < NIC; ++i) {
+                const int t = oc_t[i], m = oc_m[i];
+                if (t >= nact) continue;
                 const int64_t j = j0 + t;
                 const T piv = W[t * WP + t];
                 const T lv = m == 0 ? T(1) : W[(t + m) * WP + t];
-                const T uv = m == 0 ? T(1) / piv : W[t * WP + t + m];
+                const T uv = m == 0 ? uiw[(pnl & 1) * B + t] : W[t * WP + t + m];
                 if (!ul) {
-                    T *ob = obuf + (int)(j % S) * 2 * CS;
-                    ob[m] = lv;
-                    ob[CS + m] = uv;
+                    const bool in = j + m < nb;
+                    a.Lc[(s0 + j) * CP + m] = lv;
+                    if (in) a.Uc[(s0 + j + m) * CP + m] = uv;
+                    if (a.Ur) a.Ur[(s0 + j) * CP + m] = in ? uv : T(0);
+                    if (a.Lr && in) a.Lr[(s0 + j + m) * CP + m] = lv;
                 } else if (a.corner && j >= nb - k && j + m < nb) {
                     const int64_t b0 = j - (nb - k);
                     T *cn = a.corner + (int64_t)blk * k * k;
@@ -593,8 +639,8 @@ __global__ __launch_bounds__(NT) void k_banded_lu_blk(LuArgs<T> a)
         if ((e0 % S) == 0) prefetch(e0 / S + 1);
         __syncthreads();
     }
-    flush((nb - 1) / S * S);
     if (tid == 0 && nboost) atomicAdd(&a.status[0], nboost);
+    if (tid == 0 && zero_piv) a.status[1] = 1;
 }
 
 template <typename T, int B, int S, int NT, int RPL>
@@ -602,7 +648,7 @@ static hipError_t launch_lu_blk(const LuArgs<T> &a, hipStream_t s)
 {
     const int k = a.pt.k, KB = k + B;
     const size_t lds = (2 * (size_t)KB * (KB + 1) + 2 * (size_t)(2 * k + 3) * S +
-                        (size_t)S * 2 * (k + 1)) * sizeof(T);
+                        2 * (size_t)B) * sizeof(T);
     if (lds > kMaxLds) return hipErrorInvalidValue;
     auto kern = k_banded_lu_blk<T, B, S, NT, RPL>;
     hipError_t e = hipFuncSetAttribute((const void *)kern,

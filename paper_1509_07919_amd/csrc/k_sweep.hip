@@ -24,7 +24,9 @@
 // static for any K <= 255.
 // Per step: one FMA for x_j (lane u holds the result), a v_readlane
 // broadcast (lane index in an SGPR), and one FMA per register in every lane.
-// Outputs are gathered in a register and written 64 at a time, coalesced.
+// A lane's pending sum is final once its step is reached (later steps push
+// zeros to it), so the outputs of a 64-step block are formed at its end and
+// written 64 at a time, coalesced.
 //
 // Chunked form (sap_internal.h): the same chain runs over one row chunk per
 // workgroup, so a block's sweep has nch chains in flight instead of one.  The
@@ -225,14 +227,19 @@ __global__ __launch_bounds__(256, 2) void k_sweep(SweepArgs<T> a, int nbuf)
         }
     } else {
         // ------------------------------------------------------- compute wave
-        // Steps run in groups of G; the LDS operands of group g+1 (diagonal
-        // factor, prescaled input, and the KR coefficients each lane pushes)
-        // are read while the dependent chain of group g runs.  Rows past the
-        // chunk's end are zero, so groups run whole.
+        // Steps run in groups of G; the KR coefficients each lane pushes for
+        // group g+1 are read from LDS while the dependent chain of group g
+        // runs.  Rows past the chunk's end are zero, so groups run whole.
+        // Lane l keeps d and v*d of step l of the current 64-step block in
+        // registers (loaded with the chunk that holds it), so the step itself
+        // is one FMA in lane u.  Offsets m <= 0 (lanes whose step is done, and
+        // lane u itself) read the zero slot K+1 like offsets m > K, so a done
+        // lane's pending sum stays final and the outputs of the block are
+        // formed at its end, again one FMA per lane.
         constexpr int G = 4;
         static_assert(S % (2 * G) == 0, "groups tile the chunk");
         struct Grp {
-            T d[G], vd[G], cf[G][KR];
+            T cf[G][KR];
         };
         T acc[KR];
 #pragma unroll
@@ -243,45 +250,44 @@ __global__ __launch_bounds__(256, 2) void k_sweep(SweepArgs<T> a, int nbuf)
                          ? -a.st[((int64_t)blk * a.nch + ch) * k + m] : T(0);
         }
 
-        T ov = T(0);                                  // outputs of the current 64-block
+        T dl = T(0), vdl = T(0);                      // step `lane` of the 64-block
         for (int t = 0; t < nchunks; ++t) {
             __syncthreads();                          // chunk t staged
             const T *buf = stage + (size_t)(t % nbuf) * S * CP;
-            const T *vv = vst + (t % nbuf) * S;
             // the staged steps t*S .. t*S+cnt-1 are steps ub .. ub+cnt-1 of the
             // 64-step block that starts at step jb
             const int ub = (t * S) & 63;
             const int64_t jb = (int64_t)t * S - ub;
             const int cnt = count(t);
             const int ulim = ub + cnt;
+            if (lane >= ub && lane < ub + S) {
+                const int uc = lane - ub;
+                dl = DIAG ? buf[ridx(uc) * CP] : T(1);
+                vdl = vst[(t % nbuf) * S + uc];
+            }
             auto load = [&](int u0, Grp &q) {
 #pragma unroll
                 for (int e = 0; e < G; ++e) {
                     const int uc = min(u0 + e, S - 1);       // staged step
                     const int u = ub + uc;                    // step in the 64-block
-                    const T *crow = buf + ridx(uc) * CP;
-                    q.d[e] = DIAG ? crow[0] : T(1);
-                    q.vd[e] = vv[uc];
+                    // slots 1..K+1 of the row: offset m maps to slot
+                    // min(m - 1, K) + 1 taken unsigned, which is K+1 (zero)
+                    // for m <= 0 and m > K
+                    const T *crow1 = buf + ridx(uc) * CP + 1;
+                    const int m1 = lane - 1 - u;
 #pragma unroll
-                    for (int s = 0; s < KR; ++s) {
-                        // step offset of slot (s, lane).  Offsets > K read the
-                        // zero slot K+1; offsets <= 0 occur only for s = 0 in
-                        // lanes whose step is already done, where the value is
-                        // unused.
-                        const int m = 64 * s + lane - u;
-                        q.cf[e][s] = crow[min(max(m, 0), k + 1)];
-                    }
+                    for (int s = 0; s < KR; ++s)
+                        q.cf[e][s] = crow1[min((unsigned)(m1 + 64 * s), (unsigned)k)];
                 }
             };
             auto run = [&](int u0, const Grp &q) {
 #pragma unroll
                 for (int e = 0; e < G; ++e) {
                     const int u = ub + u0 + e;
-                    const T x = fma(acc[0], q.d[e], q.vd[e]);   // acc = -pending
+                    const T x = fma(acc[0], dl, vdl);        // x_u in lane u (acc = -pending)
                     const T xb = lane_bcast(x, u);
 #pragma unroll
                     for (int s = 0; s < KR; ++s) acc[s] = fma(-q.cf[e][s], xb, acc[s]);
-                    ov = lane == u ? x : ov;
                 }
             };
             Grp ga, gb;
@@ -296,6 +302,7 @@ __global__ __launch_bounds__(256, 2) void k_sweep(SweepArgs<T> a, int nbuf)
             if (ulim == 64 || last) {
                 const int64_t st = jb + lane;
                 if (PH != SWEEP_ZERO_STATE && lane < ulim) {
+                    const T ov = fma(acc[0], dl, vdl);     // x of step `lane`
                     const int64_t r = s0 + row_of(st);
                     if (a.dout) a.dout[r] = (double)ov;
                     else a.tout[r] = ov;
@@ -312,7 +319,6 @@ __global__ __launch_bounds__(256, 2) void k_sweep(SweepArgs<T> a, int nbuf)
 #pragma unroll
                 for (int s = 0; s < KR - 1; ++s) acc[s] = acc[s + 1];
                 acc[KR - 1] = T(0);
-                ov = T(0);
             }
         }
     }
