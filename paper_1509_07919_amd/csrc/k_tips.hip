@@ -11,25 +11,23 @@
 //                 the UL factorization A_{i+1} = U' L'
 //   Rbar_i = I - W_{i+1}^(t) V_i^(b)            -- eq:solveTopBottom
 //
-// Rbar_i is factored with partial pivoting and inverted once here, so that
-// each preconditioner application only needs small matrix-vector products.
+// Rbar_i is inverted once here (with partial pivoting), so that each
+// preconditioner application only needs small matrix-vector products.
 //
-// One 256-thread workgroup per interface; thread b owns column b of every
-// K x K right-hand side (K <= 255).  The working matrices and both staged
-// factor corners live in LDS when they fit (4 K^2 elements <= 128 KB); then
-// the V and W solves run side by side (threads 0..K-1 and K..2K-1).  Else
-// they live in global memory and the two solves run one after the other.
-// This step is O(P K^3) and runs once per factorization.
+// One 256-thread workgroup per interface.  When the four K x K working
+// matrices fit in LDS, k_tips_lds spreads every step over all threads (K <=
+// 71 for FP64 factors, K <= 100 for FP32); else k_tips_global keeps them in
+// global memory with one thread per right-hand-side column.  This step is
+// O(P K^3) and runs once per factorization.
 #include "sap_internal.h"
 
 namespace sap {
 
-// Workgroup barrier that also orders the workgroup's global-memory
-// accesses (needed only when the working matrices live in global memory).
-template <bool LDS>
+// Workgroup barrier that also orders the workgroup's global-memory accesses
+// (the working matrices of k_tips_global live in global memory).
 __device__ __forceinline__ void block_sync()
 {
-    if (!LDS) __threadfence_block();
+    __threadfence_block();
     __syncthreads();
 }
 
@@ -50,15 +48,13 @@ __device__ __forceinline__ T rowdot(const T *M, const T *X, int k, int r, int b,
     return (s0 + s1) + (s2 + s3);
 }
 
-// X, Y (right-hand-side columns, thread b owns column b) and F (the staged
-// K x K factor corner, later Rbar and its LU) are row-major K x K working
-// matrices, with G (the second corner) in LDS mode: in LDS when 4*K*K
-// elements fit, else in global memory (the V, W and Rlu slots; the Rinv
-// columns are then solved in place in Rinv).
-template <typename T, bool LDS>
-__global__ __launch_bounds__(256) void k_tips(TipsArgs<T> a)
+// Global-memory version, for K too large for LDS: X, Y (right-hand-side
+// columns, thread b owns column b) and F (the staged K x K factor corner,
+// later Rbar and its LU) are row-major K x K working matrices in the V, W and
+// Rlu slots; the Rinv columns are solved in place in Rinv.
+template <typename T>
+__global__ __launch_bounds__(256) void k_tips_global(TipsArgs<T> a)
 {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
     const int i = blockIdx.x;                   // interface i: blocks i, i+1
     const int k = a.pt.k;
     const int64_t n = a.pt.n;
@@ -68,10 +64,10 @@ __global__ __launch_bounds__(256) void k_tips(TipsArgs<T> a)
     const int64_t kk = (int64_t)k * k;
     T *B = a.B + i * kk, *C = a.C + i * kk, *V = a.V + i * kk, *W = a.W + i * kk;
     T *R = a.Rbar + i * kk, *RI = a.Rinv + i * kk;
-    T *X = LDS ? reinterpret_cast<T *>(smem_raw) : V;
-    T *Y = LDS ? reinterpret_cast<T *>(smem_raw) + kk : W;
-    T *F = LDS ? reinterpret_cast<T *>(smem_raw) + 2 * kk : a.Rlu + i * kk;
-    T *Z = LDS ? Y : RI;                        // Rinv working columns
+    T *X = V;
+    T *Y = W;
+    T *F = a.Rlu + i * kk;
+    T *Z = RI;                                  // Rinv working columns
     int *piv = a.piv + (int64_t)i * k;
     const T *cn = a.corner + (int64_t)(i + 1) * kk;   // UL corner of block i+1
     const int tid = threadIdx.x;
@@ -84,10 +80,7 @@ __global__ __launch_bounds__(256) void k_tips(TipsArgs<T> a)
     // -> Y, and the bottom-right corner of LU(A_i) -> F, with
     // F[r][c] = l(base+r, base+c) for r > c (unit diagonal implied) and
     // F[r][c] = u(base+r, base+c) for r <= c; the stored diagonal of U is
-    // its reciprocal.  In LDS mode the reversed corner of LU(J A_{i+1} J) goes
-    // to G at the same time: U'_tt (unit upper) above the diagonal, L'_tt on
-    // and below it.
-    T *G = LDS ? reinterpret_cast<T *>(smem_raw) + 3 * kk : nullptr;
+    // its reciprocal.
     for (int64_t e = tid; e < kk; e += 256) {
         const int r = (int)(e / k), c = (int)(e % k);
         const int64_t br = s1 - k + r, bc = s1 + c;          // B: a[br][bc]
@@ -100,52 +93,33 @@ __global__ __launch_bounds__(256) void k_tips(TipsArgs<T> a)
         Y[e] = cv;
         F[e] = (r > c) ? a.Lc[(base + c) * CP + (r - c)]
                        : a.Uc[(base + c) * CP + (c - r)];    // c == r: 1/u_rr
-        if (LDS) G[e] = cn[(int64_t)(k - 1 - r) * k + (k - 1 - c)];
     }
     if (tid == 0) zero_sh = T(0);
-    block_sync<LDS>();
+    block_sync();
 
     const int b = tid;
-    if (LDS) {
-        // V (threads 0..K-1) and W (threads K..2K-1) at the same time
-        if (b < k) {
-            // V = U_bb^{-1} (L_bb^{-1} B_i), column b, in X
-            for (int r = 1; r < k; ++r) X[r * k + b] -= rowdot(F, X, k, r, b, 0, r);
-            for (int r = k - 1; r >= 0; --r)
-                X[r * k + b] = (X[r * k + b] - rowdot(F, X, k, r, b, r + 1, k)) * F[r * k + r];
-        } else if (b < 2 * k) {
-            // W = L'_tt^{-1} (U'_tt^{-1} C_{i+1}), column b - K, in Y
-            const int w = b - k;
-            for (int r = k - 2; r >= 0; --r) Y[r * k + w] -= rowdot(G, Y, k, r, w, r + 1, k);
-            for (int r = 0; r < k; ++r)
-                Y[r * k + w] = (Y[r * k + w] - rowdot(G, Y, k, r, w, 0, r)) / G[r * k + r];
-        }
-        block_sync<LDS>();
-        for (int64_t e = tid; e < kk; e += 256) V[e] = X[e];
-    } else {
-        if (b < k) {
-            // V = U_bb^{-1} (L_bb^{-1} B_i), column b, in X
-            for (int r = 1; r < k; ++r) X[r * k + b] -= rowdot(F, X, k, r, b, 0, r);
-            for (int r = k - 1; r >= 0; --r)
-                X[r * k + b] = (X[r * k + b] - rowdot(F, X, k, r, b, r + 1, k)) * F[r * k + r];
-        }
-        block_sync<LDS>();
-        // corner of LU(J A_{i+1} J) -> F reversed: F[r][c] = cn[(k-1-r)*k + (k-1-c)],
-        // i.e. U'_tt (unit upper) above the diagonal and L'_tt on and below it
-        for (int64_t e = tid; e < kk; e += 256) {
-            const int r = (int)(e / k), c = (int)(e % k);
-            F[e] = cn[(int64_t)(k - 1 - r) * k + (k - 1 - c)];
-            V[e] = X[e];
-        }
-        block_sync<LDS>();
-        if (b < k) {
-            // W = L'_tt^{-1} (U'_tt^{-1} C_{i+1}), column b, in Y
-            for (int r = k - 2; r >= 0; --r) Y[r * k + b] -= rowdot(F, Y, k, r, b, r + 1, k);
-            for (int r = 0; r < k; ++r)
-                Y[r * k + b] = (Y[r * k + b] - rowdot(F, Y, k, r, b, 0, r)) / F[r * k + r];
-        }
+    if (b < k) {
+        // V = U_bb^{-1} (L_bb^{-1} B_i), column b, in X
+        for (int r = 1; r < k; ++r) X[r * k + b] -= rowdot(F, X, k, r, b, 0, r);
+        for (int r = k - 1; r >= 0; --r)
+            X[r * k + b] = (X[r * k + b] - rowdot(F, X, k, r, b, r + 1, k)) * F[r * k + r];
     }
-    block_sync<LDS>();
+    block_sync();
+    // corner of LU(J A_{i+1} J) -> F reversed: F[r][c] = cn[(k-1-r)*k + (k-1-c)],
+    // i.e. U'_tt (unit upper) above the diagonal and L'_tt on and below it
+    for (int64_t e = tid; e < kk; e += 256) {
+        const int r = (int)(e / k), c = (int)(e % k);
+        F[e] = cn[(int64_t)(k - 1 - r) * k + (k - 1 - c)];
+        V[e] = X[e];
+    }
+    block_sync();
+    if (b < k) {
+        // W = L'_tt^{-1} (U'_tt^{-1} C_{i+1}), column b, in Y
+        for (int r = k - 2; r >= 0; --r) Y[r * k + b] -= rowdot(F, Y, k, r, b, r + 1, k);
+        for (int r = 0; r < k; ++r)
+            Y[r * k + b] = (Y[r * k + b] - rowdot(F, Y, k, r, b, 0, r)) / F[r * k + r];
+    }
+    block_sync();
     // Rbar = I - W V -> F and R (global)
     for (int64_t e = tid; e < kk; e += 256) W[e] = Y[e];
     if (b < k) {
@@ -155,7 +129,7 @@ __global__ __launch_bounds__(256) void k_tips(TipsArgs<T> a)
             F[r * k + b] = s;
         }
     }
-    block_sync<LDS>();
+    block_sync();
     // LU with partial pivoting of Rbar in F (ties to the lowest row); the
     // pivot search is a wave-0 argmax
     for (int j = 0; j < k; ++j) {
@@ -178,7 +152,7 @@ __global__ __launch_bounds__(256) void k_tips(TipsArgs<T> a)
                 if (best == T(0)) a.status[1] = 2;
             }
         }
-        block_sync<LDS>();
+        block_sync();
         const int p = pr_sh;
         if (p != j)
             for (int c = tid; c < k; c += 256) {
@@ -186,7 +160,7 @@ __global__ __launch_bounds__(256) void k_tips(TipsArgs<T> a)
                 F[j * k + c] = F[p * k + c];
                 F[p * k + c] = t;
             }
-        block_sync<LDS>();
+        block_sync();
         const T d = F[j * k + j];
         const T dinv = d != T(0) ? T(1) / d : zero_sh;
         const int m = k - 1 - j;                               // trailing size
@@ -194,9 +168,9 @@ __global__ __launch_bounds__(256) void k_tips(TipsArgs<T> a)
             const int r = j + 1 + e / m, c = j + 1 + e % m;
             F[r * k + c] = fma(-F[r * k + j] * dinv, F[j * k + c], F[r * k + c]);
         }
-        block_sync<LDS>();
+        block_sync();
         for (int r = j + 1 + tid; r < k; r += 256) F[r * k + j] *= dinv;
-        block_sync<LDS>();
+        block_sync();
     }
     // Rinv = Rbar^{-1}: column b solves Rbar y = e_b with the pivoted LU (in Z)
     if (b < k) {
@@ -212,24 +186,276 @@ __global__ __launch_bounds__(256) void k_tips(TipsArgs<T> a)
         for (int r = 1; r < k; ++r) Z[r * k + b] -= rowdot(F, Z, k, r, b, 0, r);
         for (int r = k - 1; r >= 0; --r)
             Z[r * k + b] = (Z[r * k + b] - rowdot(F, Z, k, r, b, r + 1, k)) / F[r * k + r];
-        if (LDS)
-            for (int r = 0; r < k; ++r) RI[r * k + b] = Z[r * k + b];
     }
+}
+
+
+
+// ---------------------------------------------------------------------------
+// The same quantities with every K x K working matrix in LDS (4 K^2 + 3 K
+// elements), spread over all 256 threads:
+//   (a) B, C, the two factor corners and 1/diag(L'_tt) are loaded, all loads
+//       of a batch issued before the first store;
+//   (b) V and W by right-looking (column-sweep) substitution, one pivot row
+//       per step and one barrier per step: threads 0..127 work on V, threads
+//       128..255 on W, element (row, column) pairs spread over the team.  The
+//       scaling by a pivot of the non-unit triangle is applied on the fly to
+//       the pivot row that the step reads, and written back one step later,
+//       when no thread reads that row any more;
+//   (c) Rbar = I - W V, one 2 x 4 block of outputs per thread and pass;
+//   (d) Rinv by Gauss-Jordan elimination with partial pivoting (ties to the
+//       lowest row), in place, three barriers per pivot: wave 0 finds the
+//       pivot, all threads stage the scaled pivot row and the pivot column,
+//       then every other row is eliminated (the item of the pivot's row also
+//       moves the displaced row); the column order is restored when Rinv is
+//       written out.
+template <typename T>
+__global__ __launch_bounds__(256) void k_tips_lds(TipsArgs<T> a)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int i = blockIdx.x;                   // interface i: blocks i, i+1
+    const int k = a.pt.k;
+    const int64_t n = a.pt.n;
+    const int CP = coef_pitch(k, (int)sizeof(T));   // row pitch in HBM
+    const int64_t s1 = a.pt.starts[i + 1];      // first row of block i+1
+    const int kk = k * k;
+    T *X = reinterpret_cast<T *>(smem_raw);     // V
+    T *Y = X + kk;                              // W
+    T *F = Y + kk;                              // LU corner of block i, then Rbar
+    T *G = F + kk;                              // UL corner of block i+1
+    T *gi = G + kk;                             // 1 / diag(L'_tt)
+    T *colj = gi + k;                           // Gauss-Jordan pivot column
+    T *rowj = colj + k;                         // Gauss-Jordan scaled pivot row
+    __shared__ int perm_sh[kMaxK], ord_sh[kMaxK];
+    __shared__ int p_sh;
+    __shared__ T d_sh;
+    const int tid = threadIdx.x;
+    const int64_t base = s1 - k;                // first row of block i's bottom corner
+    const T *cn = a.corner + (int64_t)(i + 1) * kk;
+    const int64_t ikk = (int64_t)i * kk;
+
+    // (a) B_i (lower triangular incl. diagonal) -> X, C_{i+1} (upper
+    // triangular) -> Y, the bottom-right corner of LU(A_i) -> F (l below the
+    // diagonal, u on and above it with the reciprocal on the diagonal), the
+    // reversed corner of LU(J A_{i+1} J) -> G (U'_tt above the diagonal, L'_tt
+    // on and below it)
+    // thread (gc, gr0) covers column gc, rows gr0 + grs * q (grs = floor(256 / K))
+    const int grs = 256 / k;
+    const int gc = tid % k, gr0 = tid / k;
+    const bool gact = gr0 < grs;
+    constexpr int QB = 4;
+    for (int rb = 0; rb < k; rb += grs * QB) {
+        double bv[QB], cv[QB];
+        T fv[QB], gv[QB];
+        const int c = gc;
+#pragma unroll
+        for (int q = 0; q < QB; ++q) {
+            const int r = rb + gr0 + grs * q;
+            bv[q] = cv[q] = 0.0;
+            fv[q] = gv[q] = T(0);
+            if (gact && r < k) {
+                if (c <= r) bv[q] = a.band[(int64_t)(r - c) * n + s1 + c];
+                if (r <= c) cv[q] = a.band[(int64_t)(2 * k + r - c) * n + s1 - k + c];
+                fv[q] = (r > c) ? a.Lc[(base + c) * CP + (r - c)] : a.Uc[(base + c) * CP + (c - r)];
+                gv[q] = cn[(k - 1 - r) * k + (k - 1 - c)];
+            }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int q = 0; q < QB; ++q) {
+            const int r = rb + gr0 + grs * q;
+            if (gact && r < k) {
+                const int e = r * k + c;
+                a.B[ikk + e] = (T)bv[q];
+                a.C[ikk + e] = (T)cv[q];
+                X[e] = (T)bv[q];
+                Y[e] = (T)cv[q];
+                F[e] = fv[q];
+                G[e] = gv[q];
+            }
+        }
+    }
+    __syncthreads();
+    for (int c = tid; c < k; c += 256) gi[c] = T(1) / G[c * k + c];
+    __syncthreads();
+
+    // (b) V = U_bb^{-1} (L_bb^{-1} B_i) in X, W = L'_tt^{-1} (U'_tt^{-1} C_{i+1}) in Y
+    // a team thread owns column tc and the rows congruent to tr0 modulo
+    // trs = floor(128 / K) (threads past trs*K idle), so no step divides
+    const bool vteam = tid < 128;
+    const int tt = vteam ? tid : tid - 128;
+    const int trs = 128 / k;
+    const int tc = tt % k, tr0 = tt / k;
+    const bool tact = tr0 < trs;
+    // unit triangles: V forward with L_bb (step s: pivot row s), W backward
+    // with U'_tt (pivot row k-1-s)
+    for (int s = 0; s + 1 < k; ++s) {
+        if (tact) {
+            if (vteam) {
+                const int c = s;
+                const T xc = X[c * k + tc];
+                for (int r = c + 1 + tr0; r < k; r += trs)
+                    X[r * k + tc] = fma(-F[r * k + c], xc, X[r * k + tc]);
+            } else {
+                const int c = k - 1 - s;
+                const T yc = Y[c * k + tc];
+                for (int r = tr0; r < c; r += trs)
+                    Y[r * k + tc] = fma(-G[r * k + c], yc, Y[r * k + tc]);
+            }
+        }
+        __syncthreads();
+    }
+    // non-unit triangles: V backward with U_bb (pivot row k-1-s, scaled by
+    // the stored reciprocal), W forward with L'_tt (pivot row s, scaled by gi)
+    for (int s = 0; s < k; ++s) {
+        if (tact) {
+            if (vteam) {
+                const int c = k - 1 - s;
+                const T xc = X[c * k + tc] * F[c * k + c];
+                for (int r = tr0; r < c; r += trs)
+                    X[r * k + tc] = fma(-F[r * k + c], xc, X[r * k + tc]);
+                if (c + 1 < k && tr0 == 0)      // the previous pivot row
+                    X[(c + 1) * k + tc] *= F[(c + 1) * k + c + 1];
+            } else {
+                const int c = s;
+                const T yc = Y[c * k + tc] * gi[c];
+                for (int r = c + 1 + tr0; r < k; r += trs)
+                    Y[r * k + tc] = fma(-G[r * k + c], yc, Y[r * k + tc]);
+                if (c > 0 && tr0 == 0)
+                    Y[(c - 1) * k + tc] *= gi[c - 1];
+            }
+        }
+        __syncthreads();
+    }
+    if (tact && tr0 == 0) {
+        if (vteam) X[tc] *= F[0];
+        else Y[(k - 1) * k + tc] *= gi[k - 1];
+    }
+    __syncthreads();
+    for (int e = tid; e < kk; e += 256) {
+        a.V[ikk + e] = X[e];
+        a.W[ikk + e] = Y[e];
+    }
+
+    // (c) Rbar = I - W V -> F and Rbar (global); item (row pair, 4 columns)
+    {
+        const int ng = (k + 3) / 4, nr = (k + 1) / 2;
+        for (int it = tid; it < nr * ng; it += 256) {
+            const int r0 = 2 * (it / ng), c0 = 4 * (it - (it / ng) * ng);
+            const int r1 = min(r0 + 1, k - 1);
+            T acc0[4] = {T(0), T(0), T(0), T(0)}, acc1[4] = {T(0), T(0), T(0), T(0)};
+            for (int m = 0; m < k; ++m) {
+                const T y0 = Y[r0 * k + m], y1 = Y[r1 * k + m];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const T xv = X[m * k + min(c0 + q, k - 1)];
+                    acc0[q] = fma(y0, xv, acc0[q]);
+                    acc1[q] = fma(y1, xv, acc1[q]);
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int c = c0 + q;
+                if (c >= k) continue;
+                const T v0 = ((r0 == c) ? T(1) : T(0)) - acc0[q];
+                F[r0 * k + c] = v0;
+                a.Rbar[ikk + r0 * k + c] = v0;
+                if (r0 + 1 < k) {
+                    const T v1 = ((r0 + 1 == c) ? T(1) : T(0)) - acc1[q];
+                    F[(r0 + 1) * k + c] = v1;
+                    a.Rbar[ikk + (r0 + 1) * k + c] = v1;
+                }
+            }
+        }
+    }
+    __syncthreads();
+
+    // (d) Gauss-Jordan inversion of Rbar in F with row interchanges (thread
+    // (gc, gr0) as in (a))
+    for (int j = 0; j < k; ++j) {
+        if (tid < 64) {
+            T best = T(-1);
+            int p = j;
+            for (int r = j + tid; r < k; r += 64) {
+                const T v = fabs(F[r * k + j]);
+                if (v > best) { best = v; p = r; }
+            }
+            for (int o = 32; o > 0; o >>= 1) {
+                const T ob = __shfl_xor(best, o, 64);
+                const int op = __shfl_xor(p, o, 64);
+                if (ob > best || (ob == best && op < p)) { best = ob; p = op; }
+            }
+            if (tid == 0) {
+                const T pv = F[p * k + j];
+                perm_sh[j] = p;
+                p_sh = p;
+                if (pv == T(0)) a.status[1] = 2;
+                d_sh = pv != T(0) ? T(1) / pv : T(0);
+            }
+        }
+        __syncthreads();
+        const int p = p_sh;
+        const T d = d_sh;
+        // staged pivot row (the new row j, scaled) and pivot column (by the
+        // row each entry will sit in after the interchange)
+        if (tid < k) {
+            const int c = tid;
+            rowj[c] = (c == j ? T(1) : F[p * k + c]) * d;
+        } else if (tid >= 128 && tid - 128 < k) {
+            const int r = tid - 128;
+            const int src = r == j ? p : (r == p ? j : r);
+            colj[r] = F[src * k + j];
+        }
+        __syncthreads();
+        if (gact) {
+            const int c = gc;
+            const T rc = rowj[c];
+            // the row that moves to p (when p != j) is handled with row p
+            for (int r = gr0; r < k; r += grs) {
+                if (r == j) {
+                    if (p == j) F[j * k + c] = rc;
+                } else if (r == p) {
+                    const T old = c == j ? T(0) : F[j * k + c];
+                    F[j * k + c] = rc;
+                    F[p * k + c] = fma(-colj[p], rc, old);
+                } else {
+                    const T old = c == j ? T(0) : F[r * k + c];
+                    F[r * k + c] = fma(-colj[r], rc, old);
+                }
+            }
+        }
+        __syncthreads();
+    }
+    // Rinv = F P_{K-1} ... P_0 (P_j swaps j and perm[j]): undoing the
+    // interchanges from the last to the first maps output column c to column
+    // ord[c] of F
+    if (tid == 0) {
+        for (int c = 0; c < k; ++c) ord_sh[c] = c;
+        for (int j = k - 1; j >= 0; --j) {
+            const int q = perm_sh[j];
+            const int t = ord_sh[j];
+            ord_sh[j] = ord_sh[q];
+            ord_sh[q] = t;
+        }
+    }
+    __syncthreads();
+    for (int r = gr0; gact && r < k; r += grs) a.Rinv[ikk + r * k + gc] = F[r * k + ord_sh[gc]];
 }
 
 template <typename T>
 hipError_t launch_tips(const TipsArgs<T> &a, hipStream_t s)
 {
     if (a.pt.p < 2) return hipSuccess;
-    const size_t lds = 4 * (size_t)a.pt.k * a.pt.k * sizeof(T);
-    if (lds <= 128 * 1024 && 2 * a.pt.k <= 256) {
-        auto kern = k_tips<T, true>;
+    const size_t kk = (size_t)a.pt.k * a.pt.k;
+    const size_t lds = (4 * kk + 3 * (size_t)a.pt.k) * sizeof(T);
+    if (lds <= kMaxLds) {
+        auto kern = k_tips_lds<T>;
         hipError_t e = hipFuncSetAttribute((const void *)kern,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(kern, dim3(a.pt.p - 1), dim3(256), lds, s, a);
     } else {
-        hipLaunchKernelGGL((k_tips<T, false>), dim3(a.pt.p - 1), dim3(256), 0, s, a);
+        hipLaunchKernelGGL(k_tips_global<T>, dim3(a.pt.p - 1), dim3(256), 0, s, a);
     }
     return hipGetLastError();
 }
