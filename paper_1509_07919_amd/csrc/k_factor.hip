@@ -288,18 +288,18 @@ __global__ __launch_bounds__(NT) void k_banded_lu(LuArgs<T> a)
 //
 // The same factorization, B pivots per panel.  The active window of the block
 // -- rows and columns j0 .. j0+K+B-1 -- is a (K+B) x (K+B) array in LDS,
-// double-buffered.  Per panel (three barriers):
-//   1. K threads form U12 = L11^{-1} A12 (B x K), one column each;
-//   2. all threads form the next panel's B columns of the next window (the
-//      rank-B Schur update A22 -= L21 U12 restricted to them, entering
+// double-buffered.  On entering panel p its first B columns are factored and
+// its U12 = L11^{-1} A12 is formed.  Per panel (two barriers):
+//   1. all threads form the next window's first B columns and first B rows
+//      (the rank-B Schur update A22 -= L21 U12 restricted to them, entering
 //      entries elsewhere);
-//   3. wave 0 factors that panel in registers (one row per lane, pivot rows
-//      broadcast with v_readlane, the same boosting rule) while the other
-//      waves apply the rest of the update, writing straight into the other
-//      buffer shifted by (B, B) so the window slides for free, copy the
-//      entering rows and columns from the LDS stage, and write the panel's L
-//      columns and U rows to HBM (look-ahead: the panel factorization is off
-//      the critical path).
+//   2. wave 0 factors the next panel in registers (one row per lane, pivot
+//      rows broadcast with v_readlane, the same boosting rule) and forms its
+//      U12, while the other waves apply the rest of the update, writing
+//      straight into the other buffer shifted by (B, B) so the window slides
+//      for free, copy the entering rows and columns from the LDS stage, and
+//      write the panel's L columns and U rows to HBM (look-ahead: the panel
+//      factorization and U12 are off the critical path).
 // Row r of block i appears at window row r - j0 for the LU; the UL runs the
 // same code on the reversed block.
 template <typename T, int B, int S, int NT, int RPL>
@@ -427,28 +427,47 @@ __global__ __launch_bounds__(NT) void k_banded_lu_blk(LuArgs<T> a)
             }
         }
     };
-    // entry (r, c) of the next window with r >= K or c >= K: an untouched
-    // entry of A from the stage of chunk e0/S (global (j1+r, j1+c), entering
-    // index j0 + max(r, c) - K, delta = r - c)
-    auto entering = [&](const T *stg, int64_t j0_, int64_t e0_, int r, int c) -> T {
-        const int delta = r - c;
-        const int so = (int)((j0_ + max(r, c) - k) - (e0_ / S) * S);      // in [0, S)
-        const int qrow = min(max(delta + k, -1), W2);
-        return stg[qrow * S + so];
-    };
-    // Per-thread work items of the update waves that are the same for every
-    // panel.  3b: entering entries of the next window outside its first B
-    // columns -- rows K..KB-1 x columns B..KB-1, and rows 0..K-1 x columns
-    // max(K, B)..KB-1 -- as (window offset, stage offset less the panel's
-    // offset inside its chunk).  3c: (pivot t, offset m) of the outputs.
+    // Per-thread work items that are the same for every panel.
+    //   3L (all threads): the next window's first B columns (rows 0..KB-1)
+    //     and first B rows (columns B..KB-1).  An entry (r, c) of the next
+    //     window is a Schur update of the current window's (B+r, B+c) when
+    //     r, c < K, else an entering entry of A.  Kept as (window offset,
+    //     current-window row offset and column for the Schur update, or the
+    //     stage offset less the panel's offset inside its chunk).
+    //   3b (update waves): the other entering entries of the next window,
+    //     rows max(K, B)..KB-1 x columns B..KB-1 and rows B..K-1 x columns
+    //     max(K, B)..KB-1, as (window offset, stage offset).
+    //   3c (update waves): (pivot t, offset m) of the outputs.
+    constexpr int NIL = ((KMAX + B) * B + B * KMAX + NT - 1) / NT;
     constexpr int NTR_ = NT - 64;
     constexpr int NIB = (2 * B * KMAX + NTR_ - 1) / NTR_;
     constexpr int NIC = (B * (KMAX + 1) + NTR_ - 1) / NTR_;
+    int il_dst[NIL], il_row[NIL], il_col[NIL];   // il_row < 0: entering, stage offset -1-il_row-S
     int eb_dst[NIB], eb_src[NIB], oc_t[NIC], oc_m[NIC];
     {
+#pragma unroll
+        for (int i = 0; i < NIL; ++i) {
+            const int idx = tid + NT * i;
+            il_dst[i] = -1;
+            il_row[i] = il_col[i] = 0;
+            if (idx < KB * B + B * k) {
+                int r, c;
+                if (idx < KB * B) { r = idx / B; c = idx % B; }
+                else { const int q2 = idx - KB * B; r = q2 / k; c = B + q2 % k; }
+                il_dst[i] = r * WP + c;
+                if (r < k && c < k) {
+                    il_row[i] = (B + r) * WP;
+                    il_col[i] = B + c;
+                } else {
+                    // stage offset + S >= 0 (row q = -1 is the zero row)
+                    const int qrow = min(max(r - c + k, -1), W2);
+                    il_row[i] = -1 - ((qrow + 1) * S + max(r, c) - k);
+                }
+            }
+        }
         const int tr = tid - 64;
-        const int cb0 = max(k, B);
-        const int na = B * k, nbb = k * (KB - cb0);
+        const int rlo = max(k, B), mkb = min(k, B);
+        const int na = mkb * k, nbb = max(0, k - B) * mkb;
 #pragma unroll
         for (int i = 0; i < NIB; ++i) {
             const int idx = tr + NTR_ * i;
@@ -456,8 +475,8 @@ __global__ __launch_bounds__(NT) void k_banded_lu_blk(LuArgs<T> a)
             eb_src[i] = 0;
             if (tr >= 0 && idx < na + nbb) {
                 int r, c;
-                if (idx < na) { r = k + idx / k; c = B + idx % k; }
-                else { const int q2 = idx - na; r = q2 / (KB - cb0); c = cb0 + q2 % (KB - cb0); }
+                if (idx < na) { r = rlo + idx / k; c = B + idx % k; }
+                else { const int q2 = idx - na; r = B + q2 / mkb; c = rlo + q2 % mkb; }
                 const int qrow = min(max(r - c + k, -1), W2);
                 eb_dst[i] = r * WP + c;
                 eb_src[i] = qrow * S + max(r, c) - k;
@@ -471,6 +490,26 @@ __global__ __launch_bounds__(NT) void k_banded_lu_blk(LuArgs<T> a)
             oc_m[i] = ok ? idx % CS : 0;
         }
     }
+    // U12 = L11^{-1} A12 of window Wx (rows 0..B-1, columns B..KB-1), a
+    // column per lane of wave 0; L11 and the column are read before the
+    // substitution starts
+    auto u12 = [&](T *Wx) {
+        for (int c = B + lane; c < KB; c += 64) {
+            T u[B], l11[B][B];
+#pragma unroll
+            for (int t = 0; t < B; ++t) {
+                u[t] = Wx[t * WP + c];
+#pragma unroll
+                for (int s2 = 0; s2 < t; ++s2) l11[t][s2] = Wx[t * WP + s2];
+            }
+#pragma unroll
+            for (int t = 1; t < B; ++t)
+#pragma unroll
+                for (int s2 = 0; s2 < t; ++s2) u[t] = fma(-l11[t][s2], u[s2], u[t]);
+#pragma unroll
+            for (int t = 0; t < B; ++t) Wx[t * WP + c] = u[t];
+        }
+    };
     if (wave == 0) {                                  // panel 0
         T pv[RPL][B];
 #pragma unroll
@@ -487,6 +526,7 @@ __global__ __launch_bounds__(NT) void k_banded_lu_blk(LuArgs<T> a)
 #pragma unroll
                 for (int t = 0; t < B; ++t) win0[rr * WP + t] = pv[x][t];
         }
+        u12(win0);
     }
     __syncthreads();
     // Loop invariant: the panel columns 0..B-1 of the current window are
@@ -498,53 +538,43 @@ __global__ __launch_bounds__(NT) void k_banded_lu_blk(LuArgs<T> a)
         T *W = win0 + (pnl & 1) * KB * WP;            // current window
         T *Wn = win0 + ((pnl + 1) & 1) * KB * WP;     // next window
         const int64_t e0 = j0;                        // entering indices of this panel
-        if ((e0 % S) == 0) commit(e0 / S);
+        if ((e0 % S) == 0) {
+            // the next chunk's loads go out right after this chunk's commit,
+            // before this panel's output stores: a wait for the loads then
+            // does not also wait for fresh stores
+            commit(e0 / S);
+            prefetch(e0 / S + 1);
+            __syncthreads();                  // the stage is read in 3L
+        }
         const int nact = (int)min((int64_t)B, nb - j0);   // pivots in this panel
         const T *stg = stage + (((e0) / S) & 1) * stage_sz + S;
 
-        // 2. U12 = L11^{-1} A12 (rows 0..B-1, window columns B..KB-1); the
-        // unit lower triangle L11 and the column are read before the
-        // substitution starts
-        for (int c = B + tid; c < KB; c += NT) {
-            T u[B], l11[B][B];
-#pragma unroll
-            for (int t = 0; t < B; ++t) {
-                u[t] = W[t * WP + c];
-#pragma unroll
-                for (int s2 = 0; s2 < t; ++s2) l11[t][s2] = W[t * WP + s2];
-            }
-#pragma unroll
-            for (int t = 1; t < B; ++t)
-#pragma unroll
-                for (int s2 = 0; s2 < t; ++s2) u[t] = fma(-l11[t][s2], u[s2], u[t]);
-#pragma unroll
-            for (int t = 0; t < B; ++t) W[t * WP + c] = u[t];
-        }
-        __syncthreads();
-
-        // 3L. the next panel's columns 0..B-1 of the next window, by all
-        // threads: Schur update where r, c < K, entering entries elsewhere
+        // 3L. the next window's first B columns and first B rows, by all
+        // threads (U12 of this panel was formed with its factorization)
         if (pnl + 1 < npanel) {
-            for (int idx = tid; idx < KB * B; idx += NT) {
-                const int rr = idx / B, cb = idx - rr * B;
+            const int pofs = (int)((pnl * B) % S);
+#pragma unroll
+            for (int i = 0; i < NIL; ++i) {
+                if (il_dst[i] < 0) continue;
                 T v;
-                if (rr < k && cb < k) {
+                if (il_row[i] >= 0) {
                     // all operands are read before the first FMA (the
                     // scheduler would otherwise wait on each read in turn)
+                    const int ro = il_row[i], co = il_col[i];
                     T lr[B], uc[B];
-                    v = W[(B + rr) * WP + B + cb];
+                    v = W[ro + co];
 #pragma unroll
                     for (int t = 0; t < B; ++t) {
-                        lr[t] = W[(B + rr) * WP + t];
-                        uc[t] = W[t * WP + B + cb];
+                        lr[t] = W[ro + t];
+                        uc[t] = W[t * WP + co];
                     }
                     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
                     for (int t = 0; t < B; ++t) v = fma(-lr[t], uc[t], v);
                 } else {
-                    v = entering(stg, j0, e0, rr, cb);
+                    v = stg[-1 - il_row[i] - S + pofs];
                 }
-                Wn[rr * WP + cb] = v;
+                Wn[il_dst[i]] = v;
             }
         }
         __syncthreads();
@@ -566,19 +596,20 @@ __global__ __launch_bounds__(NT) void k_banded_lu_blk(LuArgs<T> a)
 #pragma unroll
                         for (int t = 0; t < B; ++t) Wn[rr * WP + t] = pv[x][t];
                 }
+                u12(Wn);       // rows 0..B-1 of Wn were formed in 3L
             }
         } else {
             const int wr = wave - 1, NR = NW - 1, tr = tid - 64, NTR = NT - 64;
-            // 3a. Schur update of the other columns into the next window:
-            // Wn[r-B][c-B] = W[r][c] - L21 U12 for window columns c >= 2B
-            // (rows four at a time, so the LDS reads of four rows are in
-            // flight together)
+            // 3a. Schur update of the other entries into the next window:
+            // Wn[r-B][c-B] = W[r][c] - L21 U12 for window rows and columns
+            // >= 2B (rows four at a time, so the LDS reads of four rows are
+            // in flight together)
             for (int cb = B + lane; cb < k; cb += 64) {
                 const int c = B + cb;
                 T uc[B];
 #pragma unroll
                 for (int t = 0; t < B; ++t) uc[t] = W[t * WP + c];
-                int rb = wr;
+                int rb = B + wr;                        // rows < B: formed in 3L
                 for (; rb + 3 * NR < k; rb += 4 * NR) {
                     T v[4], lr[4][B];
 #pragma unroll
@@ -608,7 +639,7 @@ __global__ __launch_bounds__(NT) void k_banded_lu_blk(LuArgs<T> a)
                 }
             }
             // 3b. entering entries of the next window outside its first B
-            // columns (items fixed per thread, set up before the loop)
+            // columns and rows (items fixed per thread, set up before the loop)
             const int pofs = (int)((pnl * B) % S);
 #pragma unroll
             for (int i = 0; i < NIB; ++i)
@@ -636,7 +667,6 @@ __global__ __launch_bounds__(NT) void k_banded_lu_blk(LuArgs<T> a)
                 }
             }
         }
-        if ((e0 % S) == 0) prefetch(e0 / S + 1);
         __syncthreads();
     }
     if (tid == 0 && nboost) atomicAdd(&a.status[0], nboost);
