@@ -11,13 +11,15 @@
 // only in the array and the direction.
 //
 // MI355X design.  One workgroup per block (or per row chunk of a block, see
-// below): wave 0 runs the dependent chain, waves 1-3 stage the coefficient
-// rows and the inputs of the coming chunks of 32 steps in LDS.  A chunk's
-// rows are one contiguous, 16-byte aligned run in HBM (row pitch CP), so it
-// is copied with 16-byte global_load_lds, 1 KiB per instruction, into one of
-// 2-4 LDS buffers (as many as fit two workgroups per CU); each loader wave
-// owns every third chunk and waits only for its own copies.  The pending sums
-// acc_{j+1..j+K} live in wave 0's VGPRs: register s, lane l holds the step
+// below): wave 0 runs the dependent chain, seven loader waves stage the
+// coefficient rows and the inputs of the coming chunks of 32 steps in LDS.
+// A chunk's rows are one contiguous, 16-byte aligned run in HBM (row pitch
+// CP), so it is copied with 16-byte global_load_lds, 1 KiB per instruction,
+// into one of up to 8 LDS buffers (as many as fit two workgroups per CU);
+// each loader wave owns every seventh chunk, has at most that one in flight
+// and waits only for its own copies.  The chain itself needs few bytes per
+// step, so what sets the pace is how many chunks are in flight per CU.
+// The pending sums acc_{j+1..j+K} live in wave 0's VGPRs: register s, lane l holds the step
 // 64*s + l counted from the start of the current 64-step block; KR = 1 +
 // ceil(K/64) registers cover the reach of step 63 of the block (63 + K), and
 // the registers shift down by one every 64 steps, so register indices stay
@@ -39,18 +41,21 @@
 
 namespace sap {
 
+// Waves per sweep workgroup: one compute wave and kSweepWaves - 1 loaders.
+constexpr int kSweepWaves = 4;
 
 // Chains the chunk states of block blk (run by the last workgroup of the
-// zero-state pass, 256 threads, K < 64): wave w sums the terms i in
-// [16w, 16w+16) of X(c)^T p for output slot m = lane.
-template <typename T, bool FWD>
+// zero-state pass, NW waves, K < 64): wave w sums the terms i in
+// [IW w, IW w + IW) of X(c)^T p for output slot m = lane, IW = 64 / NW.
+template <typename T, bool FWD, int NW>
 __device__ void chain_states(const SweepArgs<T> &a, int blk, int nchb, T *sh)
 {
+    constexpr int IW = 64 / NW;
     const int k = a.pt.k;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int64_t base = (int64_t)blk * a.nch;
     T *cur = sh;                 // [64] state entering the current chunk
-    T *part = sh + 64;           // [4][64] partial sums
+    T *part = sh + 64;           // [NW][64] partial sums
     if (nchb < 2) return;                          // one chunk: nothing to chain
     const int c0 = FWD ? 0 : nchb - 1;            // chunk whose q seeds the chain
     const int dir = FWD ? 1 : -1;
@@ -67,14 +72,14 @@ __device__ void chain_states(const SweepArgs<T> &a, int blk, int nchb, T *sh)
     auto load_x = [&](int c, T *dst) {
         const T *x = a.xf + (base + c) * k * k;
 #pragma unroll
-        for (int e = 0; e < 16; ++e) {
-            const int i = 16 * wave + e;
+        for (int e = 0; e < IW; ++e) {
+            const int i = IW * wave + e;
             dst[e] = (i < k && lane < k) ? x[i * k + lane] : T(0);
         }
     };
     __syncthreads();
     for (int g = 0; g < nlink; g += NG) {
-        T xg[NG][16], qg[NG];
+        T xg[NG][IW], qg[NG];
 #pragma unroll
         for (int j = 0; j < NG; ++j) {
             const int c = c0 + dir * (1 + g + j);
@@ -89,14 +94,21 @@ __device__ void chain_states(const SweepArgs<T> &a, int blk, int nchb, T *sh)
                 const int c = c0 + dir * (1 + g + j);       // chunk of this link
                 T s0 = T(0), s1 = T(0);
 #pragma unroll
-                for (int e = 0; e < 16; e += 2) {
-                    s0 = fma(xg[j][e], cur[16 * wave + e], s0);
-                    s1 = fma(xg[j][e + 1], cur[16 * wave + e + 1], s1);
+                for (int e = 0; e < IW; e += 2) {
+                    s0 = fma(xg[j][e], cur[IW * wave + e], s0);
+                    s1 = fma(xg[j][e + 1], cur[IW * wave + e + 1], s1);
                 }
                 part[wave * 64 + lane] = s0 + s1;
                 __syncthreads();
                 if (wave == 0) {
-                    const T v = qg[j] + ((part[lane] + part[64 + lane]) + (part[128 + lane] + part[192 + lane]));
+                    T ps[NW];
+#pragma unroll
+                    for (int w = 0; w < NW; ++w) ps[w] = part[w * 64 + lane];
+#pragma unroll
+                    for (int h = NW / 2; h >= 1; h /= 2)
+#pragma unroll
+                        for (int w = 0; w < h; ++w) ps[w] += ps[w + h];
+                    const T v = qg[j] + ps[0];
                     cur[lane] = lane < k ? v : T(0);
                     if (lane < k) a.st[(base + c + dir) * k + lane] = v;
                 }
@@ -104,6 +116,25 @@ __device__ void chain_states(const SweepArgs<T> &a, int blk, int nchb, T *sh)
             }
         }
     }
+}
+
+// End of a zero-state workgroup: the last of a block's workgroups to arrive
+// (atomic ticket) chains the block's chunk states.
+template <typename T, bool FWD, int NW>
+__device__ void chain_if_last(const SweepArgs<T> &a, int blk, int nchb, T *scratch)
+{
+    __shared__ int last_sh;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();                        // publish this chunk's q
+        const unsigned old = atomicAdd(a.ticket + blk, 1u);
+        last_sh = old == (unsigned)(a.nch - 1);
+    }
+    __syncthreads();
+    if (!last_sh) return;
+    __threadfence();                            // see every chunk's q
+    chain_states<T, FWD, NW>(a, blk, nchb, scratch);
+    if (threadIdx.x == 0) a.ticket[blk] = 0u;   // ready for the next sweep
 }
 
 // Rows of one staged chunk, and the LDS of a sweep workgroup: nbuf staging
@@ -114,12 +145,15 @@ template <typename T>
 static size_t sweep_lds_bytes(int cp, int nbuf)
 {
     const size_t b = ((size_t)nbuf * kSweepRows * cp + (size_t)nbuf * kSweepRows) * sizeof(T);
-    return b > 320 * sizeof(T) ? b : 320 * sizeof(T);   // chain_states scratch
+    const size_t chain = (size_t)64 * (kSweepWaves + 1) * sizeof(T);   // chain_states scratch
+    return b > chain ? b : chain;
 }
 
 template <typename T, int KR, bool FWD, bool DIAG, int PH>
-__global__ __launch_bounds__(256, 2) void k_sweep(SweepArgs<T> a, int nbuf)
+// two workgroups per CU: kSweepWaves / 2 waves per SIMD
+__global__ __launch_bounds__(64 * kSweepWaves, kSweepWaves / 2) void k_sweep(SweepArgs<T> a, int nbuf)
 {
+    constexpr int NL = kSweepWaves - 1;               // loader waves
     constexpr int S = kSweepRows;
     static_assert(S == 32, "a chunk is half a 64-step block");
     static_assert(KR >= 2, "ring must cover 64 + K slots");
@@ -148,7 +182,7 @@ __global__ __launch_bounds__(256, 2) void k_sweep(SweepArgs<T> a, int nbuf)
     // the zero-state pass has nothing to run for the last chunk of a sweep,
     // but its workgroup still takes part in the block's ticket
     const int nchunks = (PH == SWEEP_ZERO_STATE && !passes) ? 0 : (int)((nst + S - 1) / S);
-    // chunks staged ahead of the one being swept (nbuf is 2..4)
+    // chunks staged ahead of the one being swept (nbuf is 2..NL+1)
     const int depth = nbuf - 1;
     const T *dtop = (a.dtop && blk > 0) ? a.dtop + (int64_t)blk * k : nullptr;
     const T *dbot = (a.dbot && blk < a.pt.p - 1) ? a.dbot + (int64_t)blk * k : nullptr;
@@ -162,7 +196,7 @@ __global__ __launch_bounds__(256, 2) void k_sweep(SweepArgs<T> a, int nbuf)
 
     if (wave != 0) {
         // ------------------------------------------------------ loaders
-        // Loader wave lw owns the chunks t = lw (mod 3).  A chunk is one
+        // Loader wave lw owns the chunks t = lw (mod NL).  A chunk is one
         // contiguous, 16-byte aligned run of cnt*CP entries in HBM, copied
         // straight into LDS with 16-byte global_load_lds (1 KiB per
         // instruction), together with its inputs.  The owner waits for its
@@ -215,16 +249,29 @@ __global__ __launch_bounds__(256, 2) void k_sweep(SweepArgs<T> a, int nbuf)
                 vst[(t % nbuf) * S + lane] = lane < cnt ? vin * d : T(0);
             }
         };
+        // A zero-state chunk in the middle of a block will have its transfer
+        // matrix X read by the block's chaining workgroup: touch its lines
+        // now so that read hits the L2 (a block's chunks share blockIdx mod
+        // P, hence the XCD when P is a multiple of the XCD count).
+        T pf = T(0);
+        if (PH == SWEEP_ZERO_STATE && passes && receives) {
+            const int64_t xbytes = (int64_t)k * k * (int64_t)sizeof(T);
+            const int64_t off = (int64_t)(lw * 64 + lane) * 128;
+            if (off < xbytes)
+                pf = *reinterpret_cast<const T *>(
+                    reinterpret_cast<const unsigned char *>(a.xf + ((int64_t)blk * a.nch + ch) * k * k) + off);
+        }
         if (lw < depth && lw < nchunks) issue(lw);
         for (int t = 0; t < nchunks; ++t) {
-            if (t % 3 == lw) {
+            if (t % NL == lw) {
                 __builtin_amdgcn_s_waitcnt(0);        // this wave's copies of chunk t
                 finish(t);
             }
             __syncthreads();                          // chunk t staged; chunk t-1 swept
             const int tn = t + depth;                 // goes to the buffer of chunk t-1
-            if (tn < nchunks && tn % 3 == lw) issue(tn);
+            if (tn < nchunks && tn % NL == lw) issue(tn);
         }
+        asm volatile("" ::"v"(pf));                   // keeps the prefetch load
     } else {
         // ------------------------------------------------------- compute wave
         // Steps run in groups of G; the KR coefficients each lane pushes for
@@ -323,19 +370,250 @@ __global__ __launch_bounds__(256, 2) void k_sweep(SweepArgs<T> a, int nbuf)
         }
     }
     if (PH != SWEEP_ZERO_STATE) return;
-    // ------------------------------------------- ticket: last one chains
-    __shared__ int last_sh;
-    __syncthreads();
-    if (tid == 0) {
-        __threadfence();                        // publish this chunk's q
-        const unsigned old = atomicAdd(a.ticket + blk, 1u);
-        last_sh = old == (unsigned)(a.nch - 1);
+    chain_if_last<T, FWD, kSweepWaves>(a, blk, nchb, stage);
+}
+
+// ------------------------------------------------ circular form, K <= 56
+// The same chain with the pending sums in ONE register per lane: lane l
+// holds the step j with j = l (mod 64), a ring of 64 slots that covers the
+// K + 1 live sums when K < 64.  Step u pushes x_u to lane l with the
+// coefficient of offset m = (l - u) mod 64, which is zero unless 1 <= m <= K.
+// Loader waves copy a chunk's compact rows into LDS with 16-byte
+// global_load_lds as above, then rotate each row into that lane order: lane
+// m reads offset m of the row (offset 0 and offsets past K read the row's
+// zero slot K+1) and writes it to lane (u + m) mod 64 of the step's 64-entry
+// line, so every line is written whole, zeros included.  The compute wave
+// then reads one LDS word per step at a fixed offset, with no index
+// arithmetic: per step one FMA for x_u, the v_readlane broadcast and one FMA
+// per lane.  A lane's sum is final once its step is reached and receives
+// nothing more until step u + 64 - K starts the next use of the slot; so
+// every G = 8 steps the lanes of the group's steps take their outputs and
+// clear their slots, which needs G <= 64 - K.
+constexpr int kCircMaxK = 56;
+constexpr int kCircG = 8;
+template <typename T>
+constexpr int circ_waves() { return sizeof(T) == 8 ? 4 : 8; }   // one compute wave, the rest load
+template <typename T>
+static size_t circ_lds_bytes(int cp)
+{
+    constexpr int NS = circ_waves<T>() - 1;           // one staging buffer per loader
+    // [NS][S][CP] staged rows, [2][S][64] rotated lines, [2][S] v*d and [2][S] d
+    const size_t b = ((size_t)NS * kSweepRows * cp + (size_t)2 * kSweepRows * 64 + 4 * kSweepRows) * sizeof(T);
+    const size_t chain = (size_t)64 * (circ_waves<T>() + 1) * sizeof(T);
+    return b > chain ? b : chain;
+}
+
+template <typename T, bool FWD, bool DIAG, int PH>
+__global__ __launch_bounds__(64 * circ_waves<T>(), circ_waves<T>() / 2) void k_sweep_circ(SweepArgs<T> a)
+{
+    constexpr int S = kSweepRows;
+    constexpr int G = kCircG;
+    constexpr int NW = circ_waves<T>();
+    constexpr int NL = NW - 1;
+    static_assert(S % (2 * G) == 0, "groups tile the chunk");
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int k = a.pt.k;
+    const int CP = coef_pitch(k, (int)sizeof(T));
+    T *gsh = reinterpret_cast<T *>(smem_raw);         // [2][S][64]
+    T *vst = gsh + 2 * S * 64;                        // [2][S]
+    T *dsh = vst + 2 * S;                             // [2][S]
+    T *stage = dsh + 2 * S;                           // [NL][S][CP], 16-byte aligned
+
+    const int blk = PH == SWEEP_WHOLE ? (int)blockIdx.x : (int)(blockIdx.x % a.pt.p);
+    const int ch = PH == SWEEP_WHOLE ? 0 : (int)(blockIdx.x / a.pt.p);
+    const int64_t s0 = a.pt.starts[blk];
+    const int64_t nb = a.pt.starts[blk + 1] - s0;
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6;
+    const int lane = tid & 63;
+    const int nchb = PH == SWEEP_WHOLE ? 1 : (int)((nb + a.clen - 1) / a.clen);
+    const int64_t r0 = PH == SWEEP_WHOLE ? 0 : min((int64_t)ch * a.clen, nb);
+    const int64_t r1 = PH == SWEEP_WHOLE ? nb : min(r0 + a.clen, nb);
+    const int64_t nst = r1 - r0;
+    const bool passes = ch < nchb && (FWD ? ch + 1 < nchb : ch > 0);
+    const bool receives = ch < nchb && (FWD ? ch > 0 : ch + 1 < nchb);
+    if (PH == SWEEP_FROM_STATE && ch >= nchb) return;
+    const int nchunks = (PH == SWEEP_ZERO_STATE && !passes) ? 0 : (int)((nst + S - 1) / S);
+    const T *dtop = (a.dtop && blk > 0) ? a.dtop + (int64_t)blk * k : nullptr;
+    const T *dbot = (a.dbot && blk < a.pt.p - 1) ? a.dbot + (int64_t)blk * k : nullptr;
+    auto row_of = [&](int64_t t) -> int64_t { return FWD ? r0 + t : r1 - 1 - t; };
+    auto ridx = [&](int uc) { return FWD ? uc : S - 1 - uc; };
+    auto count = [&](int t) { return (int)min((int64_t)S, nst - (int64_t)t * S); };
+
+    if (wave != 0) {
+        // ------------------------------------------------------ loaders
+        // Loader wave lw owns the chunks t = lw (mod NL) and its staging
+        // buffer lw; it has at most one chunk in flight.  After its copies of
+        // chunk t land it rotates the rows into the line buffer t mod 2
+        // (free: the compute wave finished chunk t-2 before the previous
+        // barrier), stores d and v*d and meets the compute wave at the
+        // barrier before chunk t; then it refills its staging buffer with
+        // chunk t + NL, off that critical path.
+        const int lw = __builtin_amdgcn_readfirstlane(wave - 1);
+        T *sbuf = stage + (size_t)lw * S * CP;
+        T pf = T(0);
+        if (PH == SWEEP_ZERO_STATE && passes && receives) {
+            // the chaining workgroup will read this chunk's transfer matrix:
+            // touch its lines so that read hits the L2
+            const int64_t xbytes = (int64_t)k * k * (int64_t)sizeof(T);
+            const int64_t off = (int64_t)(lw * 64 + lane) * 128;
+            if (off < xbytes)
+                pf = *reinterpret_cast<const T *>(
+                    reinterpret_cast<const unsigned char *>(a.xf + ((int64_t)blk * a.nch + ch) * k * k) + off);
+        }
+        T vin = T(0);
+        auto issue = [&](int t) {
+            const int cnt = count(t);
+            const int64_t rlo = FWD ? r0 + (int64_t)t * S : r1 - (int64_t)t * S - cnt;
+            const unsigned char *src =
+                reinterpret_cast<const unsigned char *>(a.F + (s0 + rlo) * CP);
+            unsigned char *dst = reinterpret_cast<unsigned char *>(sbuf + (FWD ? 0 : S - cnt) * CP);
+            const int nbytes = cnt * CP * (int)sizeof(T);
+            for (int q = 0; q * 1024 < nbytes; ++q) {
+                const int off = q * 1024 + lane * 16;
+                if (off < nbytes)
+                    __builtin_amdgcn_global_load_lds(
+                        (const void *)(src + off),
+                        (__attribute__((address_space(3))) void *)(dst + q * 1024), 16, 0, 0);
+            }
+            vin = T(0);
+            if (lane < cnt) {
+                const int64_t r = row_of((int64_t)t * S + lane);
+                if (a.xin) {
+                    double x = a.xin[s0 + r];
+                    if (dtop && r < k) x += (double)dtop[r];
+                    if (dbot && r >= nb - k) x += (double)dbot[r - (nb - k)];
+                    vin = (T)x;
+                } else {
+                    T x = a.tin[s0 + r];
+                    if (dtop && r < k) x += dtop[r];
+                    if (dbot && r >= nb - k) x += dbot[r - (nb - k)];
+                    vin = x;
+                }
+            }
+        };
+        // offset this lane reads from every row: m = lane, or the zero slot
+        // K+1 for m = 0 and m > K
+        const int mi = (int)min((unsigned)(lane - 1), (unsigned)k) + 1;
+        auto finish = [&](int t) {
+            const int cnt = count(t);
+            const int lu = lane + ((t * S) & 63);
+            T *g = gsh + (t & 1) * S * 64;
+            // all reads first (rows past the chunk's end hold stale data and
+            // are written as zeros), so their latencies overlap
+            T v[S];
+#pragma unroll
+            for (int uc = 0; uc < S; ++uc) v[uc] = sbuf[ridx(uc) * CP + mi];
+#pragma unroll
+            for (int uc = 0; uc < S; ++uc) g[uc * 64 + ((lu + uc) & 63)] = uc < cnt ? v[uc] : T(0);
+            if (lane < S) {
+                // steps past the chunk's end get d = 0 and v*d = 0: x = 0
+                const T d = lane < cnt ? (DIAG ? sbuf[ridx(lane) * CP] : T(1)) : T(0);
+                vst[(t & 1) * S + lane] = vin * d;
+                dsh[(t & 1) * S + lane] = d;
+            }
+        };
+        if (lw < nchunks) issue(lw);
+        for (int t = 0; t < nchunks; ++t) {
+            const bool own = t % NL == lw;
+            if (own) {
+                __builtin_amdgcn_s_waitcnt(0);        // this wave's copies of chunk t
+                finish(t);
+            }
+            __syncthreads();                          // chunk t rotated; chunk t-1 swept
+            // the staging buffer was read before the barrier: refill it
+            if (own && t + NL < nchunks) issue(t + NL);
+        }
+        asm volatile("" ::"v"(pf));                   // keeps the prefetch load
+    } else {
+        // ------------------------------------------------------- compute wave
+        T acc = (PH == SWEEP_FROM_STATE && receives && lane < k)
+                    ? -a.st[((int64_t)blk * a.nch + ch) * k + lane] : T(0);
+        T dl = T(0), vdl = T(0), xo = T(0);
+        for (int t = 0; t < nchunks; ++t) {
+            __syncthreads();                          // chunk t rotated
+            const T *g = gsh + (t & 1) * S * 64 + lane;
+            const int ub = (t * S) & 63;
+            const int cnt = count(t);
+            if (lane >= ub && lane < ub + S) {
+                dl = dsh[(t & 1) * S + lane - ub];
+                vdl = vst[(t & 1) * S + lane - ub];
+            }
+            T ca[G], cb[G];
+            auto load = [&](int u0, T (&c)[G]) {
+#pragma unroll
+                for (int e = 0; e < G; ++e) c[e] = g[(u0 + e) * 64];
+            };
+            auto run = [&](int u0, const T (&c)[G]) {
+#pragma unroll
+                for (int e = 0; e < G; ++e) {
+                    const T x = fma(acc, dl, vdl);           // x_u in lane u (acc = -pending)
+                    const T xb = lane_bcast(x, ub + u0 + e);
+                    acc = fma(-c[e], xb, acc);
+                }
+                // the group's lanes take their outputs and free their slots
+                const int d = lane - ub - u0;
+                if ((unsigned)d < (unsigned)G && u0 + d < cnt) {
+                    xo = fma(acc, dl, vdl);
+                    acc = T(0);
+                }
+            };
+            load(0, ca);
+#pragma unroll
+            for (int u0 = 0; u0 < S; u0 += 2 * G) {
+                load(u0 + G, cb);
+                run(u0, ca);
+                if (u0 + 2 * G < S) load(u0 + 2 * G, ca);
+                run(u0 + G, cb);
+            }
+            if (PH != SWEEP_ZERO_STATE && lane >= ub && lane < ub + cnt) {
+                const int64_t r = s0 + row_of((int64_t)t * S + lane - ub);
+                if (a.dout) a.dout[r] = (double)xo;
+                else a.tout[r] = xo;
+            }
+        }
+        if (PH == SWEEP_ZERO_STATE && nchunks > 0) {
+            // outgoing state: the pending sums of the K steps after the chunk,
+            // step nst + m in lane (nst + m) mod 64
+            const int m = (lane - (int)(nst & 63)) & 63;
+            if (m < k) a.q[((int64_t)blk * a.nch + ch) * k + m] = -acc;
+        }
     }
-    __syncthreads();
-    if (!last_sh) return;
-    __threadfence();                            // see every chunk's q
-    chain_states<T, FWD>(a, blk, nchb, stage);
-    if (tid == 0) a.ticket[blk] = 0u;           // ready for the next sweep
+    if (PH != SWEEP_ZERO_STATE) return;
+    chain_if_last<T, FWD, NW>(a, blk, nchb, gsh);
+}
+
+template <typename T, bool FWD, bool DIAG, int PH>
+static hipError_t launch_circ_ph(const SweepArgs<T> &a, hipStream_t s)
+{
+    const unsigned grid = PH == SWEEP_WHOLE ? a.pt.p : a.pt.p * a.nch;
+    const size_t lds = circ_lds_bytes<T>(coef_pitch(a.pt.k, (int)sizeof(T)));
+    if (lds > kMaxLds) return hipErrorInvalidValue;
+    auto kern = k_sweep_circ<T, FWD, DIAG, PH>;
+    hipError_t e = hipFuncSetAttribute((const void *)kern,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * circ_waves<T>()), lds, s, a);
+    return hipGetLastError();
+}
+
+template <typename T, bool FWD, bool DIAG>
+static hipError_t launch_circ_cfg(const SweepArgs<T> &a, hipStream_t s)
+{
+    if (a.phase == SWEEP_ZERO_STATE) return launch_circ_ph<T, FWD, DIAG, SWEEP_ZERO_STATE>(a, s);
+    if (a.phase == SWEEP_FROM_STATE) return launch_circ_ph<T, FWD, DIAG, SWEEP_FROM_STATE>(a, s);
+    return launch_circ_ph<T, FWD, DIAG, SWEEP_WHOLE>(a, s);
+}
+
+template <typename T>
+static hipError_t launch_circ(const SweepArgs<T> &a, hipStream_t s)
+{
+    if (a.fwd) {
+        if (a.diag) return launch_circ_cfg<T, true, true>(a, s);
+        return launch_circ_cfg<T, true, false>(a, s);
+    }
+    if (a.diag) return launch_circ_cfg<T, false, true>(a, s);
+    return launch_circ_cfg<T, false, false>(a, s);
 }
 
 template <typename T, int KR, bool FWD, bool DIAG, int PH>
@@ -343,10 +621,11 @@ static hipError_t launch_sweep_ph(const SweepArgs<T> &a, hipStream_t s)
 {
     const int cp = coef_pitch(a.pt.k, (int)sizeof(T));
     const unsigned grid = PH == SWEEP_WHOLE ? a.pt.p : a.pt.p * a.nch;
-    // deepest staging (2..4 buffers) that keeps two workgroups per CU when
-    // the grid has more than one workgroup per CU
+    // deepest staging (2..kSweepWaves buffers: each loader wave has one
+    // chunk in flight) that keeps two workgroups per CU when the grid has
+    // more than one workgroup per CU
     const size_t cap = grid > 256 ? kMaxLds / 2 : kMaxLds;
-    int nbuf = 4;
+    int nbuf = kSweepWaves;
     while (nbuf > 2 && sweep_lds_bytes<T>(cp, nbuf) > cap) --nbuf;
     const size_t lds = sweep_lds_bytes<T>(cp, nbuf);
     if (lds > kMaxLds) return hipErrorInvalidValue;
@@ -354,7 +633,7 @@ static hipError_t launch_sweep_ph(const SweepArgs<T> &a, hipStream_t s)
     hipError_t e = hipFuncSetAttribute((const void *)kern,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(256), lds, s, a, nbuf);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * kSweepWaves), lds, s, a, nbuf);
     return hipGetLastError();
 }
 
@@ -386,6 +665,7 @@ template <>
 hipError_t launch_sweep<float>(const SweepArgs<float> &a, hipStream_t s)
 {
     const int k = a.pt.k;
+    if (k <= kCircMaxK) return launch_circ<float>(a, s);
     if (k < 64) return launch_sweep_kr<float, 2>(a, s);
     if (k < 128) return launch_sweep_kr<float, 3>(a, s);
     if (k < 192) return launch_sweep_kr<float, 4>(a, s);
@@ -396,6 +676,7 @@ template <>
 hipError_t launch_sweep<double>(const SweepArgs<double> &a, hipStream_t s)
 {
     const int k = a.pt.k;
+    if (k <= kCircMaxK) return launch_circ<double>(a, s);
     if (k < 64) return launch_sweep_kr<double, 2>(a, s);
     if (k < 128) return launch_sweep_kr<double, 3>(a, s);
     if (k < 192) return launch_sweep_kr<double, 4>(a, s);
