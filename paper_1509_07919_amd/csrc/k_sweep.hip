@@ -33,9 +33,14 @@
 // Chunked form (sap_internal.h): the same chain runs over one row chunk per
 // workgroup, so a block's sweep has nch chains in flight instead of one.  The
 // zero-state pass ends by reading the K pending sums out of the register ring
-// (its outgoing state); the last workgroup of each block to finish then chains
-// p_in(c+1) = q(c) + X(c) p_in(c) over the block's chunks.  The from-state pass
-// seeds the ring with -p_in and writes the outputs.
+// (its outgoing state q(c)).  In the circular kernels below, each workgroup
+// of the from-state pass then chains the state entering its own chunk,
+// p_in(c+1) = q(c) + X(c) p_in(c), from the first chunk of its block, while
+// its first staging copies are in flight: the kernel boundary makes every
+// q visible, and no workgroup waits for another.  The ring kernel (K > 56)
+// has the last zero-state workgroup of each block (atomic ticket) chain all
+// the block's states instead.  The from-state pass seeds the ring with -p_in
+// and writes the outputs.
 #include "sap_internal.h"
 #include "dev_common.h"
 
@@ -44,11 +49,14 @@ namespace sap {
 // Waves per sweep workgroup: one compute wave and kSweepWaves - 1 loaders.
 constexpr int kSweepWaves = 4;
 
-// Chains the chunk states of block blk (run by the last workgroup of the
-// zero-state pass, NW waves, K < 64): wave w sums the terms i in
-// [IW w, IW w + IW) of X(c)^T p for output slot m = lane, IW = 64 / NW.
-template <typename T, bool FWD, int NW>
-__device__ void chain_states(const SweepArgs<T> &a, int blk, int nchb, T *sh)
+// Chains the chunk states of block blk over the first nlink links after
+// chunk c0 (the first chunk in the sweep direction), NW waves, K < 64: wave
+// w sums the terms i in [IW w, IW w + IW) of X(c)^T p for output slot
+// m = lane, IW = 64 / NW.  On return sh[0..64) holds the state entering
+// chunk c0 + dir (nlink + 1) (zero past K); STORE also writes every state
+// to a.st.
+template <typename T, bool FWD, int NW, bool STORE>
+__device__ void chain_states(const SweepArgs<T> &a, int blk, int nchb, int nlink, T *sh)
 {
     constexpr int IW = 64 / NW;
     const int k = a.pt.k;
@@ -56,15 +64,13 @@ __device__ void chain_states(const SweepArgs<T> &a, int blk, int nchb, T *sh)
     const int64_t base = (int64_t)blk * a.nch;
     T *cur = sh;                 // [64] state entering the current chunk
     T *part = sh + 64;           // [NW][64] partial sums
-    if (nchb < 2) return;                          // one chunk: nothing to chain
     const int c0 = FWD ? 0 : nchb - 1;            // chunk whose q seeds the chain
     const int dir = FWD ? 1 : -1;
-    const int nlink = nchb - 2;                    // chunks both receiving and passing on
     // the state entering chunk c0 + dir is q(c0)
-    if (tid < k) {
-        const T v = a.q[(base + c0) * k + tid];
+    if (tid < 64) {
+        const T v = tid < k ? a.q[(base + c0) * k + tid] : T(0);
         cur[tid] = v;
-        a.st[(base + c0 + dir) * k + tid] = v;
+        if (STORE && tid < k) a.st[(base + c0 + dir) * k + tid] = v;
     }
     // the transfer matrices of NG links are loaded at once, so their
     // latencies overlap; the links are then chained one after the other
@@ -110,7 +116,7 @@ __device__ void chain_states(const SweepArgs<T> &a, int blk, int nchb, T *sh)
                         for (int w = 0; w < h; ++w) ps[w] += ps[w + h];
                     const T v = qg[j] + ps[0];
                     cur[lane] = lane < k ? v : T(0);
-                    if (lane < k) a.st[(base + c + dir) * k + lane] = v;
+                    if (STORE && lane < k) a.st[(base + c + dir) * k + lane] = v;
                 }
                 __syncthreads();
             }
@@ -133,7 +139,7 @@ __device__ void chain_if_last(const SweepArgs<T> &a, int blk, int nchb, T *scrat
     __syncthreads();
     if (!last_sh) return;
     __threadfence();                            // see every chunk's q
-    chain_states<T, FWD, NW>(a, blk, nchb, scratch);
+    if (nchb >= 2) chain_states<T, FWD, NW, true>(a, blk, nchb, nchb - 2, scratch);
     if (threadIdx.x == 0) a.ticket[blk] = 0u;   // ready for the next sweep
 }
 
@@ -397,10 +403,10 @@ template <typename T>
 static size_t circ_lds_bytes(int cp)
 {
     constexpr int NS = circ_waves<T>() - 1;           // one staging buffer per loader
-    // [NS][S][CP] staged rows, [2][S][64] rotated lines, [2][S] v*d and [2][S] d
-    const size_t b = ((size_t)NS * kSweepRows * cp + (size_t)2 * kSweepRows * 64 + 4 * kSweepRows) * sizeof(T);
-    const size_t chain = (size_t)64 * (circ_waves<T>() + 1) * sizeof(T);
-    return b > chain ? b : chain;
+    // [2][S][64] rotated lines, [2][S] v*d, [2][S] d, [NW+1][64] chain
+    // scratch and [NS][S][CP] staged rows
+    return ((size_t)2 * kSweepRows * 64 + 4 * kSweepRows + (size_t)64 * (circ_waves<T>() + 1) +
+            (size_t)NS * kSweepRows * cp) * sizeof(T);
 }
 
 template <typename T, bool FWD, bool DIAG, int PH>
@@ -417,7 +423,8 @@ __global__ __launch_bounds__(64 * circ_waves<T>(), circ_waves<T>() / 2) void k_s
     T *gsh = reinterpret_cast<T *>(smem_raw);         // [2][S][64]
     T *vst = gsh + 2 * S * 64;                        // [2][S]
     T *dsh = vst + 2 * S;                             // [2][S]
-    T *stage = dsh + 2 * S;                           // [NL][S][CP], 16-byte aligned
+    T *csh = dsh + 2 * S;                             // [NW+1][64] chain scratch
+    T *stage = csh + (NW + 1) * 64;                   // [NL][S][CP], 16-byte aligned
 
     const int blk = PH == SWEEP_WHOLE ? (int)blockIdx.x : (int)(blockIdx.x % a.pt.p);
     const int ch = PH == SWEEP_WHOLE ? 0 : (int)(blockIdx.x / a.pt.p);
@@ -439,6 +446,13 @@ __global__ __launch_bounds__(64 * circ_waves<T>(), circ_waves<T>() / 2) void k_s
     auto row_of = [&](int64_t t) -> int64_t { return FWD ? r0 + t : r1 - 1 - t; };
     auto ridx = [&](int uc) { return FWD ? uc : S - 1 - uc; };
     auto count = [&](int t) { return (int)min((int64_t)S, nst - (int64_t)t * S); };
+    // The state entering this chunk, chained by the whole workgroup from the
+    // outgoing states q of the chunks before it in the sweep direction and
+    // their transfer matrices (all written by earlier launches), while the
+    // first staging copies are in flight; it lands in csh[0..64).
+    auto entering_state = [&]() {
+        chain_states<T, FWD, NW, false>(a, blk, nchb, FWD ? ch - 1 : nchb - 2 - ch, csh);
+    };
 
     if (wave != 0) {
         // ------------------------------------------------------ loaders
@@ -451,16 +465,6 @@ __global__ __launch_bounds__(64 * circ_waves<T>(), circ_waves<T>() / 2) void k_s
         // chunk t + NL, off that critical path.
         const int lw = __builtin_amdgcn_readfirstlane(wave - 1);
         T *sbuf = stage + (size_t)lw * S * CP;
-        T pf = T(0);
-        if (PH == SWEEP_ZERO_STATE && passes && receives) {
-            // the chaining workgroup will read this chunk's transfer matrix:
-            // touch its lines so that read hits the L2
-            const int64_t xbytes = (int64_t)k * k * (int64_t)sizeof(T);
-            const int64_t off = (int64_t)(lw * 64 + lane) * 128;
-            if (off < xbytes)
-                pf = *reinterpret_cast<const T *>(
-                    reinterpret_cast<const unsigned char *>(a.xf + ((int64_t)blk * a.nch + ch) * k * k) + off);
-        }
         T vin = T(0);
         auto issue = [&](int t) {
             const int cnt = count(t);
@@ -514,6 +518,7 @@ __global__ __launch_bounds__(64 * circ_waves<T>(), circ_waves<T>() / 2) void k_s
             }
         };
         if (lw < nchunks) issue(lw);
+        if (PH == SWEEP_FROM_STATE && receives) entering_state();
         for (int t = 0; t < nchunks; ++t) {
             const bool own = t % NL == lw;
             if (own) {
@@ -524,11 +529,10 @@ __global__ __launch_bounds__(64 * circ_waves<T>(), circ_waves<T>() / 2) void k_s
             // the staging buffer was read before the barrier: refill it
             if (own && t + NL < nchunks) issue(t + NL);
         }
-        asm volatile("" ::"v"(pf));                   // keeps the prefetch load
     } else {
         // ------------------------------------------------------- compute wave
-        T acc = (PH == SWEEP_FROM_STATE && receives && lane < k)
-                    ? -a.st[((int64_t)blk * a.nch + ch) * k + lane] : T(0);
+        if (PH == SWEEP_FROM_STATE && receives) entering_state();
+        T acc = (PH == SWEEP_FROM_STATE && receives) ? -csh[lane] : T(0);
         T dl = T(0), vdl = T(0), xo = T(0);
         for (int t = 0; t < nchunks; ++t) {
             __syncthreads();                          // chunk t rotated
@@ -579,8 +583,6 @@ __global__ __launch_bounds__(64 * circ_waves<T>(), circ_waves<T>() / 2) void k_s
             if (m < k) a.q[((int64_t)blk * a.nch + ch) * k + m] = -acc;
         }
     }
-    if (PH != SWEEP_ZERO_STATE) return;
-    chain_if_last<T, FWD, NW>(a, blk, nchb, gsh);
 }
 
 template <typename T, bool FWD, bool DIAG, int PH>

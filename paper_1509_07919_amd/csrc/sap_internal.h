@@ -121,9 +121,11 @@ hipError_t launch_tips(const TipsArgs<T> &a, hipStream_t s);
 // where q(c) is the output state for a zero incoming state and X(c) is the
 // K x K transfer matrix of the chunk (inputs zero), computed once per
 // factorization.  A sweep then runs in two launches: phase 1 runs every
-// chunk with a zero incoming state and writes q; the last workgroup of
-// each block to finish chains the recurrence and writes the true incoming
-// states st; phase 2 reruns every chunk from st and writes the outputs.
+// chunk with a zero incoming state and writes q; phase 2 obtains each
+// chunk's true incoming state by chaining the recurrence from the block's
+// first chunk (K <= 56: every workgroup for its own chunk, at its start;
+// larger K: the last phase-1 workgroup of each block, through st) and
+// reruns the chunk from it, writing the outputs.
 // Storage: q, st [p][nch][K]; X [p][nch][K][K] with X[c][i][m] = d p_out[m]
 // / d p_in[i] (row i contiguous in m); ticket [p] (zero between launches).
 enum SweepPhase : int { SWEEP_WHOLE = 0, SWEEP_ZERO_STATE = 1, SWEEP_FROM_STATE = 2 };
