@@ -248,35 +248,35 @@ __device__ void scalar_op(int op, const double *d, double *sc, double *host)
     }
     if (host) {
         if (publish) host[H_NRM2] = sc[S_NRM2];
+        if (op == OP_INIT) host[H_NRM0] = sc[S_NRM2];
         host[H_BREAK] = sc[S_BREAK];
     }
 }
 
-// Block-reduce up to three per-thread sums, store this block's partials and
-// let the last block to finish combine all partials in a fixed order (so the
-// result is bitwise reproducible) and run the scalar recurrence.
+// Block-reduce up to three per-thread sums and store this block's partials.
 __device__ void finish_dots(const DotArgs &a, double l0, double l1, double l2)
 {
     __shared__ double red[3][4];
-    __shared__ bool last;
     const int tid = threadIdx.x, wid = tid >> 6, lane = tid & 63;
     const double s0 = wave_sum(l0), s1 = wave_sum(l1), s2 = wave_sum(l2);
     if (lane == 0) { red[0][wid] = s0; red[1][wid] = s1; red[2][wid] = s2; }
     __syncthreads();
-    if (tid == 0) {
+    if (tid == 0)
         for (int d = 0; d < 3; ++d)
             a.partial[blockIdx.x * 3 + d] = (red[d][0] + red[d][1]) + (red[d][2] + red[d][3]);
-        __threadfence();
-        const unsigned ticket = atomicAdd(a.counter, 1u);
-        last = ticket == gridDim.x - 1;
-    }
-    __syncthreads();
-    if (!last) return;
-    __threadfence();
+}
+
+// One workgroup combines the kDotBlocks partials of the preceding launch in a
+// fixed order (so the result is bitwise reproducible) and runs the scalar
+// recurrence.  The kernel boundary makes the partials visible, so the
+// producing blocks need no fence or ticket.
+__global__ __launch_bounds__(256) void k_dots_final(DotArgs a)
+{
     __shared__ double tot[3][256];
+    const int tid = threadIdx.x;
     for (int d = 0; d < 3; ++d) {
         double s = 0.0;
-        for (int b = tid; b < (int)gridDim.x; b += 256) s += a.partial[b * 3 + d];
+        for (int b = tid; b < kDotBlocks; b += 256) s += a.partial[b * 3 + d];
         tot[d][tid] = s;
     }
     __syncthreads();
@@ -288,7 +288,6 @@ __device__ void finish_dots(const DotArgs &a, double l0, double l1, double l2)
     if (tid == 0) {
         const double dd[3] = {tot[0][0], tot[1][0], tot[2][0]};
         scalar_op(a.op, dd, a.sc, a.host);
-        *a.counter = 0u;
         __threadfence_system();
     }
 }
@@ -307,6 +306,7 @@ __global__ __launch_bounds__(256) void k_dots(DotArgs a)
 hipError_t launch_dots(const DotArgs &a, hipStream_t s)
 {
     hipLaunchKernelGGL(k_dots, dim3(kDotBlocks), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_dots_final, dim3(1), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
@@ -380,6 +380,7 @@ __global__ __launch_bounds__(256) void k_update(UpdArgs a)
 hipError_t launch_update(const UpdArgs &a, hipStream_t s)
 {
     hipLaunchKernelGGL(k_update, dim3(kDotBlocks), dim3(256), 0, s, a);
+    if (a.dots.nd > 0) hipLaunchKernelGGL(k_dots_final, dim3(1), dim3(256), 0, s, a.dots);
     return hipGetLastError();
 }
 

@@ -35,7 +35,7 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
     size_t starts, partial, status, Lc, Uc, Lr, Ur, corner, B, C, V, W, Rbar, Rlu, Rinv, piv,
-        gT, yT, dtop, dbot, kv, dpart, counter, sc, xLc, xUc, xLr, xUr, sq, sst, ticket, total;
+        gT, yT, dtop, dbot, kv, dpart, sc, xLc, xUc, xLr, xUr, sq, sst, ticket, total;
 };
 
 bool coupled_active(const sap_options &o) { return o.mode == SAP_COUPLED && o.p > 1 && o.k > 0; }
@@ -125,7 +125,6 @@ Layout layout_for(const sap_options &o)
     L.dbot = cpl ? take(sf * (size_t)p * k) : 0;
     L.kv = take(sizeof(double) * 8 * (size_t)n);
     L.dpart = take(sizeof(double) * 3 * kDotBlocks);
-    L.counter = take(64);
     L.sc = take(sizeof(double) * kScalars);
     const Chunking ck = chunking_for(o);
     if (ck.nch >= 2) {
@@ -304,7 +303,6 @@ DotArgs dot_args(sap_handle h, int op)
     DotArgs d{};
     d.n = h->opt.n;
     d.partial = h->ptr<double>(h->L.dpart);
-    d.counter = h->ptr<unsigned>(h->L.counter);
     d.sc = h->ptr<double>(h->L.sc);
     d.host = h->d_slots;
     d.op = op;
@@ -363,6 +361,17 @@ int read_factor_status(sap_handle h, hipStream_t s, int32_t *nboost, int32_t *si
         if (rc_ < 0) return rc_;  \
     } while (0)
 
+// Factorization times from its events; called once the solve has synchronized
+// (the factorization finished before it), so it adds no host round trip.
+static void collect_factor_times(sap_handle h)
+{
+    if (h->t_factor >= 0.0f) return;
+    if (hipEventSynchronize(h->ev[2]) != hipSuccess) return;
+    (void)hipEventElapsedTime(&h->t_factor, h->ev[0], h->ev[2]);
+    (void)hipEventElapsedTime(&h->t_lu, h->ev[0], h->ev[1]);
+    (void)hipEventElapsedTime(&h->t_tips, h->ev[1], h->ev[2]);
+}
+
 // Left-preconditioned BiCGStab(2), x0 = 0.
 int krylov(sap_handle h, int trans, const double *b, double *x, double tol, int32_t maxit,
            hipStream_t s, sap_stats *st)
@@ -379,14 +388,6 @@ int krylov(sap_handle h, int trans, const double *b, double *x, double tol, int3
 
     sap_stats loc{};
     HIP_TRY(hipEventRecord(h->ev[3], s));
-    int32_t nboost = 0, singular = 0;
-    TRY(read_factor_status(h, s, &nboost, &singular));
-    loc.n_boosted = nboost;
-    if (singular) {
-        if (st) *st = loc;
-        return fail(SAP_ERR_SINGULAR, singular == 1 ? "zero pivot in a diagonal block (boosting disabled)"
-                                                    : "singular reduced matrix Rbar");
-    }
     double *r0 = h->kvec(KV_R0), *r1 = h->kvec(KV_R1), *r2 = h->kvec(KV_R2);
     double *u0 = h->kvec(KV_U0), *u1 = h->kvec(KV_U1), *u2 = h->kvec(KV_U2);
     double *rt = h->kvec(KV_RT), *t = h->kvec(KV_T);
@@ -394,14 +395,24 @@ int krylov(sap_handle h, int trans, const double *b, double *x, double tol, int3
     const int k = h->opt.k;
     double nrm2 = 0, brk = 0;
 
+    // the factorization's status and ||b|| in one host round trip
+    HIP_TRY(hipMemcpyAsync(h->h_status, h->ptr<int>(h->L.status), 2 * sizeof(int32_t),
+                           hipMemcpyDeviceToHost, s));
     TRY(dots(h, OP_NORM, {{b, b}}, s));
     TRY(sync_read(h, s, &nrm2, &brk));
+    loc.n_boosted = h->h_status[0];
+    if (const int32_t singular = h->h_status[1]) {
+        if (st) *st = loc;
+        return fail(SAP_ERR_SINGULAR, singular == 1 ? "zero pivot in a diagonal block (boosting disabled)"
+                                                    : "singular reduced matrix Rbar");
+    }
     const double bnorm = std::sqrt(nrm2);
     HIP_TRY(launch_fill(x, 0.0, n, s));
     auto finish = [&](int code, const char *msg) {
         HIP_TRY(hipEventRecord(h->ev[4], s));
         HIP_TRY(hipEventSynchronize(h->ev[4]));
         HIP_TRY(hipEventElapsedTime(&loc.t_solve_ms, h->ev[3], h->ev[4]));
+        collect_factor_times(h);
         loc.t_factor_ms = h->t_factor;
         loc.t_lu_ms = h->t_lu;
         loc.t_tips_ms = h->t_tips;
@@ -416,23 +427,33 @@ int krylov(sap_handle h, int trans, const double *b, double *x, double tol, int3
         return finish(SAP_OK, "");
     }
 
-    // r0 = M^{-1} b, rt = r0, u0 = 0, scalars reset
+    // r0 = M^{-1} b, rt = r0, u0 = 0, scalars reset; the norm of r0 is read
+    // at the first exit test (host slot H_NRM0), saving a round trip
     TRY(precond(h, trans, b, r0, s));
     TRY(update(h, UPD_RESTART, x, OP_INIT, 2, s));
-    TRY(sync_read(h, s, &nrm2, &brk));
-    const double pnorm0 = std::sqrt(nrm2);
-    double thr = tol * pnorm0;
+    double pnorm0 = 0.0, thr = 0.0, pstart = 0.0;
+    bool started = false;          // H_NRM0 of the last (re)start read
+    double tn_restart = 0.0;       // true residual norm at the last restart
     int napply = 0;
     // Reliable updates (Sleijpen and van der Vorst 1996): with FP32 factors
     // the recursive residual stops tracking the true one near FP32 accuracy,
     // so once it has dropped by this factor since the last (re)start the true
     // residual is tested and the iteration restarted from it.
     const double reliable = h->fp32 ? 1e-4 : 0.0;
-    double pstart = pnorm0;
 
     // exit test: returns 1 = converged, 2 = restarted, 0 = continue, < 0 error
     auto exit_test = [&]() -> int {
         TRY(sync_read(h, s, &nrm2, &brk));
+        if (!started) {
+            pstart = std::sqrt(h->h_slots[H_NRM0]);
+            if (tn_restart == 0.0) {          // the initial start
+                pnorm0 = pstart;
+                thr = tol * pnorm0;
+            } else {
+                thr = tol * bnorm * pstart / tn_restart;
+            }
+            started = true;
+        }
         if (brk != 0.0) return SAP_ERR_BREAKDOWN;
         if (!std::isfinite(nrm2)) return SAP_ERR_BREAKDOWN;
         const double pn = std::sqrt(nrm2);
@@ -452,9 +473,8 @@ int krylov(sap_handle h, int trans, const double *b, double *x, double tol, int3
         ++napply;
         ++loc.restarts;
         TRY(update(h, UPD_RESTART, x, OP_INIT, 2, s));
-        TRY(sync_read(h, s, &nrm2, &brk));
-        pstart = std::sqrt(nrm2);
-        thr = tol * bnorm * pstart / tn;
+        started = false;                                         // read at the next test
+        tn_restart = tn;
         return 2;
     };
 
@@ -667,7 +687,6 @@ int sap_factor(sap_handle h, const double *a_band, void *stream)
     if (!h->starts_uploaded) {
         HIP_TRY(hipMemcpyAsync(h->ptr<int64_t>(h->L.starts), h->h_starts,
                                sizeof(int64_t) * (h->opt.p + 1), hipMemcpyHostToDevice, s));
-        HIP_TRY(hipMemsetAsync(h->ptr<unsigned>(h->L.counter), 0, 64, s));
         // the zero slots after each factor row are never written by a kernel
         const size_t fb = (h->fp32 ? 4 : 8) * (size_t)h->opt.n *
                           coef_pitch(h->opt.k, h->fp32 ? 4 : 8);
@@ -690,20 +709,10 @@ int sap_factor(sap_handle h, const double *a_band, void *stream)
     return SAP_OK;
 }
 
-static void collect_factor_times(sap_handle h)
-{
-    if (h->t_factor >= 0.0f) return;
-    if (hipEventSynchronize(h->ev[2]) != hipSuccess) return;
-    (void)hipEventElapsedTime(&h->t_factor, h->ev[0], h->ev[2]);
-    (void)hipEventElapsedTime(&h->t_lu, h->ev[0], h->ev[1]);
-    (void)hipEventElapsedTime(&h->t_tips, h->ev[1], h->ev[2]);
-}
-
 int sap_solve(sap_handle h, const double *b, double *x, double tol, int32_t maxit, void *stream,
               sap_stats *st)
 {
     if (!h) return fail(SAP_ERR_INVALID, "null handle");
-    if (h->factored) collect_factor_times(h);
     return krylov(h, 0, b, x, tol, maxit, static_cast<hipStream_t>(stream), st);
 }
 
@@ -711,7 +720,6 @@ int sap_solve_adjoint(sap_handle h, const double *g, double *lambda, double tol,
                       void *stream, sap_stats *st)
 {
     if (!h) return fail(SAP_ERR_INVALID, "null handle");
-    if (h->factored) collect_factor_times(h);
     return krylov(h, 1, g, lambda, tol, maxit, static_cast<hipStream_t>(stream), st);
 }
 

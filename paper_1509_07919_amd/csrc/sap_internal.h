@@ -61,7 +61,8 @@ enum ScalarSlot : int {
 };
 
 // host-visible (pinned, mapped) result slots written by reduction kernels
-enum HostSlot : int { H_NRM2 = 0, H_BREAK = 1, H_SPARE = 2, kHostSlots = 8 };
+// H_NRM0: squared norm of the (re)started preconditioned residual (OP_INIT)
+enum HostSlot : int { H_NRM2 = 0, H_BREAK = 1, H_NRM0 = 2, kHostSlots = 8 };
 
 struct Partition {
     const int64_t *starts;   // P+1 block boundaries (device)
@@ -193,7 +194,6 @@ struct DotArgs {
     int nd;
     int64_t n;
     double *partial;         // [kDotBlocks][3]
-    unsigned *counter;       // zero before the first launch; reset by kernel
     double *sc;              // device scalars
     double *host;            // mapped pinned host slots (may be null)
     int op;
