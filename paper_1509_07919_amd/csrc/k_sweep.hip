@@ -74,7 +74,7 @@ __device__ void chain_states(const SweepArgs<T> &a, int blk, int nchb, int nlink
     }
     // the transfer matrices of NG links are loaded at once, so their
     // latencies overlap; the links are then chained one after the other
-    constexpr int NG = sizeof(T) == 8 ? 2 : 4;
+    constexpr int NG = sizeof(T) == 8 ? (STORE ? 2 : 3) : 4;
     auto load_x = [&](int c, T *dst) {
         const T *x = a.xf + (base + c) * k * k;
 #pragma unroll
