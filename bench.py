@@ -137,6 +137,10 @@ def main():
     ap.add_argument("--cpu-reps", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--precs", default="fp64,fp32")
+    ap.add_argument("--race-d", default="0.12,0.11",
+                    help="also race FP32 against FP64 factors on the same N, K, P at these "
+                         "diagonal dominances (comma list; 0 or empty: skip)")
+    ap.add_argument("--race-steps", type=int, default=5)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -242,6 +246,34 @@ def main():
         out["race"] = {"fp64_ms": round(runs["fp64"]["ms"], 4),
                        "fp32_factor_ms": round(runs["fp32"]["ms"], 4),
                        "fp32_speedup": round(runs["fp64"]["ms"] / runs["fp32"]["ms"], 3)}
+    race_ds = [float(v) for v in str(args.race_d).split(",") if v.strip() and float(v) > 0]
+    if race_ds and "fp64" in runs and "fp32" in runs:
+        # the same race where the FP64 preconditioner is no longer exact after
+        # one application, so both precisions iterate
+        out["race_weak_dominance"] = []
+        for dw in race_ds:
+            pbw = sapgen.make_problem(n, k, d=dw, seed=args.seed,
+                                      row_scale_decades=cfg["row_scale_decades"])
+            aw = torch.from_numpy(pbw.band).to(dev)
+            bw = torch.from_numpy(pbw.b).to(dev)
+            wargs = argparse.Namespace(**vars(args))
+            wargs.steps, wargs.warmup = args.race_steps, 1
+            rw = {}
+            for prec in ("fp64", "fp32"):
+                ms, stats, _, xs = run_gpu(wargs, prec, pbw, aw, bw)
+                st = stats[-1]
+                rw[prec] = {"ms": round(ms, 4), "iters": st.iters, "restarts": st.restarts,
+                            "converged": bool(st.converged), "rel_resid_true": st.rel_resid_true,
+                            "t_factor_ms": round(st.t_factor_ms, 4),
+                            "t_solve_ms": round(st.t_solve_ms, 4),
+                            "rel_err_vs_xtrue": float(np.linalg.norm(xs - pbw.x_true)
+                                                      / np.linalg.norm(pbw.x_true))}
+            out["race_weak_dominance"].append({
+                "config": {"n": n, "k": k, "p": cfg["p"], "mode": cfg["mode"], "d": dw,
+                           "tol": cfg["tol"], "seed": args.seed},
+                "steps": args.race_steps, "fp64": rw["fp64"], "fp32": rw["fp32"],
+                "fp32_speedup": round(rw["fp64"]["ms"] / rw["fp32"]["ms"], 3)})
+            del aw, bw
     if args.copy_calibration:
         src_t = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
         dst_t = torch.empty_like(src_t)

@@ -31,8 +31,11 @@ namespace sap {
 
 // ---------------------------------------------------------------- norms
 
-// partial[blk][chunk] = max |a_rc| over the columns of one 256-column chunk
-// of diagonal block blk (rows restricted to the block).
+// partial[blk][chunk] = max |a_rc| over the columns of one 64-column chunk
+// of diagonal block blk (rows restricted to the block).  Lane l of wave w
+// takes column l of the chunk and the diagonals q = w (mod 4): each wave
+// load is one coalesced 512-byte run of a diagonal, and 4 times as many
+// workgroups as columns / 256 keep enough loads in flight for HBM.
 __global__ __launch_bounds__(256) void k_block_norm(const double *__restrict__ band,
                                                     Partition pt,
                                                     double *__restrict__ partial,
@@ -41,11 +44,12 @@ __global__ __launch_bounds__(256) void k_block_norm(const double *__restrict__ b
     const int blk = blockIdx.y;
     const int64_t s0 = pt.starts[blk];
     const int64_t nb = pt.starts[blk + 1] - s0;
-    const int64_t x = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t x = (int64_t)blockIdx.x * 64 + lane;
     double m = 0.0;
     if (x < nb) {
         const int64_t c = s0 + x;
-        for (int q = 0; q <= 2 * pt.k; ++q) {
+        for (int q = wave; q <= 2 * pt.k; q += 4) {
             const int64_t r = x + q - pt.k;
             if (r >= 0 && r < nb) m = fmax(m, fabs(band[(int64_t)q * pt.n + c]));
         }

@@ -92,7 +92,7 @@ Layout layout_for(const sap_options &o)
     const int k = o.k, p = o.p;
     const size_t sf = o.factor_prec == SAP_PREC_FP32 ? 4 : 8;
     const int64_t maxnb = n / p + (n % p ? 1 : 0);
-    const int nchunk = (int)((maxnb + 255) / 256);
+    const int nchunk = (int)((maxnb + 63) / 64);      // 64-column chunks (k_block_norm)
     const bool cpl = coupled_active(o);
     const size_t kk = (size_t)k * k;
     size_t off = 0;
