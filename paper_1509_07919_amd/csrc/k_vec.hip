@@ -7,60 +7,70 @@ namespace sap {
 
 // --------------------------------------------------------------- SpMV
 // y_r = sum_q band[q*n + c] v_c with c = r + K - q (A v), or
-// y_c = sum_q band[q*n + c] v_{c+q-K} (A^T v).  One thread per output; for a
-// fixed q consecutive threads read consecutive band entries, and the v tile
-// [r0-K, r0+256+K) is staged once in LDS.  Optional residual form b - A v.
+// y_c = sum_q band[q*n + c] v_{c+q-K} (A^T v).  A workgroup takes 64
+// outputs: lane l of wave w owns output r0 + l and the diagonals q = w
+// (mod 4), so for a fixed q a wave reads one coalesced 512-byte run of the
+// band, and four times as many waves as outputs / 256 keep enough loads in
+// flight for HBM.  The v tile [r0-K, r0+64+K) is staged once in LDS and the
+// four partial sums are added in LDS.  Optional residual form b - A v.
+constexpr int kSpmvRows = 64;
 __global__ __launch_bounds__(256) void k_spmv(const double *__restrict__ band, int64_t n,
                                               int k, const double *__restrict__ v,
                                               const double *__restrict__ b,
                                               double *__restrict__ y, int trans)
 {
-    __shared__ double vt[256 + 2 * kMaxK];
-    const int64_t r0 = (int64_t)blockIdx.x * 256;
-    const int tid = threadIdx.x;
-    for (int i = tid; i < 256 + 2 * k; i += 256) {
+    __shared__ double vt[kSpmvRows + 2 * kMaxK];
+    __shared__ double part[3][kSpmvRows];
+    const int64_t r0 = (int64_t)blockIdx.x * kSpmvRows;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    for (int i = tid; i < kSpmvRows + 2 * k; i += 256) {
         const int64_t g = r0 - k + i;
         vt[i] = (g >= 0 && g < n) ? v[g] : 0.0;
     }
     __syncthreads();
-    const int64_t r = r0 + tid;
-    if (r >= n) return;
-    double acc0 = 0.0, acc1 = 0.0;
+    const int64_t r = r0 + lane;
     const int w = 2 * k + 1;
-    if (!trans) {
-        // a[r][c] at band[(k + r - c)*n + c]; c = r + k - q in [0, n)
-        const int qlo = (int)max((int64_t)0, r + k - (n - 1));
-        const int qhi = (int)min((int64_t)(w - 1), r + k);
-        int q = qlo;
-        for (; q + 1 <= qhi; q += 2) {
-            acc0 = fma(band[(int64_t)q * n + (r + k - q)], vt[tid + 2 * k - q], acc0);
-            acc1 = fma(band[(int64_t)(q + 1) * n + (r + k - q - 1)], vt[tid + 2 * k - q - 1], acc1);
+    double acc0 = 0.0, acc1 = 0.0;
+    if (r < n) {
+        if (!trans) {
+            // a[r][c] at band[(k + r - c)*n + c]; c = r + k - q in [0, n)
+            const int qlo = (int)max((int64_t)0, r + k - (n - 1));
+            const int qhi = (int)min((int64_t)(w - 1), r + k);
+            int q = qlo + ((wave - qlo) & 3);
+            for (; q + 4 <= qhi; q += 8) {
+                acc0 = fma(band[(int64_t)q * n + (r + k - q)], vt[lane + 2 * k - q], acc0);
+                acc1 = fma(band[(int64_t)(q + 4) * n + (r + k - q - 4)], vt[lane + 2 * k - q - 4], acc1);
+            }
+            if (q <= qhi) acc0 = fma(band[(int64_t)q * n + (r + k - q)], vt[lane + 2 * k - q], acc0);
+        } else {
+            // a[rr][r] at band[q*n + r] with rr = r + q - k in [0, n)
+            const int qlo = (int)max((int64_t)0, (int64_t)k - r);
+            const int qhi = (int)min((int64_t)(w - 1), n - 1 - r + k);
+            int q = qlo + ((wave - qlo) & 3);
+            for (; q + 4 <= qhi; q += 8) {
+                acc0 = fma(band[(int64_t)q * n + r], vt[lane + q], acc0);
+                acc1 = fma(band[(int64_t)(q + 4) * n + r], vt[lane + q + 4], acc1);
+            }
+            if (q <= qhi) acc0 = fma(band[(int64_t)q * n + r], vt[lane + q], acc0);
         }
-        if (q <= qhi) acc0 = fma(band[(int64_t)q * n + (r + k - q)], vt[tid + 2 * k - q], acc0);
-    } else {
-        // a[rr][r] at band[q*n + r] with rr = r + q - k in [0, n)
-        const int qlo = (int)max((int64_t)0, (int64_t)k - r);
-        const int qhi = (int)min((int64_t)(w - 1), n - 1 - r + k);
-        int q = qlo;
-        for (; q + 1 <= qhi; q += 2) {
-            acc0 = fma(band[(int64_t)q * n + r], vt[tid + q], acc0);
-            acc1 = fma(band[(int64_t)(q + 1) * n + r], vt[tid + q + 1], acc1);
-        }
-        if (q <= qhi) acc0 = fma(band[(int64_t)q * n + r], vt[tid + q], acc0);
     }
     const double acc = acc0 + acc1;
-    y[r] = b ? b[r] - acc : acc;
+    if (wave > 0) part[wave - 1][lane] = acc;
+    __syncthreads();
+    if (wave == 0 && r < n) {
+        const double tot = (acc + part[0][lane]) + (part[1][lane] + part[2][lane]);
+        y[r] = b ? b[r] - tot : tot;
+    }
 }
 
 hipError_t launch_spmv(const double *band, int64_t n, int k, const double *v,
                        const double *b, double *y, int trans, hipStream_t s)
 {
-    const int64_t nblk = (n + 255) / 256;
+    const int64_t nblk = (n + kSpmvRows - 1) / kSpmvRows;
     hipLaunchKernelGGL(k_spmv, dim3((unsigned)nblk), dim3(256), 0, s, band, n, k, v, b, y, trans);
     return hipGetLastError();
 }
 
-// ------------------------------------------------------------ band gradient
 __global__ __launch_bounds__(256) void k_band_grad(int64_t n, int k,
                                                    const double *__restrict__ lam,
                                                    const double *__restrict__ x,
