@@ -39,8 +39,11 @@ namespace sap {
 __global__ __launch_bounds__(256) void k_block_norm(const double *__restrict__ band,
                                                     Partition pt,
                                                     double *__restrict__ partial,
-                                                    int nchunk)
+                                                    int nchunk, int *__restrict__ status)
 {
+    // the factorization's status words start at zero (the LU and tips
+    // kernels that follow count boosted pivots and flag singularity)
+    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x < kStatusWords) status[threadIdx.x] = 0;
     const int blk = blockIdx.y;
     const int64_t s0 = pt.starts[blk];
     const int64_t nb = pt.starts[blk + 1] - s0;
@@ -65,10 +68,10 @@ __global__ __launch_bounds__(256) void k_block_norm(const double *__restrict__ b
 }
 
 hipError_t launch_block_norm(const double *band, const Partition &pt, double *partial,
-                             int nchunk, hipStream_t s)
+                             int nchunk, int *status, hipStream_t s)
 {
     dim3 grid(nchunk, pt.p);
-    hipLaunchKernelGGL(k_block_norm, grid, dim3(256), 0, s, band, pt, partial, nchunk);
+    hipLaunchKernelGGL(k_block_norm, grid, dim3(256), 0, s, band, pt, partial, nchunk, status);
     return hipGetLastError();
 }
 

@@ -54,9 +54,11 @@ constexpr int kSweepWaves = 4;
 // w sums the terms i in [IW w, IW w + IW) of X(c)^T p for output slot
 // m = lane, IW = 64 / NW.  On return sh[0..64) holds the state entering
 // chunk c0 + dir (nlink + 1) (zero past K); STORE also writes every state
-// to a.st.
+// to a.st.  A non-null top gives chunk c0 the incoming state -top (K
+// entries), which adds the link of chunk c0 itself.
 template <typename T, bool FWD, int NW, bool STORE>
-__device__ void chain_states(const SweepArgs<T> &a, int blk, int nchb, int nlink, T *sh)
+__device__ void chain_states(const SweepArgs<T> &a, int blk, int nchb, int nlink, T *sh,
+                             const T *top = nullptr)
 {
     constexpr int IW = 64 / NW;
     const int k = a.pt.k;
@@ -66,11 +68,14 @@ __device__ void chain_states(const SweepArgs<T> &a, int blk, int nchb, int nlink
     T *part = sh + 64;           // [NW][64] partial sums
     const int c0 = FWD ? 0 : nchb - 1;            // chunk whose q seeds the chain
     const int dir = FWD ? 1 : -1;
-    // the state entering chunk c0 + dir is q(c0)
+    // the state entering chunk c0 + dir is q(c0), or with an incoming state
+    // -top the chain starts one link earlier, from -top entering chunk c0
+    const int first = top ? c0 : c0 + dir;        // chunk of the first link
+    if (top) ++nlink;
     if (tid < 64) {
-        const T v = tid < k ? a.q[(base + c0) * k + tid] : T(0);
+        const T v = tid < k ? (top ? -top[tid] : a.q[(base + c0) * k + tid]) : T(0);
         cur[tid] = v;
-        if (STORE && tid < k) a.st[(base + c0 + dir) * k + tid] = v;
+        if (STORE && !top && tid < k) a.st[(base + c0 + dir) * k + tid] = v;
     }
     // the transfer matrices of NG links are loaded at once, so their
     // latencies overlap; the links are then chained one after the other
@@ -88,7 +93,7 @@ __device__ void chain_states(const SweepArgs<T> &a, int blk, int nchb, int nlink
         T xg[NG][IW], qg[NG];
 #pragma unroll
         for (int j = 0; j < NG; ++j) {
-            const int c = c0 + dir * (1 + g + j);
+            const int c = first + dir * (g + j);
             if (g + j < nlink) {
                 load_x(c, xg[j]);
                 qg[j] = (wave == 0 && lane < k) ? a.q[(base + c) * k + lane] : T(0);
@@ -97,7 +102,7 @@ __device__ void chain_states(const SweepArgs<T> &a, int blk, int nchb, int nlink
 #pragma unroll
         for (int j = 0; j < NG; ++j) {
             if (g + j < nlink) {
-                const int c = c0 + dir * (1 + g + j);       // chunk of this link
+                const int c = first + dir * (g + j);         // chunk of this link
                 T s0 = T(0), s1 = T(0);
 #pragma unroll
                 for (int e = 0; e < IW; e += 2) {
@@ -450,8 +455,10 @@ __global__ __launch_bounds__(64 * circ_waves<T>(), circ_waves<T>() / 2) void k_s
     // outgoing states q of the chunks before it in the sweep direction and
     // their transfer matrices (all written by earlier launches), while the
     // first staging copies are in flight; it lands in csh[0..64).
+    // dtop as the incoming state -dtop of the block's first chunk (forward)
+    const T *top = (FWD && a.top_as_state) ? dtop : nullptr;
     auto entering_state = [&]() {
-        chain_states<T, FWD, NW, false>(a, blk, nchb, FWD ? ch - 1 : nchb - 2 - ch, csh);
+        chain_states<T, FWD, NW, false>(a, blk, nchb, FWD ? ch - 1 : nchb - 2 - ch, csh, top);
     };
 
     if (wave != 0) {
@@ -483,14 +490,15 @@ __global__ __launch_bounds__(64 * circ_waves<T>(), circ_waves<T>() / 2) void k_s
             vin = T(0);
             if (lane < cnt) {
                 const int64_t r = row_of((int64_t)t * S + lane);
+                const T *dt = top ? nullptr : dtop;    // top enters as a state
                 if (a.xin) {
                     double x = a.xin[s0 + r];
-                    if (dtop && r < k) x += (double)dtop[r];
+                    if (dt && r < k) x += (double)dt[r];
                     if (dbot && r >= nb - k) x += (double)dbot[r - (nb - k)];
                     vin = (T)x;
                 } else {
                     T x = a.tin[s0 + r];
-                    if (dtop && r < k) x += dtop[r];
+                    if (dt && r < k) x += dt[r];
                     if (dbot && r >= nb - k) x += dbot[r - (nb - k)];
                     vin = x;
                 }
@@ -532,7 +540,10 @@ __global__ __launch_bounds__(64 * circ_waves<T>(), circ_waves<T>() / 2) void k_s
     } else {
         // ------------------------------------------------------- compute wave
         if (PH == SWEEP_FROM_STATE && receives) entering_state();
-        T acc = (PH == SWEEP_FROM_STATE && receives) ? -csh[lane] : T(0);
+        // acc = -(incoming pending sums): the chained state, or top in the
+        // first chunk of a block
+        T acc = (PH == SWEEP_FROM_STATE && receives) ? -csh[lane]
+              : (PH == SWEEP_FROM_STATE && top && lane < k) ? top[lane] : T(0);
         T dl = T(0), vdl = T(0), xo = T(0);
         for (int t = 0; t < nchunks; ++t) {
             __syncthreads();                          // chunk t rotated
@@ -806,6 +817,7 @@ static hipError_t launch_xfer_km(const XferArgs<T> &a, hipStream_t s)
 }
 
 bool sweep_chunking_supported(int k, bool) { return k >= 1 && k < 64; }
+bool sweep_top_state_supported(int k) { return k >= 1 && k <= kCircMaxK; }
 
 template <typename T>
 hipError_t launch_sweep_xfer(const XferArgs<T> &a, hipStream_t s)

@@ -223,6 +223,9 @@ __device__ void scalar_op(int op, const double *d, double *sc, double *host)
         if (d[0] == 0.0) brk(2.0);
         sc[S_ALPHA] = sc[S_RHO0] / d[0];
         break;
+    case OP_TRUE:
+        if (host) host[H_TRUE] = d[0];
+        break;
     case OP_EXIT:
     case OP_NORM:
         sc[S_NRM2] = d[0]; publish = true;
@@ -298,6 +301,10 @@ __global__ __launch_bounds__(256) void k_dots_final(DotArgs a)
     if (tid == 0) {
         const double dd[3] = {tot[0][0], tot[1][0], tot[2][0]};
         scalar_op(a.op, dd, a.sc, a.host);
+        if (a.status && a.host) {
+            a.host[H_NBOOST] = (double)a.status[0];
+            a.host[H_SING] = (double)a.status[1];
+        }
         __threadfence_system();
     }
 }

@@ -46,12 +46,13 @@ bool coupled_active(const sap_options &o) { return o.mode == SAP_COUPLED && o.p 
 // at least 64 rows per chunk.
 struct Chunking {
     int nch, clen;
+    bool tails_hold_k;       // every block's last chunk has >= K rows (or is its only chunk)
 };
 Chunking chunking_for(const sap_options &o)
 {
     const int64_t maxnb = o.n / o.p + (o.n % o.p ? 1 : 0);
     const bool fp32 = o.factor_prec == SAP_PREC_FP32;
-    Chunking c{1, (int)maxnb};
+    Chunking c{1, (int)maxnb, true};
     if (o.sweep_chunks == 1 || !sweep_chunking_supported(o.k, fp32)) return c;
     int64_t want = o.sweep_chunks >= 2 ? o.sweep_chunks : 512 / o.p;
     if (want < 2) return c;
@@ -61,6 +62,12 @@ Chunking chunking_for(const sap_options &o)
     if (nch < 2) return c;
     c.nch = (int)nch;
     c.clen = (int)clen;
+    // blocks have maxnb or maxnb - 1 rows (the partition of Sec. 3.1)
+    for (int64_t nb = maxnb - 1; nb <= maxnb; ++nb) {
+        if (nb < 1) continue;
+        const int64_t nchb = (nb + clen - 1) / clen;
+        if (nchb > 1 && nb - (nchb - 1) * clen < o.k) c.tails_hold_k = false;
+    }
     return c;
 }
 
@@ -133,7 +140,7 @@ Layout layout_for(const sap_options &o)
         L.xUc = take(xb);
         L.xLr = o.adjoint ? take(xb) : 0;
         L.xUr = o.adjoint ? take(xb) : 0;
-        L.sq = take(sf * (size_t)p * ck.nch * k);
+        L.sq = take(2 * sf * (size_t)p * ck.nch * k);     // first and second sweep of a D^{-1}
         L.sst = take(sf * (size_t)p * ck.nch * k);
         L.ticket = take(sizeof(unsigned) * (size_t)p);
     }
@@ -159,7 +166,7 @@ struct sap_handle_ {
     bool factored, starts_uploaded;
     hipEvent_t ev[5];        // factor start / after LU / end, solve start / end
     hipStream_t side;        // second stream: transfer matrices beside the tips
-    hipEvent_t fork, join;
+    hipEvent_t join;         // the side stream's work joins the main stream
     float t_factor, t_lu, t_tips;
     // per-kernel timing (sap_profile): event pairs recorded around launches
     bool prof;
@@ -203,9 +210,13 @@ struct ProfScope {
 enum KVec { KV_R0 = 0, KV_R1, KV_R2, KV_U0, KV_U1, KV_U2, KV_RT, KV_T };
 
 // ------------------------------------------------------------------ sweeps
+// D^{-1} v (forward then backward sweep).  reuse_q: the previous dinv ran on
+// the same input v without dtop/dbot, so its first sweep's zero-state pass
+// (q, first half of L.sq, not overwritten since) serves this one, and dtop
+// enters the first chunk of each block as its incoming state.
 template <typename T>
 int dinv(sap_handle h, int trans, const double *xin, const T *dtop, const T *dbot,
-         double *dout, T *tout, hipStream_t s)
+         double *dout, T *tout, hipStream_t s, bool reuse_q = false)
 {
     SweepArgs<T> a1{};
     a1.pt = h->pt;
@@ -242,11 +253,15 @@ int dinv(sap_handle h, int trans, const double *xin, const T *dtop, const T *dbo
         }
         a->nch = h->ck.nch;
         a->clen = h->ck.clen;
-        a->q = h->ptr<T>(h->L.sq);
+        a->q = h->ptr<T>(h->L.sq) + (a == &a1 ? 0 : (size_t)h->opt.p * h->ck.nch * h->opt.k);
         a->st = h->ptr<T>(h->L.sst);
         a->ticket = h->ptr<unsigned>(h->L.ticket);
-        a->phase = SWEEP_ZERO_STATE;
-        {
+        // dbot must stay inside each block's last chunk, whose q is not used
+        const bool reuse = reuse_q && a == &a1 && sweep_top_state_supported(h->opt.k) &&
+                           h->ck.tails_hold_k;
+        a->top_as_state = reuse ? 1 : 0;
+        if (!reuse) {
+            a->phase = SWEEP_ZERO_STATE;
             ProfScope ps(h, SAP_KERNEL_SWEEP, s);
             HIP_TRY(launch_sweep<T>(*a, s));
         }
@@ -279,7 +294,7 @@ int precond_t(sap_handle h, int trans, const double *r, double *z, hipStream_t s
         ProfScope ps(h, SAP_KERNEL_CORR, s);
         HIP_TRY(launch_correction<T>(c, s));
     }
-    return dinv<T>(h, trans, r, dtop, dbot, z, nullptr, s);
+    return dinv<T>(h, trans, r, dtop, dbot, z, nullptr, s, true);
 }
 
 int precond(sap_handle h, int trans, const double *r, double *z, hipStream_t s)
@@ -310,9 +325,10 @@ DotArgs dot_args(sap_handle h, int op)
 }
 
 int dots(sap_handle h, int op, std::initializer_list<std::pair<const double *, const double *>> pr,
-         hipStream_t s)
+         hipStream_t s, const int *status = nullptr)
 {
     DotArgs d = dot_args(h, op);
+    d.status = status;
     int i = 0;
     for (auto &p : pr) { d.x[i] = p.first; d.y[i] = p.second; ++i; }
     d.nd = i;
@@ -395,13 +411,12 @@ int krylov(sap_handle h, int trans, const double *b, double *x, double tol, int3
     const int k = h->opt.k;
     double nrm2 = 0, brk = 0;
 
-    // the factorization's status and ||b|| in one host round trip
-    HIP_TRY(hipMemcpyAsync(h->h_status, h->ptr<int>(h->L.status), 2 * sizeof(int32_t),
-                           hipMemcpyDeviceToHost, s));
-    TRY(dots(h, OP_NORM, {{b, b}}, s));
+    // the factorization's status and ||b|| in one host round trip (the
+    // reduction kernel copies the status words to the host slots)
+    TRY(dots(h, OP_NORM, {{b, b}}, s, h->ptr<int>(h->L.status)));
     TRY(sync_read(h, s, &nrm2, &brk));
-    loc.n_boosted = h->h_status[0];
-    if (const int32_t singular = h->h_status[1]) {
+    loc.n_boosted = (int32_t)h->h_slots[H_NBOOST];
+    if (const int32_t singular = (int32_t)h->h_slots[H_SING]) {
         if (st) *st = loc;
         return fail(SAP_ERR_SINGULAR, singular == 1 ? "zero pivot in a diagonal block (boosting disabled)"
                                                     : "singular reduced matrix Rbar");
@@ -433,6 +448,8 @@ int krylov(sap_handle h, int trans, const double *b, double *x, double tol, int3
     TRY(update(h, UPD_RESTART, x, OP_INIT, 2, s));
     double pnorm0 = 0.0, thr = 0.0, pstart = 0.0;
     bool started = false;          // H_NRM0 of the last (re)start read
+    bool first_start = true;       // no restart yet
+    bool tn_pending = false;       // H_TRUE of the last restart not read yet
     double tn_restart = 0.0;       // true residual norm at the last restart
     int napply = 0;
     // Reliable updates (Sleijpen and van der Vorst 1996): with FP32 factors
@@ -444,11 +461,17 @@ int krylov(sap_handle h, int trans, const double *b, double *x, double tol, int3
     // exit test: returns 1 = converged, 2 = restarted, 0 = continue, < 0 error
     auto exit_test = [&]() -> int {
         TRY(sync_read(h, s, &nrm2, &brk));
+        if (tn_pending) {
+            tn_restart = std::sqrt(h->h_slots[H_TRUE]);
+            loc.rel_resid_true = tn_restart / bnorm;
+            tn_pending = false;
+        }
         if (!started) {
             pstart = std::sqrt(h->h_slots[H_NRM0]);
-            if (tn_restart == 0.0) {          // the initial start
+            if (first_start) {
                 pnorm0 = pstart;
                 thr = tol * pnorm0;
+                first_start = false;
             } else {
                 thr = tol * bnorm * pstart / tn_restart;
             }
@@ -462,6 +485,19 @@ int krylov(sap_handle h, int trans, const double *b, double *x, double tol, int3
         {
             ProfScope ps(h, SAP_KERNEL_SPMV, s);
             HIP_TRY(launch_spmv(A, n, k, x, b, t, trans, s));    // t = b - A x
+        }
+        if (pn > thr) {
+            // reliable update before the recursive residual reached the
+            // tolerance: restart from the true residual without testing it on
+            // the host; its norm is read at the next exit test
+            TRY(dots(h, OP_TRUE, {{t, t}}, s));
+            TRY(precond(h, trans, t, r0, s));
+            ++napply;
+            ++loc.restarts;
+            TRY(update(h, UPD_RESTART, x, OP_INIT, 2, s));
+            started = false;
+            tn_pending = true;
+            return 2;
         }
         TRY(dots(h, OP_NORM, {{t, t}}, s));
         double tn2 = 0, b2 = 0;
@@ -555,12 +591,12 @@ int factor_t(sap_handle h, const double *a_band, hipStream_t s)
     // on the factors: they run on the side stream beside the tips
     const bool side = h->ck.nch >= 2 && h->coupled;
     hipStream_t xs = side ? h->side : s;
-    if (side) {
-        HIP_TRY(hipEventRecord(h->fork, s));
-        HIP_TRY(hipStreamWaitEvent(h->side, h->fork, 0));
-    }
+    // ev[1] (the LU's end, for its time) also forks the side stream
+    HIP_TRY(hipEventRecord(h->ev[1], s));
+    if (side) HIP_TRY(hipStreamWaitEvent(h->side, h->ev[1], 0));
     if (h->ck.nch >= 2) {
-        HIP_TRY(hipMemsetAsync(h->ptr<unsigned>(h->L.ticket), 0, sizeof(unsigned) * h->opt.p, xs));
+        if (!sweep_top_state_supported(h->opt.k))      // ring kernel: per-block tickets
+            HIP_TRY(hipMemsetAsync(h->ptr<unsigned>(h->L.ticket), 0, sizeof(unsigned) * h->opt.p, xs));
         struct Arr { T *F; size_t xf; int fwd, diag; };
         const Arr arrs[4] = {{lu.Lc, h->L.xLc, 1, 0}, {lu.Uc, h->L.xUc, 0, 1},
                              {lu.Ur, h->L.xUr, 1, 1}, {lu.Lr, h->L.xLr, 0, 0}};
@@ -579,7 +615,6 @@ int factor_t(sap_handle h, const double *a_band, hipStream_t s)
         ProfScope ps(h, SAP_KERNEL_XFER, xs);
         HIP_TRY(launch_sweep_xfer<T>(xa, xs));
     }
-    HIP_TRY(hipEventRecord(h->ev[1], s));
     if (h->coupled) {
         TipsArgs<T> ta{};
         ta.band = a_band;
@@ -653,7 +688,6 @@ int sap_create(const sap_options *opt, void *workspace, size_t ws_bytes, sap_han
         if (h->h_status) (void)hipHostFree(h->h_status);
         for (auto &e : h->ev)
             if (e) (void)hipEventDestroy(e);
-        if (h->fork) (void)hipEventDestroy(h->fork);
         if (h->join) (void)hipEventDestroy(h->join);
         if (h->side) (void)hipStreamDestroy(h->side);
         delete h;
@@ -667,8 +701,7 @@ int sap_create(const sap_options *opt, void *workspace, size_t ws_bytes, sap_han
         return cleanup(SAP_ERR_HIP, "hipHostGetDevicePointer failed");
     for (auto &e : h->ev)
         if (hipEventCreate(&e) != hipSuccess) return cleanup(SAP_ERR_HIP, "hipEventCreate failed");
-    if (hipEventCreateWithFlags(&h->fork, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&h->join, hipEventDisableTiming) != hipSuccess ||
+    if (hipEventCreateWithFlags(&h->join, hipEventDisableTiming) != hipSuccess ||
         hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking) != hipSuccess)
         return cleanup(SAP_ERR_HIP, "creating the side stream failed");
     // Sec. 3.1: first P_r = N - P*floor(N/P) blocks get floor(N/P) + 1 rows
@@ -694,11 +727,11 @@ int sap_factor(sap_handle h, const double *a_band, void *stream)
             if (off) HIP_TRY(hipMemsetAsync(h->ws + off, 0, fb, s));
         h->starts_uploaded = true;
     }
-    HIP_TRY(hipMemsetAsync(h->ptr<int>(h->L.status), 0, 64, s));
     HIP_TRY(hipEventRecord(h->ev[0], s));
     {
-        ProfScope ps(h, SAP_KERNEL_NORM, s);
-        HIP_TRY(launch_block_norm(a_band, h->pt, h->ptr<double>(h->L.partial), h->nchunk, s));
+        ProfScope ps(h, SAP_KERNEL_NORM, s);       // also zeroes the status words
+        HIP_TRY(launch_block_norm(a_band, h->pt, h->ptr<double>(h->L.partial), h->nchunk,
+                                  h->ptr<int>(h->L.status), s));
     }
     int rc = h->fp32 ? factor_t<float>(h, a_band, s) : factor_t<double>(h, a_band, s);
     if (rc) return rc;
@@ -835,7 +868,6 @@ int sap_destroy(sap_handle h)
         (void)hipStreamSynchronize(h->side);
         (void)hipStreamDestroy(h->side);
     }
-    if (h->fork) (void)hipEventDestroy(h->fork);
     if (h->join) (void)hipEventDestroy(h->join);
     delete h;
     return SAP_OK;

@@ -52,6 +52,7 @@ enum KrylovOp : int {
     OP_MR2,        // d0=(r2,r2) d1=(r0,r2)
     OP_FINAL,      // d0=(r0,r0) d1=(r0,rt): publish, then next j=0 prep
     OP_NORM,       // d0=(v,v): publish only
+    OP_TRUE,       // d0=(t,t): the true residual at a restart, to host slot H_TRUE
 };
 
 // device scalar slots of the BiCGStab(2) recurrences (double sc[kScalars])
@@ -61,8 +62,11 @@ enum ScalarSlot : int {
 };
 
 // host-visible (pinned, mapped) result slots written by reduction kernels
-// H_NRM0: squared norm of the (re)started preconditioned residual (OP_INIT)
-enum HostSlot : int { H_NRM2 = 0, H_BREAK = 1, H_NRM0 = 2, kHostSlots = 8 };
+// H_NRM0: squared norm of the (re)started preconditioned residual (OP_INIT);
+// H_TRUE: squared norm of the true residual a restart started from (OP_TRUE);
+// H_NBOOST, H_SING: the factorization's status words (DotArgs::status)
+enum HostSlot : int { H_NRM2 = 0, H_BREAK = 1, H_NRM0 = 2, H_TRUE = 3, H_NBOOST = 4, H_SING = 5,
+                      kHostSlots = 8 };
 
 struct Partition {
     const int64_t *starts;   // P+1 block boundaries (device)
@@ -73,8 +77,9 @@ struct Partition {
 };
 
 // ------------------------------------------------------------- factorization
+constexpr int kStatusWords = 16;   // int status[16]: [0] boosted pivots, [1] singular flag
 hipError_t launch_block_norm(const double *band, const Partition &pt,
-                             double *partial, int nchunk, hipStream_t s);
+                             double *partial, int nchunk, int *status, hipStream_t s);
 
 template <typename T>
 struct LuArgs {
@@ -146,9 +151,16 @@ struct SweepArgs {
     T *q, *st;
     const T *xf;
     unsigned *ticket;
+    // From-state pass of a forward sweep (K <= 56): dtop enters as the
+    // incoming state -dtop of each block's first chunk instead of being added
+    // to its first K inputs (the same sums), so the zero-state pass of an
+    // earlier sweep of the same input without dtop supplies q.
+    int top_as_state;
 };
 template <typename T>
 hipError_t launch_sweep(const SweepArgs<T> &a, hipStream_t s);
+// whether the chunked sweeps take dtop as an incoming state (top_as_state)
+bool sweep_top_state_supported(int k);
 
 // Transfer matrices X(c) of every chunk that hands a state on (see above),
 // for up to four coefficient arrays in one launch.
@@ -196,6 +208,7 @@ struct DotArgs {
     double *partial;         // [kDotBlocks][3]
     double *sc;              // device scalars
     double *host;            // mapped pinned host slots (may be null)
+    const int *status;       // if set, copied to host slots H_NBOOST, H_SING
     int op;
 };
 hipError_t launch_dots(const DotArgs &a, hipStream_t s);
