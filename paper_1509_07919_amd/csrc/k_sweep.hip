@@ -711,7 +711,6 @@ template <typename T, int KM>
 __global__ __launch_bounds__(256) void k_sweep_xfer(XferArgs<T> a)
 {
     static_assert(KM <= 64, "coefficients are spread one per lane");
-    constexpr int EPT = (63 * 63 + 255) / 256;  // product elements per thread
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *Xs = reinterpret_cast<T *>(smem_raw);   // [4][K][K]
     const int k = a.pt.k;
@@ -767,39 +766,63 @@ __global__ __launch_bounds__(256) void k_sweep_xfer(XferArgs<T> a)
             if (m < k) xw[m] = p[m];
     }
     __syncthreads();
-    // Y = X_0 X_1 and Z = X_2 X_3, then X = Y Z
-    T y[EPT], z[EPT];
+    // Y = X_0 X_1 and Z = X_2 X_3, then X = Y Z, each thread forming 4 x 4
+    // output blocks (8 LDS reads per 16 FMAs; rows and columns past K are
+    // clamped on read and not written)
+    const int nbk = (k + 3) / 4, nblk = nbk * nbk;
+    auto block_mul = [&](const T *A, const T *Bm, int b, T (&acc)[4][4]) {
+        const int i0 = 4 * (b / nbk), m0 = 4 * (b - (b / nbk) * nbk);
+        int ir[4], mc[4];
 #pragma unroll
-    for (int q = 0; q < EPT; ++q) {
-        const int e = tid + 256 * q;
-        y[q] = z[q] = T(0);
-        if (e < kk) {
-            const int i = e / k, m = e - (e / k) * k;
-            T sy = T(0), sz = T(0);
-            for (int c = 0; c < k; ++c) {
-                sy = fma(Xs[i * k + c], Xs[kk + c * k + m], sy);
-                sz = fma(Xs[2 * kk + i * k + c], Xs[3 * kk + c * k + m], sz);
-            }
-            y[q] = sy;
-            z[q] = sz;
+        for (int q = 0; q < 4; ++q) {
+            ir[q] = min(i0 + q, k - 1) * k;
+            mc[q] = min(m0 + q, k - 1);
         }
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[r][q] = T(0);
+        for (int c = 0; c < k; ++c) {
+            T av[4], bv[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                av[q] = A[ir[q] + c];
+                bv[q] = Bm[c * k + mc[q]];
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) acc[r][q] = fma(av[r], bv[q], acc[r][q]);
+        }
+    };
+    auto block_store = [&](T *D, int b, const T (&acc)[4][4]) {
+        const int i0 = 4 * (b / nbk), m0 = 4 * (b - (b / nbk) * nbk);
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (i0 + r < k && m0 + q < k) D[(i0 + r) * k + m0 + q] = acc[r][q];
+    };
+    // blocks b < nblk of Y, nblk <= b < 2 nblk of Z: 2 ceil(K/4)^2 <= 512,
+    // at most two per thread
+    T acc0[4][4], acc1[4][4];
+    const int b0 = tid, b1 = tid + 256;
+    if (b0 < 2 * nblk) {
+        if (b0 < nblk) block_mul(Xs, Xs + kk, b0, acc0);
+        else block_mul(Xs + 2 * kk, Xs + 3 * kk, b0 - nblk, acc0);
+    }
+    if (b1 < 2 * nblk) {
+        if (b1 < nblk) block_mul(Xs, Xs + kk, b1, acc1);
+        else block_mul(Xs + 2 * kk, Xs + 3 * kk, b1 - nblk, acc1);
     }
     __syncthreads();
-#pragma unroll
-    for (int q = 0; q < EPT; ++q) {
-        const int e = tid + 256 * q;
-        if (e < kk) {
-            Xs[e] = y[q];
-            Xs[kk + e] = z[q];
-        }
-    }
+    if (b0 < 2 * nblk) block_store(b0 < nblk ? Xs : Xs + kk, b0 < nblk ? b0 : b0 - nblk, acc0);
+    if (b1 < 2 * nblk) block_store(b1 < nblk ? Xs : Xs + kk, b1 < nblk ? b1 : b1 - nblk, acc1);
     __syncthreads();
     T *out = a.xf[arr] + ((int64_t)blk * a.nch + ch) * kk;
-    for (int e = tid; e < kk; e += 256) {
-        const int i = e / k, m = e - i * k;
-        T sx = T(0);
-        for (int c = 0; c < k; ++c) sx = fma(Xs[i * k + c], Xs[kk + c * k + m], sx);
-        out[e] = sx;
+    if (tid < nblk) {
+        block_mul(Xs, Xs + kk, tid, acc0);
+        block_store(out, tid, acc0);
     }
 }
 
