@@ -180,11 +180,98 @@ __global__ __launch_bounds__(256) void k_correction(CorrArgs<T> a)
     }
 }
 
+// The same correction with the interface's five K x K matrices (W, Rinv, V,
+// B, C) staged in LDS by one coalesced pass, so their loads overlap, and each
+// mat-vec spread over four threads per row (partial sums over c = q mod 4,
+// added with two lane exchanges).  Used when they fit in LDS.
+template <typename T>
+__global__ __launch_bounds__(256) void k_correction_lds(CorrArgs<T> a)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int i = blockIdx.x;
+    const int k = a.pt.k;
+    const int kk = k * k;
+    const int64_t s1 = a.pt.starts[i + 1];
+    const int64_t ikk = (int64_t)i * kk;
+    T *sm = reinterpret_cast<T *>(smem_raw);
+    T *Ws = sm, *Rs = sm + kk, *Vs = sm + 2 * kk, *Bs = sm + 3 * kk, *Cs = sm + 4 * kk;
+    T *vb = sm + 5 * kk, *vt = vb + k, *w1 = vt + k, *w2 = w1 + k, *w3 = w2 + k;
+    const int t = threadIdx.x;
+    for (int e = t; e < kk; e += 256) {
+        const T w = a.W[ikk + e], r = a.Rinv[ikk + e], v = a.V[ikk + e];
+        const T b = a.B[ikk + e], c = a.C[ikk + e];
+        Ws[e] = w; Rs[e] = r; Vs[e] = v; Bs[e] = b; Cs[e] = c;
+    }
+    if (t < k) {
+        vb[t] = a.g[s1 - k + t];
+        vt[t] = a.g[s1 + t];
+    }
+    __syncthreads();
+    const int r = t >> 2, q = t & 3;
+    const bool act = r < k;
+    // sum_c M[r][c] x[c] (tr: M[c][r]) over this thread's c, then over the 4
+    auto mv = [&](const T *M, bool tr, const T *x) {
+        T s = T(0);
+        if (act)
+            for (int c = q; c < k; c += 4) s = fma(tr ? M[c * k + r] : M[r * k + c], x[c], s);
+        s += __shfl_xor(s, 1, 64);
+        s += __shfl_xor(s, 2, 64);
+        return s;
+    };
+    T *dbot = a.dbot + (int64_t)i * k;          // bottom rows of block i
+    T *dtop = a.dtop + (int64_t)(i + 1) * k;    // top rows of block i+1
+    const bool lead = act && q == 0;
+    if (!a.trans) {
+        T s = mv(Ws, false, vb);
+        if (lead) w1[r] = vt[r] - s;
+        __syncthreads();
+        s = mv(Rs, false, w1);
+        if (lead) w2[r] = s;                                 // y
+        __syncthreads();
+        s = mv(Vs, false, w2);
+        if (lead) w3[r] = vb[r] - s;                         // z
+        __syncthreads();
+        const T sb = mv(Bs, false, w2), st = mv(Cs, false, w3);
+        if (lead) {
+            dbot[r] = -sb;
+            dtop[r] = -st;
+        }
+    } else {
+        const T sy = mv(Bs, true, vb), sz = mv(Cs, true, vt);
+        if (lead) {
+            w1[r] = -sy;                                     // ybar
+            w2[r] = -sz;                                     // zbar
+        }
+        __syncthreads();
+        T s = mv(Vs, true, w2);
+        if (lead) w3[r] = w1[r] - s;                         // ybar - V^T zbar
+        __syncthreads();
+        s = mv(Rs, true, w3);
+        if (lead) w1[r] = s;                                 // tbar
+        __syncthreads();
+        s = mv(Ws, true, w1);
+        if (lead) {
+            dbot[r] = w2[r] - s;
+            dtop[r] = w1[r];
+        }
+    }
+}
+
 template <typename T>
 hipError_t launch_correction(const CorrArgs<T> &a, hipStream_t s)
 {
     if (a.pt.p < 2 || a.pt.k == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_correction<T>, dim3(a.pt.p - 1), dim3(256), 0, s, a);
+    const size_t kk = (size_t)a.pt.k * a.pt.k;
+    const size_t lds = (5 * kk + 5 * (size_t)a.pt.k) * sizeof(T);
+    if (lds <= kMaxLds && a.pt.k <= 64) {
+        auto kern = k_correction_lds<T>;
+        hipError_t e = hipFuncSetAttribute((const void *)kern,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(kern, dim3(a.pt.p - 1), dim3(256), lds, s, a);
+    } else {
+        hipLaunchKernelGGL(k_correction<T>, dim3(a.pt.p - 1), dim3(256), 0, s, a);
+    }
     return hipGetLastError();
 }
 template hipError_t launch_correction<float>(const CorrArgs<float> &, hipStream_t);
