@@ -448,7 +448,9 @@ hipError_t launch_tips(const TipsArgs<T> &a, hipStream_t s)
     if (a.pt.p < 2) return hipSuccess;
     const size_t kk = (size_t)a.pt.k * a.pt.k;
     const size_t lds = (4 * kk + 3 * (size_t)a.pt.k) * sizeof(T);
-    if (lds <= kMaxLds) {
+    // plus the static LDS of k_tips_lds (perm_sh, ord_sh, p_sh, d_sh)
+    const size_t lds_static = 2 * kMaxK * sizeof(int) + sizeof(int) + sizeof(T) + 64;
+    if (lds + lds_static <= kMaxLds) {
         auto kern = k_tips_lds<T>;
         hipError_t e = hipFuncSetAttribute((const void *)kern,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

@@ -99,10 +99,11 @@ def test_precond_parity(n, k, p, mode, prec):
 
 # wide bands: the matrix-core blocked LU (K >= 64; several window sizes, a
 # partial last panel), the register-ring LU (FP64 97..127, FP32 > 208) and
-# the global-memory tips kernel (3 K^2 elements beyond 128 KB)
+# the global-memory tips kernel (when the LDS one does not fit: FP64 K >= 71,
+# where its static arrays tip the total over 160 KB)
 WIDE_CASES = [
     (4001, 58, 4, "fp64"), (4001, 62, 4, "fp32"), (4001, 64, 4, "fp32"),
-    (4001, 64, 4, "fp64"), (5003, 96, 5, "fp64"),
+    (4001, 64, 4, "fp64"), (4501, 71, 4, "fp64"), (5003, 96, 5, "fp64"),
     (5003, 100, 5, "fp32"), (6007, 127, 5, "fp64"), (6007, 128, 5, "fp64"),
     (6007, 150, 7, "fp32"), (6400, 160, 8, "fp64"), (6400, 200, 8, "fp32"),
     (6400, 208, 8, "fp32"), (7001, 255, 6, "fp32"),
