@@ -706,13 +706,13 @@ hipError_t launch_sweep<double>(const SweepArgs<double> &a, hipStream_t s)
 // p[m-1] = p[m] + F[j][m]*x.  Coefficient rows are loaded one per lane
 // (coefficient m in lane m), eight rows ahead, and broadcast with
 // v_readlane.  The chunk's transfer is the product X_0 X_1 X_2 X_3 (a state
-// s maps to s X), formed in LDS.
+// s maps to s X), formed through two LDS slots.
 template <typename T, int KM>
 __global__ __launch_bounds__(256) void k_sweep_xfer(XferArgs<T> a)
 {
     static_assert(KM <= 64, "coefficients are spread one per lane");
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    T *Xs = reinterpret_cast<T *>(smem_raw);   // [4][K][K]
+    T *Xs = reinterpret_cast<T *>(smem_raw);   // [2][K][K]
     const int k = a.pt.k;
     const int CP = coef_pitch(k, (int)sizeof(T));   // row pitch in HBM
     const int kk = k * k;
@@ -759,18 +759,22 @@ __global__ __launch_bounds__(256) void k_sweep_xfer(XferArgs<T> a)
 #pragma unroll
         for (int e = 0; e < D; ++e) fr[e] = fn[e];
     }
-    if (lane < k) {
-        T *xw = Xs + wave * kk + lane * k;
+    // X = ((X_0 X_1) X_2) X_3 through two K x K slots of LDS (A: the running
+    // product, B: the next factor), so the kernel needs 2 K^2 elements of
+    // LDS and three workgroups fit on a CU beside the tips kernel; each
+    // thread forms a 4 x 4 output block (8 LDS reads per 16 FMAs; rows and
+    // columns past K are clamped on read and not written)
+    T *A = Xs, *Bm = Xs + kk;
+    auto put = [&](int w, T *dst) {
+        if (wave == w && lane < k) {
+            T *xw = dst + lane * k;
 #pragma unroll
-        for (int m = 0; m < KM; ++m)
-            if (m < k) xw[m] = p[m];
-    }
-    __syncthreads();
-    // Y = X_0 X_1 and Z = X_2 X_3, then X = Y Z, each thread forming 4 x 4
-    // output blocks (8 LDS reads per 16 FMAs; rows and columns past K are
-    // clamped on read and not written)
-    const int nbk = (k + 3) / 4, nblk = nbk * nbk;
-    auto block_mul = [&](const T *A, const T *Bm, int b, T (&acc)[4][4]) {
+            for (int m = 0; m < KM; ++m)
+                if (m < k) xw[m] = p[m];
+        }
+    };
+    const int nbk = (k + 3) / 4, nblk = nbk * nbk;     // <= 256 for K <= 64
+    auto block_mul = [&](int b, T (&acc)[4][4]) {
         const int i0 = 4 * (b / nbk), m0 = 4 * (b - (b / nbk) * nbk);
         int ir[4], mc[4];
 #pragma unroll
@@ -803,33 +807,32 @@ __global__ __launch_bounds__(256) void k_sweep_xfer(XferArgs<T> a)
             for (int q = 0; q < 4; ++q)
                 if (i0 + r < k && m0 + q < k) D[(i0 + r) * k + m0 + q] = acc[r][q];
     };
-    // blocks b < nblk of Y, nblk <= b < 2 nblk of Z: 2 ceil(K/4)^2 <= 512,
-    // at most two per thread
-    T acc0[4][4], acc1[4][4];
-    const int b0 = tid, b1 = tid + 256;
-    if (b0 < 2 * nblk) {
-        if (b0 < nblk) block_mul(Xs, Xs + kk, b0, acc0);
-        else block_mul(Xs + 2 * kk, Xs + 3 * kk, b0 - nblk, acc0);
+    // waves 2 and 3 park X_2 and X_3 in global scratch (their registers are
+    // then free: the kernel keeps few enough VGPRs for three workgroups per
+    // CU); they are copied back into slot B when their product comes
+    T *scr = a.scratch + (((int64_t)arr * a.pt.p + blk) * a.nch + ch) * 2 * kk;
+    put(0, A);
+    put(1, Bm);
+    put(2, scr);
+    put(3, scr + kk);
+    T acc[4][4];
+    for (int w = 2; w <= 4; ++w) {
+        __threadfence_block();                    // the parked partials, to this workgroup
+        __syncthreads();                          // A and B complete
+        if (tid < nblk) block_mul(tid, acc);
+        __syncthreads();                          // A and B read
+        if (w == 4) break;
+        if (tid < nblk) block_store(A, tid, acc);
+        for (int e = tid; e < kk; e += 256) Bm[e] = scr[(w - 2) * kk + e];
     }
-    if (b1 < 2 * nblk) {
-        if (b1 < nblk) block_mul(Xs, Xs + kk, b1, acc1);
-        else block_mul(Xs + 2 * kk, Xs + 3 * kk, b1 - nblk, acc1);
-    }
-    __syncthreads();
-    if (b0 < 2 * nblk) block_store(b0 < nblk ? Xs : Xs + kk, b0 < nblk ? b0 : b0 - nblk, acc0);
-    if (b1 < 2 * nblk) block_store(b1 < nblk ? Xs : Xs + kk, b1 < nblk ? b1 : b1 - nblk, acc1);
-    __syncthreads();
     T *out = a.xf[arr] + ((int64_t)blk * a.nch + ch) * kk;
-    if (tid < nblk) {
-        block_mul(Xs, Xs + kk, tid, acc0);
-        block_store(out, tid, acc0);
-    }
+    if (tid < nblk) block_store(out, tid, acc);
 }
 
 template <typename T, int KM>
 static hipError_t launch_xfer_km(const XferArgs<T> &a, hipStream_t s)
 {
-    const size_t lds = 4 * (size_t)a.pt.k * a.pt.k * sizeof(T);
+    const size_t lds = 2 * (size_t)a.pt.k * a.pt.k * sizeof(T);
     if (lds > kMaxLds) return hipErrorInvalidValue;
     auto kern = k_sweep_xfer<T, KM>;
     hipError_t e = hipFuncSetAttribute((const void *)kern,

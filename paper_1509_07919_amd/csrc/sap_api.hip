@@ -35,7 +35,7 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
     size_t starts, partial, status, Lc, Uc, Lr, Ur, corner, B, C, V, W, Rbar, Rlu, Rinv, piv,
-        gT, yT, dtop, dbot, kv, dpart, sc, xLc, xUc, xLr, xUr, sq, sst, ticket, total;
+        gT, yT, dtop, dbot, kv, dpart, sc, xLc, xUc, xLr, xUr, xscr, sq, sst, ticket, total;
 };
 
 bool coupled_active(const sap_options &o) { return o.mode == SAP_COUPLED && o.p > 1 && o.k > 0; }
@@ -140,6 +140,7 @@ Layout layout_for(const sap_options &o)
         L.xUc = take(xb);
         L.xLr = o.adjoint ? take(xb) : 0;
         L.xUr = o.adjoint ? take(xb) : 0;
+        L.xscr = take(2 * xb * (o.adjoint ? 4 : 2));     // k_sweep_xfer partials
         L.sq = take(2 * sf * (size_t)p * ck.nch * k);     // first and second sweep of a D^{-1}
         L.sst = take(sf * (size_t)p * ck.nch * k);
         L.ticket = take(sizeof(unsigned) * (size_t)p);
@@ -602,6 +603,7 @@ int factor_t(sap_handle h, const double *a_band, hipStream_t s)
                              {lu.Ur, h->L.xUr, 1, 1}, {lu.Lr, h->L.xLr, 0, 0}};
         XferArgs<T> xa{};
         xa.pt = h->pt;
+        xa.scratch = h->ptr<T>(h->L.xscr);
         xa.nch = h->ck.nch;
         xa.clen = h->ck.clen;
         for (const Arr &r : arrs) {

@@ -172,6 +172,7 @@ struct XferArgs {
     const T *F[4];
     T *xf[4];
     int fwd[4], diag[4];
+    T *scratch;              // [narr][p][nch][2][K][K]: partial transfers X_2, X_3
 };
 template <typename T>
 hipError_t launch_sweep_xfer(const XferArgs<T> &a, hipStream_t s);
