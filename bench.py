@@ -115,6 +115,51 @@ def run_gpu(args, prec, pb, a, b):
     return (t1 - t0) * 1e3 / args.steps, stats, kt, xs
 
 
+# The paper's dense banded studies (Sec. 4.1.1-4.1.3), on synthetic matrices
+# generated as for the benchmark (sapgen): time to solution of SaP-C and SaP-D
+# with an FP32 preconditioner and FP64 BiCGStab(2), as the paper runs them.
+#   psweep: N = 200000, K = 200, d = 1, P varied (Sec. 4.1.1)
+#   dsweep: N = 200000, K = 200, P = 50, d in [0.06, 1.2] (Sec. 4.1.2)
+#   grid:   P = 50, d = 1, N x K (Table t:denseBandedSweep; K <= 255 here)
+EXPERIMENTS = {
+    "psweep": [dict(n=200000, k=200, p=p_, d=1.0) for p_ in (10, 20, 30, 40, 50, 64, 80, 100)],
+    "dsweep": [dict(n=200000, k=200, p=50, d=d_) for d_ in (0.06, 0.08, 0.1, 0.2, 0.4, 0.6, 0.8, 1.0, 1.2)],
+    "grid": [dict(n=n_, k=k_, p=50, d=1.0) for n_ in (10000, 50000, 200000, 1000000)
+             for k_ in (10, 20, 50, 100, 200)],
+}
+
+
+def run_experiment(args):
+    import numpy as np
+    import torch
+
+    import sapgen
+    dev = torch.device("cuda:0")
+    for c in EXPERIMENTS[args.experiment]:
+        pb = sapgen.make_problem(c["n"], c["k"], d=c["d"], seed=args.seed)
+        a = torch.from_numpy(pb.band).to(dev)
+        b = torch.from_numpy(pb.b).to(dev)
+        for mode in ("coupled", "decoupled"):
+            args.cfg = {"n": c["n"], "k": c["k"], "p": c["p"], "mode": mode, "tol": 1e-10}
+            line = {"experiment": args.experiment, "n": c["n"], "k": c["k"], "p": c["p"],
+                    "d": c["d"], "mode": "SaP-C" if mode == "coupled" else "SaP-D",
+                    "factor_prec": "fp32", "steps": args.steps}
+            try:
+                ms, stats, _, xs = run_gpu(args, "fp32", pb, a, b)
+                st = stats[-1]
+                line.update({"ms": round(ms, 3), "iters": st.iters, "restarts": st.restarts,
+                             "converged": bool(st.converged),
+                             "rel_resid_true": st.rel_resid_true,
+                             "t_factor_ms": round(st.t_factor_ms, 3),
+                             "t_solve_ms": round(st.t_solve_ms, 3),
+                             "rel_err_vs_xtrue": float(np.linalg.norm(xs - pb.x_true)
+                                                       / np.linalg.norm(pb.x_true))})
+            except Exception as e:      # e.g. not converged within maxit, or K unsupported
+                line["error"] = str(e)[:200]
+            print(json.dumps(line), flush=True)
+        del a, b
+
+
 def cpu_baseline(cfg, pb, reps):
     """The CPU oracle (plain FP64 SaP-C + BiCGStab(2)) on the same workload,
     single thread, median of `reps` full solves."""
@@ -148,11 +193,17 @@ def main():
     ap.add_argument("--race-steps", type=int, default=5)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 1 GiB device copy (counter calibration)")
+    ap.add_argument("--experiment", choices=sorted(EXPERIMENTS),
+                    help="instead of the benchmark line, run one of the paper's dense "
+                         "sensitivity studies and print one JSON line per configuration")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only; --gpus %d is not supported"
               % args.gpus, file=sys.stderr)
         sys.exit(2)
+    if args.experiment:
+        run_experiment(args)
+        return
 
     import numpy as np
     import torch
