@@ -313,6 +313,9 @@ __device__ void scalar_op(int op, const double *d, double *sc, double *host)
     case OP_TRUE:
         if (host) host[H_TRUE] = d[0];
         break;
+    case OP_SPEC:
+        if (host) host[H_SPEC] = d[0];
+        break;
     case OP_EXIT:
     case OP_NORM:
         sc[S_NRM2] = d[0]; publish = true;

@@ -459,8 +459,28 @@ int krylov(sap_handle h, int trans, const double *b, double *x, double tol, int3
     // residual is tested and the iteration restarted from it.
     const double reliable = h->fp32 ? 1e-4 : 0.0;
 
+    // recursive residuals at the last two exit tests since the (re)start
+    double pn_last = 0.0, pn_last2 = 0.0;
+    int pn_hist = 0;
     // exit test: returns 1 = converged, 2 = restarted, 0 = continue, < 0 error
     auto exit_test = [&]() -> int {
+        // When this test may converge or restart (the first after a
+        // (re)start, or when the last two tests extrapolate below the
+        // threshold), t = b - A x and its norm are enqueued before the
+        // synchronization: a converged test then needs no second round trip,
+        // and a restart reuses t.  Otherwise they are left out.
+        bool spec = !started;
+        if (started && pn_hist >= 2 && pn_last2 > 0.0) {
+            const double est = pn_last * (pn_last / pn_last2);
+            spec = est <= thr || est <= reliable * pstart;
+        }
+        if (spec) {
+            {
+                ProfScope ps(h, SAP_KERNEL_SPMV, s);
+                HIP_TRY(launch_spmv(A, n, k, x, b, t, trans, s));    // t = b - A x
+            }
+            TRY(dots(h, OP_SPEC, {{t, t}}, s));
+        }
         TRY(sync_read(h, s, &nrm2, &brk));
         if (tn_pending) {
             tn_restart = std::sqrt(h->h_slots[H_TRUE]);
@@ -477,12 +497,29 @@ int krylov(sap_handle h, int trans, const double *b, double *x, double tol, int3
                 thr = tol * bnorm * pstart / tn_restart;
             }
             started = true;
+            pn_hist = 0;
         }
         if (brk != 0.0) return SAP_ERR_BREAKDOWN;
         if (!std::isfinite(nrm2)) return SAP_ERR_BREAKDOWN;
         const double pn = std::sqrt(nrm2);
         loc.rel_resid_precond = pn / pnorm0;
+        pn_last2 = pn_last;
+        pn_last = pn;
+        ++pn_hist;
         if (pn > thr && !(pn <= reliable * pstart)) return 0;
+        if (spec) {
+            // t and its norm are already here: test, else restart from t
+            const double tn = std::sqrt(h->h_slots[H_SPEC]);
+            loc.rel_resid_true = tn / bnorm;
+            if (loc.rel_resid_true <= tol) return 1;
+            TRY(precond(h, trans, t, r0, s));
+            ++napply;
+            ++loc.restarts;
+            TRY(update(h, UPD_RESTART, x, OP_INIT, 2, s));
+            started = false;
+            tn_restart = tn;
+            return 2;
+        }
         {
             ProfScope ps(h, SAP_KERNEL_SPMV, s);
             HIP_TRY(launch_spmv(A, n, k, x, b, t, trans, s));    // t = b - A x

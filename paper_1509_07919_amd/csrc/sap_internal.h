@@ -53,6 +53,7 @@ enum KrylovOp : int {
     OP_FINAL,      // d0=(r0,r0) d1=(r0,rt): publish, then next j=0 prep
     OP_NORM,       // d0=(v,v): publish only
     OP_TRUE,       // d0=(t,t): the true residual at a restart, to host slot H_TRUE
+    OP_SPEC,       // d0=(t,t): the true residual ahead of an exit test, to H_SPEC
 };
 
 // device scalar slots of the BiCGStab(2) recurrences (double sc[kScalars])
@@ -64,9 +65,10 @@ enum ScalarSlot : int {
 // host-visible (pinned, mapped) result slots written by reduction kernels
 // H_NRM0: squared norm of the (re)started preconditioned residual (OP_INIT);
 // H_TRUE: squared norm of the true residual a restart started from (OP_TRUE);
-// H_NBOOST, H_SING: the factorization's status words (DotArgs::status)
+// H_NBOOST, H_SING: the factorization's status words (DotArgs::status);
+// H_SPEC: squared norm of the true residual enqueued ahead of an exit test
 enum HostSlot : int { H_NRM2 = 0, H_BREAK = 1, H_NRM0 = 2, H_TRUE = 3, H_NBOOST = 4, H_SING = 5,
-                      kHostSlots = 8 };
+                      H_SPEC = 6, kHostSlots = 8 };
 
 struct Partition {
     const int64_t *starts;   // P+1 block boundaries (device)
