@@ -16,15 +16,16 @@
 //
 // One 256-thread workgroup per interface.  When the four K x K working
 // matrices fit in LDS, k_tips_lds spreads every step over all threads (K <=
-// 71 for FP64 factors, K <= 100 for FP32); else k_tips_global keeps them in
-// global memory with one thread per right-hand-side column.  This step is
-// O(P K^3) and runs once per factorization.
+// 71 for FP64 factors, K <= 100 for FP32); else the k_tips_global_* kernels
+// keep them in global memory with one thread per right-hand-side column, V
+// and W side by side and Rbar split by rows.  This step is O(P K^3) and runs
+// once per factorization.
 #include "sap_internal.h"
 
 namespace sap {
 
 // Workgroup barrier that also orders the workgroup's global-memory accesses
-// (the working matrices of k_tips_global live in global memory).
+// (the working matrices of the k_tips_global_* kernels live in global memory).
 __device__ __forceinline__ void block_sync()
 {
     __threadfence_block();
@@ -48,87 +49,113 @@ __device__ __forceinline__ T rowdot(const T *M, const T *X, int k, int r, int b,
     return (s0 + s1) + (s2 + s3);
 }
 
-// Global-memory version, for K too large for LDS: X, Y (right-hand-side
-// columns, thread b owns column b) and F (the staged K x K factor corner,
-// later Rbar and its LU) are row-major K x K working matrices in the V, W and
-// Rlu slots; the Rinv columns are solved in place in Rinv.
+// Global-memory version, for K too large for LDS, in three launches (the
+// K x K working matrices are row-major in global memory, one thread per
+// right-hand-side column):
+//   k_tips_global_vw    grid (P-1, 2): y = 0 stages B_i and the bottom-right
+//                       corner of LU(A_i) (in the Rlu slot) and forms V in
+//                       the V slot; y = 1 stages C_{i+1} and the corner of the
+//                       UL factorization (in the Rbar slot) and forms W in the
+//                       W slot; the two substitutions run side by side;
+//   k_tips_global_rbar  grid (P-1, kTipsRowSplit): Rbar = I - W V, each
+//                       workgroup a range of rows, into the Rbar and Rlu slots;
+//   k_tips_global_lu    grid (P-1): the pivoted LU of Rbar in the Rlu slot,
+//                       then the Rinv columns, solved in place in Rinv.
+constexpr int kTipsRowSplit = 4;
+
 template <typename T>
-__global__ __launch_bounds__(256) void k_tips_global(TipsArgs<T> a)
+__global__ __launch_bounds__(256) void k_tips_global_vw(TipsArgs<T> a)
 {
     const int i = blockIdx.x;                   // interface i: blocks i, i+1
     const int k = a.pt.k;
     const int64_t n = a.pt.n;
-    const int CS = k + 1;
     const int CP = coef_pitch(k, (int)sizeof(T));   // row pitch in HBM
     const int64_t s1 = a.pt.starts[i + 1];      // first row of block i+1
     const int64_t kk = (int64_t)k * k;
-    T *B = a.B + i * kk, *C = a.C + i * kk, *V = a.V + i * kk, *W = a.W + i * kk;
-    T *R = a.Rbar + i * kk, *RI = a.Rinv + i * kk;
-    T *X = V;
-    T *Y = W;
-    T *F = a.Rlu + i * kk;
-    T *Z = RI;                                  // Rinv working columns
-    int *piv = a.piv + (int64_t)i * k;
-    const T *cn = a.corner + (int64_t)(i + 1) * kk;   // UL corner of block i+1
     const int tid = threadIdx.x;
-    const int64_t base = s1 - k;                // first row of block i's bottom corner
-    __shared__ int pr_sh;
-    __shared__ int piv_sh[kMaxK];
-    __shared__ T zero_sh;
-
-    // B_i (lower triangular incl. diagonal) -> X, C_{i+1} (upper triangular)
-    // -> Y, and the bottom-right corner of LU(A_i) -> F, with
-    // F[r][c] = l(base+r, base+c) for r > c (unit diagonal implied) and
-    // F[r][c] = u(base+r, base+c) for r <= c; the stored diagonal of U is
-    // its reciprocal.
-    for (int64_t e = tid; e < kk; e += 256) {
-        const int r = (int)(e / k), c = (int)(e % k);
-        const int64_t br = s1 - k + r, bc = s1 + c;          // B: a[br][bc]
-        const T bv = (c <= r) ? (T)a.band[(int64_t)(k + br - bc) * n + bc] : T(0);
-        const int64_t cr = s1 + r, cc = s1 - k + c;          // C: a[cr][cc]
-        const T cv = (r <= c) ? (T)a.band[(int64_t)(k + cr - cc) * n + cc] : T(0);
-        B[e] = bv;
-        C[e] = cv;
-        X[e] = bv;
-        Y[e] = cv;
-        F[e] = (r > c) ? a.Lc[(base + c) * CP + (r - c)]
-                       : a.Uc[(base + c) * CP + (c - r)];    // c == r: 1/u_rr
-    }
-    if (tid == 0) zero_sh = T(0);
-    block_sync();
-
     const int b = tid;
-    if (b < k) {
-        // V = U_bb^{-1} (L_bb^{-1} B_i), column b, in X
-        for (int r = 1; r < k; ++r) X[r * k + b] -= rowdot(F, X, k, r, b, 0, r);
-        for (int r = k - 1; r >= 0; --r)
-            X[r * k + b] = (X[r * k + b] - rowdot(F, X, k, r, b, r + 1, k)) * F[r * k + r];
+    if (blockIdx.y == 0) {
+        T *B = a.B + i * kk, *X = a.V + i * kk, *F = a.Rlu + i * kk;
+        const int64_t base = s1 - k;            // first row of block i's bottom corner
+        // B_i (lower triangular incl. diagonal) -> B and X, and the
+        // bottom-right corner of LU(A_i) -> F, with F[r][c] = l(base+r,
+        // base+c) for r > c (unit diagonal implied) and F[r][c] = u(base+r,
+        // base+c) for r <= c; the stored diagonal of U is its reciprocal
+        for (int64_t e = tid; e < kk; e += 256) {
+            const int r = (int)(e / k), c = (int)(e % k);
+            const int64_t br = s1 - k + r, bc = s1 + c;      // B: a[br][bc]
+            const T bv = (c <= r) ? (T)a.band[(int64_t)(k + br - bc) * n + bc] : T(0);
+            B[e] = bv;
+            X[e] = bv;
+            F[e] = (r > c) ? a.Lc[(base + c) * CP + (r - c)]
+                           : a.Uc[(base + c) * CP + (c - r)];    // c == r: 1/u_rr
+        }
+        block_sync();
+        if (b < k) {
+            // V = U_bb^{-1} (L_bb^{-1} B_i), column b
+            for (int r = 1; r < k; ++r) X[r * k + b] -= rowdot(F, X, k, r, b, 0, r);
+            for (int r = k - 1; r >= 0; --r)
+                X[r * k + b] = (X[r * k + b] - rowdot(F, X, k, r, b, r + 1, k)) * F[r * k + r];
+        }
+    } else {
+        T *C = a.C + i * kk, *Y = a.W + i * kk, *F = a.Rbar + i * kk;
+        const T *cn = a.corner + (int64_t)(i + 1) * kk;   // UL corner of block i+1
+        // C_{i+1} (upper triangular) -> C and Y, and the corner of
+        // LU(J A_{i+1} J) reversed -> F: F[r][c] = cn[(k-1-r)*k + (k-1-c)],
+        // i.e. U'_tt (unit upper) above the diagonal and L'_tt on and below it
+        for (int64_t e = tid; e < kk; e += 256) {
+            const int r = (int)(e / k), c = (int)(e % k);
+            const int64_t cr = s1 + r, cc = s1 - k + c;      // C: a[cr][cc]
+            const T cv = (r <= c) ? (T)a.band[(int64_t)(k + cr - cc) * n + cc] : T(0);
+            C[e] = cv;
+            Y[e] = cv;
+            F[e] = cn[(int64_t)(k - 1 - r) * k + (k - 1 - c)];
+        }
+        block_sync();
+        if (b < k) {
+            // W = L'_tt^{-1} (U'_tt^{-1} C_{i+1}), column b
+            for (int r = k - 2; r >= 0; --r) Y[r * k + b] -= rowdot(F, Y, k, r, b, r + 1, k);
+            for (int r = 0; r < k; ++r)
+                Y[r * k + b] = (Y[r * k + b] - rowdot(F, Y, k, r, b, 0, r)) / F[r * k + r];
+        }
     }
-    block_sync();
-    // corner of LU(J A_{i+1} J) -> F reversed: F[r][c] = cn[(k-1-r)*k + (k-1-c)],
-    // i.e. U'_tt (unit upper) above the diagonal and L'_tt on and below it
-    for (int64_t e = tid; e < kk; e += 256) {
-        const int r = (int)(e / k), c = (int)(e % k);
-        F[e] = cn[(int64_t)(k - 1 - r) * k + (k - 1 - c)];
-        V[e] = X[e];
-    }
-    block_sync();
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_tips_global_rbar(TipsArgs<T> a)
+{
+    const int i = blockIdx.x;
+    const int k = a.pt.k;
+    const int64_t kk = (int64_t)k * k;
+    const T *X = a.V + i * kk, *Y = a.W + i * kk;
+    T *R = a.Rbar + i * kk, *F = a.Rlu + i * kk;
+    const int rows = (k + kTipsRowSplit - 1) / kTipsRowSplit;
+    const int r0 = (int)blockIdx.y * rows, r1 = min(k, r0 + rows);
+    const int b = threadIdx.x;
     if (b < k) {
-        // W = L'_tt^{-1} (U'_tt^{-1} C_{i+1}), column b, in Y
-        for (int r = k - 2; r >= 0; --r) Y[r * k + b] -= rowdot(F, Y, k, r, b, r + 1, k);
-        for (int r = 0; r < k; ++r)
-            Y[r * k + b] = (Y[r * k + b] - rowdot(F, Y, k, r, b, 0, r)) / F[r * k + r];
-    }
-    block_sync();
-    // Rbar = I - W V -> F and R (global)
-    for (int64_t e = tid; e < kk; e += 256) W[e] = Y[e];
-    if (b < k) {
-        for (int r = 0; r < k; ++r) {
+        for (int r = r0; r < r1; ++r) {
             const T s = ((r == b) ? T(1) : T(0)) - rowdot(Y, X, k, r, b, 0, k);
             R[r * k + b] = s;
             F[r * k + b] = s;
         }
     }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_tips_global_lu(TipsArgs<T> a)
+{
+    const int i = blockIdx.x;
+    const int k = a.pt.k;
+    const int64_t kk = (int64_t)k * k;
+    T *F = a.Rlu + i * kk;
+    T *Z = a.Rinv + i * kk;                     // Rinv working columns
+    int *piv = a.piv + (int64_t)i * k;
+    const int tid = threadIdx.x;
+    const int b = tid;
+    __shared__ int pr_sh;
+    __shared__ int piv_sh[kMaxK];
+    __shared__ T zero_sh;
+    if (tid == 0) zero_sh = T(0);
     block_sync();
     // LU with partial pivoting of Rbar in F (ties to the lowest row); the
     // pivot search is a wave-0 argmax
@@ -457,7 +484,10 @@ hipError_t launch_tips(const TipsArgs<T> &a, hipStream_t s)
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(kern, dim3(a.pt.p - 1), dim3(256), lds, s, a);
     } else {
-        hipLaunchKernelGGL(k_tips_global<T>, dim3(a.pt.p - 1), dim3(256), 0, s, a);
+        hipLaunchKernelGGL(k_tips_global_vw<T>, dim3(a.pt.p - 1, 2), dim3(256), 0, s, a);
+        hipLaunchKernelGGL(k_tips_global_rbar<T>, dim3(a.pt.p - 1, kTipsRowSplit), dim3(256), 0,
+                           s, a);
+        hipLaunchKernelGGL(k_tips_global_lu<T>, dim3(a.pt.p - 1), dim3(256), 0, s, a);
     }
     return hipGetLastError();
 }
