@@ -49,22 +49,30 @@ __device__ __forceinline__ T rowdot(const T *M, const T *X, int k, int r, int b,
     return (s0 + s1) + (s2 + s3);
 }
 
-// Global-memory version, for K too large for LDS, in three launches (the
-// K x K working matrices are row-major in global memory, one thread per
-// right-hand-side column):
-//   k_tips_global_vw    grid (P-1, 2): y = 0 stages B_i and the bottom-right
-//                       corner of LU(A_i) (in the Rlu slot) and forms V in
-//                       the V slot; y = 1 stages C_{i+1} and the corner of the
-//                       UL factorization (in the Rbar slot) and forms W in the
-//                       W slot; the two substitutions run side by side;
+// Global-memory version, for K too large for LDS, in five launches (the
+// K x K working matrices are row-major in global memory):
+//   k_tips_global_stage grid (P-1, 2): y = 0 stages B_i (into the B and V
+//                       slots) and the bottom-right corner of LU(A_i) (into
+//                       the Rlu slot); y = 1 stages C_{i+1} (into the C and W
+//                       slots) and the corner of the UL factorization (into
+//                       the Rbar slot);
+//   k_tips_global_vw    grid (P-1, 2 x column groups), one wave: V (y <
+//                       groups) or W by substitution, one thread per
+//                       right-hand-side column, the wave's 64 columns held in
+//                       LDS and the factor corner read from global memory
+//                       (the same address in every lane);
 //   k_tips_global_rbar  grid (P-1, kTipsRowSplit): Rbar = I - W V, each
 //                       workgroup a range of rows, into the Rbar and Rlu slots;
-//   k_tips_global_lu    grid (P-1): the pivoted LU of Rbar in the Rlu slot,
-//                       then the Rinv columns, solved in place in Rinv.
+//   k_tips_global_lu    grid (P-1): the pivoted LU of Rbar in the Rlu slot;
+//   k_tips_global_rinv  grid (P-1, column groups), one wave: the Rinv columns
+//                       from the pivoted LU, held in LDS like V and W.
+// Each column's substitution is a chain over K rows; with the column in LDS a
+// row no longer waits for a global round trip of the values stored by the
+// row before.
 constexpr int kTipsRowSplit = 4;
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_tips_global_vw(TipsArgs<T> a)
+__global__ __launch_bounds__(256) void k_tips_global_stage(TipsArgs<T> a)
 {
     const int i = blockIdx.x;                   // interface i: blocks i, i+1
     const int k = a.pt.k;
@@ -73,7 +81,6 @@ __global__ __launch_bounds__(256) void k_tips_global_vw(TipsArgs<T> a)
     const int64_t s1 = a.pt.starts[i + 1];      // first row of block i+1
     const int64_t kk = (int64_t)k * k;
     const int tid = threadIdx.x;
-    const int b = tid;
     if (blockIdx.y == 0) {
         T *B = a.B + i * kk, *X = a.V + i * kk, *F = a.Rlu + i * kk;
         const int64_t base = s1 - k;            // first row of block i's bottom corner
@@ -90,13 +97,6 @@ __global__ __launch_bounds__(256) void k_tips_global_vw(TipsArgs<T> a)
             F[e] = (r > c) ? a.Lc[(base + c) * CP + (r - c)]
                            : a.Uc[(base + c) * CP + (c - r)];    // c == r: 1/u_rr
         }
-        block_sync();
-        if (b < k) {
-            // V = U_bb^{-1} (L_bb^{-1} B_i), column b
-            for (int r = 1; r < k; ++r) X[r * k + b] -= rowdot(F, X, k, r, b, 0, r);
-            for (int r = k - 1; r >= 0; --r)
-                X[r * k + b] = (X[r * k + b] - rowdot(F, X, k, r, b, r + 1, k)) * F[r * k + r];
-        }
     } else {
         T *C = a.C + i * kk, *Y = a.W + i * kk, *F = a.Rbar + i * kk;
         const T *cn = a.corner + (int64_t)(i + 1) * kk;   // UL corner of block i+1
@@ -111,14 +111,56 @@ __global__ __launch_bounds__(256) void k_tips_global_vw(TipsArgs<T> a)
             Y[e] = cv;
             F[e] = cn[(int64_t)(k - 1 - r) * k + (k - 1 - c)];
         }
-        block_sync();
-        if (b < k) {
-            // W = L'_tt^{-1} (U'_tt^{-1} C_{i+1}), column b
-            for (int r = k - 2; r >= 0; --r) Y[r * k + b] -= rowdot(F, Y, k, r, b, r + 1, k);
-            for (int r = 0; r < k; ++r)
-                Y[r * k + b] = (Y[r * k + b] - rowdot(F, Y, k, r, b, 0, r)) / F[r * k + r];
-        }
     }
+}
+
+// dot of row r of M (entries c in [c0, c1), global) with the column of
+// thread t held in LDS (xs[c * 64 + t]); the same summation order as rowdot
+template <typename T>
+__device__ __forceinline__ T rowdot_lds(const T *__restrict__ M, const T *xs, int k, int r, int t,
+                                        int c0, int c1)
+{
+    T s0 = T(0), s1 = T(0), s2 = T(0), s3 = T(0);
+    int c = c0;
+    for (; c + 3 < c1; c += 4) {
+        s0 = fma(M[r * k + c], xs[c * 64 + t], s0);
+        s1 = fma(M[r * k + c + 1], xs[(c + 1) * 64 + t], s1);
+        s2 = fma(M[r * k + c + 2], xs[(c + 2) * 64 + t], s2);
+        s3 = fma(M[r * k + c + 3], xs[(c + 3) * 64 + t], s3);
+    }
+    for (; c < c1; ++c) s0 = fma(M[r * k + c], xs[c * 64 + t], s0);
+    return (s0 + s1) + (s2 + s3);
+}
+
+// V = U_bb^{-1} (L_bb^{-1} B_i) or W = L'_tt^{-1} (U'_tt^{-1} C_{i+1}) for
+// the 64 columns of this workgroup; each thread works on its own column
+// only, so the kernel has no barrier
+template <typename T>
+__global__ __launch_bounds__(64) void k_tips_global_vw(TipsArgs<T> a)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T *xs = reinterpret_cast<T *>(smem_raw);    // [K][64]
+    const int i = blockIdx.x;
+    const int k = a.pt.k;
+    const int ncg = (k + 63) / 64;
+    const int which = (int)blockIdx.y / ncg;    // 0: V, 1: W
+    const int t = threadIdx.x;
+    const int b = ((int)blockIdx.y % ncg) * 64 + t;
+    const int64_t kk = (int64_t)k * k;
+    if (b >= k) return;
+    T *X = (which == 0 ? a.V : a.W) + i * kk;
+    const T *__restrict__ F = (which == 0 ? a.Rlu : a.Rbar) + i * kk;
+    for (int c = 0; c < k; ++c) xs[c * 64 + t] = X[c * k + b];
+    if (which == 0) {
+        for (int r = 1; r < k; ++r) xs[r * 64 + t] -= rowdot_lds(F, xs, k, r, t, 0, r);
+        for (int r = k - 1; r >= 0; --r)
+            xs[r * 64 + t] = (xs[r * 64 + t] - rowdot_lds(F, xs, k, r, t, r + 1, k)) * F[r * k + r];
+    } else {
+        for (int r = k - 2; r >= 0; --r) xs[r * 64 + t] -= rowdot_lds(F, xs, k, r, t, r + 1, k);
+        for (int r = 0; r < k; ++r)
+            xs[r * 64 + t] = (xs[r * 64 + t] - rowdot_lds(F, xs, k, r, t, 0, r)) / F[r * k + r];
+    }
+    for (int c = 0; c < k; ++c) X[c * k + b] = xs[c * 64 + t];
 }
 
 template <typename T>
@@ -148,12 +190,9 @@ __global__ __launch_bounds__(256) void k_tips_global_lu(TipsArgs<T> a)
     const int k = a.pt.k;
     const int64_t kk = (int64_t)k * k;
     T *F = a.Rlu + i * kk;
-    T *Z = a.Rinv + i * kk;                     // Rinv working columns
     int *piv = a.piv + (int64_t)i * k;
     const int tid = threadIdx.x;
-    const int b = tid;
     __shared__ int pr_sh;
-    __shared__ int piv_sh[kMaxK];
     __shared__ T zero_sh;
     if (tid == 0) zero_sh = T(0);
     block_sync();
@@ -174,7 +213,6 @@ __global__ __launch_bounds__(256) void k_tips_global_lu(TipsArgs<T> a)
             }
             if (tid == 0) {
                 piv[j] = p;
-                piv_sh[j] = p;
                 pr_sh = p;
                 if (best == T(0)) a.status[1] = 2;
             }
@@ -199,23 +237,38 @@ __global__ __launch_bounds__(256) void k_tips_global_lu(TipsArgs<T> a)
         for (int r = j + 1 + tid; r < k; r += 256) F[r * k + j] *= dinv;
         block_sync();
     }
-    // Rinv = Rbar^{-1}: column b solves Rbar y = e_b with the pivoted LU (in Z)
-    if (b < k) {
-        for (int r = 0; r < k; ++r) Z[r * k + b] = (r == b) ? T(1) : T(0);
-        for (int j = 0; j < k; ++j) {                  // apply interchanges
-            const int p = piv_sh[j];
-            if (p != j) {
-                const T t = Z[j * k + b];
-                Z[j * k + b] = Z[p * k + b];
-                Z[p * k + b] = t;
-            }
-        }
-        for (int r = 1; r < k; ++r) Z[r * k + b] -= rowdot(F, Z, k, r, b, 0, r);
-        for (int r = k - 1; r >= 0; --r)
-            Z[r * k + b] = (Z[r * k + b] - rowdot(F, Z, k, r, b, r + 1, k)) / F[r * k + r];
-    }
 }
 
+// Rinv = Rbar^{-1}: column b solves Rbar y = e_b with the pivoted LU of the
+// Rlu slot, held in LDS like V and W
+template <typename T>
+__global__ __launch_bounds__(64) void k_tips_global_rinv(TipsArgs<T> a)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T *xs = reinterpret_cast<T *>(smem_raw);    // [K][64]
+    const int i = blockIdx.x;
+    const int k = a.pt.k;
+    const int t = threadIdx.x;
+    const int b = (int)blockIdx.y * 64 + t;
+    const int64_t kk = (int64_t)k * k;
+    if (b >= k) return;
+    const T *__restrict__ F = a.Rlu + i * kk;
+    const int *__restrict__ piv = a.piv + (int64_t)i * k;
+    for (int r = 0; r < k; ++r) xs[r * 64 + t] = (r == b) ? T(1) : T(0);
+    for (int j = 0; j < k; ++j) {                      // apply interchanges
+        const int p = piv[j];
+        if (p != j) {
+            const T v = xs[j * 64 + t];
+            xs[j * 64 + t] = xs[p * 64 + t];
+            xs[p * 64 + t] = v;
+        }
+    }
+    for (int r = 1; r < k; ++r) xs[r * 64 + t] -= rowdot_lds(F, xs, k, r, t, 0, r);
+    for (int r = k - 1; r >= 0; --r)
+        xs[r * 64 + t] = (xs[r * 64 + t] - rowdot_lds(F, xs, k, r, t, r + 1, k)) / F[r * k + r];
+    T *Z = a.Rinv + i * kk;
+    for (int r = 0; r < k; ++r) Z[r * k + b] = xs[r * 64 + t];
+}
 
 
 // ---------------------------------------------------------------------------
@@ -484,10 +537,19 @@ hipError_t launch_tips(const TipsArgs<T> &a, hipStream_t s)
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(kern, dim3(a.pt.p - 1), dim3(256), lds, s, a);
     } else {
-        hipLaunchKernelGGL(k_tips_global_vw<T>, dim3(a.pt.p - 1, 2), dim3(256), 0, s, a);
+        const int ncg = (a.pt.k + 63) / 64;
+        const size_t cols = (size_t)a.pt.k * 64 * sizeof(T);    // <= 130560 B at K = 255
+        if (cols > kMaxLds) return hipErrorInvalidValue;
+        for (const void *f : {(const void *)k_tips_global_vw<T>, (const void *)k_tips_global_rinv<T>}) {
+            hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)cols);
+            if (e != hipSuccess) return e;
+        }
+        hipLaunchKernelGGL(k_tips_global_stage<T>, dim3(a.pt.p - 1, 2), dim3(256), 0, s, a);
+        hipLaunchKernelGGL(k_tips_global_vw<T>, dim3(a.pt.p - 1, 2 * ncg), dim3(64), cols, s, a);
         hipLaunchKernelGGL(k_tips_global_rbar<T>, dim3(a.pt.p - 1, kTipsRowSplit), dim3(256), 0,
                            s, a);
         hipLaunchKernelGGL(k_tips_global_lu<T>, dim3(a.pt.p - 1), dim3(256), 0, s, a);
+        hipLaunchKernelGGL(k_tips_global_rinv<T>, dim3(a.pt.p - 1, ncg), dim3(64), cols, s, a);
     }
     return hipGetLastError();
 }
