@@ -63,7 +63,9 @@ __device__ __forceinline__ T rowdot(const T *M, const T *X, int k, int r, int b,
 //                       (the same address in every lane);
 //   k_tips_global_rbar  grid (P-1, kTipsRowSplit): Rbar = I - W V, each
 //                       workgroup a range of rows, into the Rbar and Rlu slots;
-//   k_tips_global_lu    grid (P-1): the pivoted LU of Rbar in the Rlu slot;
+//   k_tips_global_lu    grid (P-1): the pivoted LU of Rbar, in LDS when K^2
+//                       elements fit (FP32 K <= 202, FP64 K <= 143), stored
+//                       in the Rlu slot;
 //   k_tips_global_rinv  grid (P-1, column groups), one wave: the Rinv columns
 //                       from the pivoted LU, held in LDS like V and W.
 // Each column's substitution is a chain over K rows; with the column in LDS a
@@ -183,17 +185,23 @@ __global__ __launch_bounds__(256) void k_tips_global_rbar(TipsArgs<T> a)
     }
 }
 
-template <typename T>
+// INLDS: Rbar is factored in LDS (K^2 elements of dynamic LDS) and written
+// back to the Rlu slot at the end; else in place in the Rlu slot
+template <typename T, bool INLDS>
 __global__ __launch_bounds__(256) void k_tips_global_lu(TipsArgs<T> a)
 {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
     const int i = blockIdx.x;
     const int k = a.pt.k;
     const int64_t kk = (int64_t)k * k;
-    T *F = a.Rlu + i * kk;
+    T *G = a.Rlu + i * kk;
+    T *F = INLDS ? reinterpret_cast<T *>(smem_raw) : G;
     int *piv = a.piv + (int64_t)i * k;
     const int tid = threadIdx.x;
     __shared__ int pr_sh;
     __shared__ T zero_sh;
+    if (INLDS)
+        for (int e = tid; e < kk; e += 256) F[e] = G[e];
     if (tid == 0) zero_sh = T(0);
     block_sync();
     // LU with partial pivoting of Rbar in F (ties to the lowest row); the
@@ -237,6 +245,8 @@ __global__ __launch_bounds__(256) void k_tips_global_lu(TipsArgs<T> a)
         for (int r = j + 1 + tid; r < k; r += 256) F[r * k + j] *= dinv;
         block_sync();
     }
+    if (INLDS)
+        for (int e = tid; e < kk; e += 256) G[e] = F[e];
 }
 
 // Rinv = Rbar^{-1}: column b solves Rbar y = e_b with the pivoted LU of the
@@ -548,7 +558,15 @@ hipError_t launch_tips(const TipsArgs<T> &a, hipStream_t s)
         hipLaunchKernelGGL(k_tips_global_vw<T>, dim3(a.pt.p - 1, 2 * ncg), dim3(64), cols, s, a);
         hipLaunchKernelGGL(k_tips_global_rbar<T>, dim3(a.pt.p - 1, kTipsRowSplit), dim3(256), 0,
                            s, a);
-        hipLaunchKernelGGL(k_tips_global_lu<T>, dim3(a.pt.p - 1), dim3(256), 0, s, a);
+        const size_t rb = kk * sizeof(T);
+        if (rb + 64 <= kMaxLds) {               // + pr_sh, zero_sh
+            hipError_t e = hipFuncSetAttribute((const void *)k_tips_global_lu<T, true>,
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)rb);
+            if (e != hipSuccess) return e;
+            hipLaunchKernelGGL((k_tips_global_lu<T, true>), dim3(a.pt.p - 1), dim3(256), rb, s, a);
+        } else {
+            hipLaunchKernelGGL((k_tips_global_lu<T, false>), dim3(a.pt.p - 1), dim3(256), 0, s, a);
+        }
         hipLaunchKernelGGL(k_tips_global_rinv<T>, dim3(a.pt.p - 1, ncg), dim3(64), cols, s, a);
     }
     return hipGetLastError();
