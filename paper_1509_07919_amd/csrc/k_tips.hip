@@ -68,9 +68,8 @@ __device__ __forceinline__ T rowdot(const T *M, const T *X, int k, int r, int b,
 //                       in the Rlu slot;
 //   k_tips_global_rinv  grid (P-1, column groups), one wave: the Rinv columns
 //                       from the pivoted LU, held in LDS like V and W.
-// Each column's substitution is a chain over K rows; with the column in LDS a
-// row no longer waits for a global round trip of the values stored by the
-// row before.
+// Each column's substitution is a chain over K rows; with the column and the
+// factor row in LDS a row waits on LDS only, not on a global round trip.
 constexpr int kTipsRowSplit = 4;
 
 template <typename T>
@@ -116,22 +115,60 @@ __global__ __launch_bounds__(256) void k_tips_global_stage(TipsArgs<T> a)
     }
 }
 
-// dot of row r of M (entries c in [c0, c1), global) with the column of
-// thread t held in LDS (xs[c * 64 + t]); the same summation order as rowdot
-template <typename T>
-__device__ __forceinline__ T rowdot_lds(const T *__restrict__ M, const T *xs, int k, int r, int t,
-                                        int c0, int c1)
+// Row-by-row substitution on the columns held in LDS (xs[c * 64 + t]) by a
+// one-wave workgroup.  FWD: rows rfirst..K-1, each minus its dot over
+// columns [0, r); else rows rfirst..0, each minus its dot over [r+1, K).
+// DIAG: 0 unit diagonal, 1 multiply by M[r][r] (a stored reciprocal), 2
+// divide by it.  The wave stages each factor row in LDS (fs, two K-element
+// slots), loading the row after next into registers while it works on the
+// current one, so a row waits on LDS only; the dot keeps rowdot's order.
+template <typename T, bool FWD, int DIAG>
+__device__ __forceinline__ void subst_rows(const T *__restrict__ M, T *xs, T *fs, int k, int t,
+                                           int rfirst)
 {
-    T s0 = T(0), s1 = T(0), s2 = T(0), s3 = T(0);
-    int c = c0;
-    for (; c + 3 < c1; c += 4) {
-        s0 = fma(M[r * k + c], xs[c * 64 + t], s0);
-        s1 = fma(M[r * k + c + 1], xs[(c + 1) * 64 + t], s1);
-        s2 = fma(M[r * k + c + 2], xs[(c + 2) * 64 + t], s2);
-        s3 = fma(M[r * k + c + 3], xs[(c + 3) * 64 + t], s3);
+    const int nrow = FWD ? k - rfirst : rfirst + 1;
+    if (nrow <= 0) return;
+    T pre[4];                                   // K <= 255: four entries per lane
+    auto issue = [&](int s2) {
+        const int r = FWD ? rfirst + s2 : rfirst - s2;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int c = t + 64 * q;
+            pre[q] = (s2 < nrow && c < k) ? M[r * k + c] : T(0);
+        }
+    };
+    auto commit = [&](T *dst) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int c = t + 64 * q;
+            if (c < k) dst[c] = pre[q];
+        }
+        __builtin_amdgcn_wave_barrier();
+    };
+    issue(0);
+    commit(fs);
+    issue(1);
+    for (int s2 = 0; s2 < nrow; ++s2) {
+        const int r = FWD ? rfirst + s2 : rfirst - s2;
+        const T *f = fs + (s2 & 1) * k;
+        const int c0 = FWD ? 0 : r + 1, c1 = FWD ? r : k;
+        T s0 = T(0), s1 = T(0), s2v = T(0), s3 = T(0);
+        int c = c0;
+        for (; c + 3 < c1; c += 4) {
+            s0 = fma(f[c], xs[c * 64 + t], s0);
+            s1 = fma(f[c + 1], xs[(c + 1) * 64 + t], s1);
+            s2v = fma(f[c + 2], xs[(c + 2) * 64 + t], s2v);
+            s3 = fma(f[c + 3], xs[(c + 3) * 64 + t], s3);
+        }
+        for (; c < c1; ++c) s0 = fma(f[c], xs[c * 64 + t], s0);
+        T v = xs[r * 64 + t] - ((s0 + s1) + (s2v + s3));
+        if (DIAG == 1) v *= f[r];
+        if (DIAG == 2) v /= f[r];
+        xs[r * 64 + t] = v;
+        __builtin_amdgcn_wave_barrier();
+        commit(fs + ((s2 + 1) & 1) * k);
+        issue(s2 + 2);
     }
-    for (; c < c1; ++c) s0 = fma(M[r * k + c], xs[c * 64 + t], s0);
-    return (s0 + s1) + (s2 + s3);
 }
 
 // V = U_bb^{-1} (L_bb^{-1} B_i) or W = L'_tt^{-1} (U'_tt^{-1} C_{i+1}) for
@@ -149,20 +186,20 @@ __global__ __launch_bounds__(64) void k_tips_global_vw(TipsArgs<T> a)
     const int t = threadIdx.x;
     const int b = ((int)blockIdx.y % ncg) * 64 + t;
     const int64_t kk = (int64_t)k * k;
-    if (b >= k) return;
+    const bool act = b < k;                     // every lane stages factor rows
+    T *fs = xs + (size_t)k * 64;                // [2][K]
     T *X = (which == 0 ? a.V : a.W) + i * kk;
     const T *__restrict__ F = (which == 0 ? a.Rlu : a.Rbar) + i * kk;
-    for (int c = 0; c < k; ++c) xs[c * 64 + t] = X[c * k + b];
+    for (int c = 0; c < k; ++c) xs[c * 64 + t] = act ? X[c * k + b] : T(0);
     if (which == 0) {
-        for (int r = 1; r < k; ++r) xs[r * 64 + t] -= rowdot_lds(F, xs, k, r, t, 0, r);
-        for (int r = k - 1; r >= 0; --r)
-            xs[r * 64 + t] = (xs[r * 64 + t] - rowdot_lds(F, xs, k, r, t, r + 1, k)) * F[r * k + r];
+        subst_rows<T, true, 0>(F, xs, fs, k, t, 1);
+        subst_rows<T, false, 1>(F, xs, fs, k, t, k - 1);
     } else {
-        for (int r = k - 2; r >= 0; --r) xs[r * 64 + t] -= rowdot_lds(F, xs, k, r, t, r + 1, k);
-        for (int r = 0; r < k; ++r)
-            xs[r * 64 + t] = (xs[r * 64 + t] - rowdot_lds(F, xs, k, r, t, 0, r)) / F[r * k + r];
+        subst_rows<T, false, 0>(F, xs, fs, k, t, k - 2);
+        subst_rows<T, true, 2>(F, xs, fs, k, t, 0);
     }
-    for (int c = 0; c < k; ++c) X[c * k + b] = xs[c * 64 + t];
+    if (act)
+        for (int c = 0; c < k; ++c) X[c * k + b] = xs[c * 64 + t];
 }
 
 template <typename T>
@@ -261,7 +298,8 @@ __global__ __launch_bounds__(64) void k_tips_global_rinv(TipsArgs<T> a)
     const int t = threadIdx.x;
     const int b = (int)blockIdx.y * 64 + t;
     const int64_t kk = (int64_t)k * k;
-    if (b >= k) return;
+    const bool act = b < k;                     // every lane stages factor rows
+    T *fs = xs + (size_t)k * 64;                // [2][K]
     const T *__restrict__ F = a.Rlu + i * kk;
     const int *__restrict__ piv = a.piv + (int64_t)i * k;
     for (int r = 0; r < k; ++r) xs[r * 64 + t] = (r == b) ? T(1) : T(0);
@@ -273,11 +311,11 @@ __global__ __launch_bounds__(64) void k_tips_global_rinv(TipsArgs<T> a)
             xs[p * 64 + t] = v;
         }
     }
-    for (int r = 1; r < k; ++r) xs[r * 64 + t] -= rowdot_lds(F, xs, k, r, t, 0, r);
-    for (int r = k - 1; r >= 0; --r)
-        xs[r * 64 + t] = (xs[r * 64 + t] - rowdot_lds(F, xs, k, r, t, r + 1, k)) / F[r * k + r];
+    subst_rows<T, true, 0>(F, xs, fs, k, t, 1);
+    subst_rows<T, false, 2>(F, xs, fs, k, t, k - 1);
     T *Z = a.Rinv + i * kk;
-    for (int r = 0; r < k; ++r) Z[r * k + b] = xs[r * 64 + t];
+    if (act)
+        for (int r = 0; r < k; ++r) Z[r * k + b] = xs[r * 64 + t];
 }
 
 
@@ -548,7 +586,7 @@ hipError_t launch_tips(const TipsArgs<T> &a, hipStream_t s)
         hipLaunchKernelGGL(kern, dim3(a.pt.p - 1), dim3(256), lds, s, a);
     } else {
         const int ncg = (a.pt.k + 63) / 64;
-        const size_t cols = (size_t)a.pt.k * 64 * sizeof(T);    // <= 130560 B at K = 255
+        const size_t cols = (size_t)a.pt.k * 66 * sizeof(T);    // columns + 2 factor rows: <= 134640 B
         if (cols > kMaxLds) return hipErrorInvalidValue;
         for (const void *f : {(const void *)k_tips_global_vw<T>, (const void *)k_tips_global_rinv<T>}) {
             hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)cols);
