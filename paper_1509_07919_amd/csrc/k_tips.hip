@@ -61,8 +61,8 @@ __device__ __forceinline__ T rowdot(const T *M, const T *X, int k, int r, int b,
 //                       right-hand-side column, the wave's 64 columns held in
 //                       LDS and the factor corner read from global memory
 //                       (the same address in every lane);
-//   k_tips_global_rbar  grid (P-1, kTipsRowSplit): Rbar = I - W V, each
-//                       workgroup a range of rows, into the Rbar and Rlu slots;
+//   k_tips_global_rbar  grid (P-1, tiles^2): Rbar = I - W V in 64 x 64
+//                       tiles staged through LDS, into the Rbar and Rlu slots;
 //   k_tips_global_lu    grid (P-1): the pivoted LU of Rbar, in LDS when K^2
 //                       elements fit (FP32 K <= 202, FP64 K <= 143), stored
 //                       in the Rlu slot;
@@ -70,8 +70,6 @@ __device__ __forceinline__ T rowdot(const T *M, const T *X, int k, int r, int b,
 //                       from the pivoted LU, held in LDS like V and W.
 // Each column's substitution is a chain over K rows; with the column and the
 // factor row in LDS a row waits on LDS only, not on a global round trip.
-constexpr int kTipsRowSplit = 4;
-
 template <typename T>
 __global__ __launch_bounds__(256) void k_tips_global_stage(TipsArgs<T> a)
 {
@@ -202,22 +200,63 @@ __global__ __launch_bounds__(64) void k_tips_global_vw(TipsArgs<T> a)
         for (int c = 0; c < k; ++c) X[c * k + b] = xs[c * 64 + t];
 }
 
+// Rbar = I - W V as 64 x 64 output tiles (grid (P-1, tiles^2)): the tile's
+// rows of W and columns of V pass through LDS 16 at a time, and each thread
+// accumulates a 4 x 4 block of outputs (rows ty + 16 u, columns tx + 16 v)
 template <typename T>
 __global__ __launch_bounds__(256) void k_tips_global_rbar(TipsArgs<T> a)
 {
+    constexpr int TB = 64, KC = 16;
+    __shared__ T ysh[TB][KC + 1];               // W[r0 + row][c0 + col]
+    __shared__ T xsh[KC][TB + 1];               // V[c0 + row][b0 + col]
     const int i = blockIdx.x;
     const int k = a.pt.k;
     const int64_t kk = (int64_t)k * k;
     const T *X = a.V + i * kk, *Y = a.W + i * kk;
     T *R = a.Rbar + i * kk, *F = a.Rlu + i * kk;
-    const int rows = (k + kTipsRowSplit - 1) / kTipsRowSplit;
-    const int r0 = (int)blockIdx.y * rows, r1 = min(k, r0 + rows);
-    const int b = threadIdx.x;
-    if (b < k) {
-        for (int r = r0; r < r1; ++r) {
-            const T s = ((r == b) ? T(1) : T(0)) - rowdot(Y, X, k, r, b, 0, k);
-            R[r * k + b] = s;
-            F[r * k + b] = s;
+    const int nt = (k + TB - 1) / TB;
+    const int r0 = ((int)blockIdx.y / nt) * TB, b0 = ((int)blockIdx.y % nt) * TB;
+    const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+    T acc[4][4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[u][v] = T(0);
+    for (int c0 = 0; c0 < k; c0 += KC) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int e = tid + 256 * q;        // 1024 entries of each tile
+            const int yr = e >> 4, yc = e & 15;
+            ysh[yr][yc] = (r0 + yr < k && c0 + yc < k) ? Y[(int64_t)(r0 + yr) * k + c0 + yc] : T(0);
+            const int xr = e >> 6, xc = e & 63;
+            xsh[xr][xc] = (c0 + xr < k && b0 + xc < k) ? X[(int64_t)(c0 + xr) * k + b0 + xc] : T(0);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int c = 0; c < KC; ++c) {
+            T yv[4], xv[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) yv[u] = ysh[ty + 16 * u][c];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) xv[v] = xsh[c][tx + 16 * v];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) acc[u][v] = fma(yv[u], xv[v], acc[u][v]);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int r = r0 + ty + 16 * u;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int b = b0 + tx + 16 * v;
+            if (r < k && b < k) {
+                const T s = ((r == b) ? T(1) : T(0)) - acc[u][v];
+                R[(int64_t)r * k + b] = s;
+                F[(int64_t)r * k + b] = s;
+            }
         }
     }
 }
@@ -594,8 +633,8 @@ hipError_t launch_tips(const TipsArgs<T> &a, hipStream_t s)
         }
         hipLaunchKernelGGL(k_tips_global_stage<T>, dim3(a.pt.p - 1, 2), dim3(256), 0, s, a);
         hipLaunchKernelGGL(k_tips_global_vw<T>, dim3(a.pt.p - 1, 2 * ncg), dim3(64), cols, s, a);
-        hipLaunchKernelGGL(k_tips_global_rbar<T>, dim3(a.pt.p - 1, kTipsRowSplit), dim3(256), 0,
-                           s, a);
+        const int nt = (a.pt.k + 63) / 64;
+        hipLaunchKernelGGL(k_tips_global_rbar<T>, dim3(a.pt.p - 1, nt * nt), dim3(256), 0, s, a);
         const size_t rb = kk * sizeof(T);
         if (rb + 64 <= kMaxLds) {               // + pr_sh, zero_sh
             hipError_t e = hipFuncSetAttribute((const void *)k_tips_global_lu<T, true>,
