@@ -312,10 +312,12 @@ __global__ __launch_bounds__(256) void k_tips_global_lu(TipsArgs<T> a)
         block_sync();
         const T d = F[j * k + j];
         const T dinv = d != T(0) ? T(1) / d : zero_sh;
-        const int m = k - 1 - j;                               // trailing size
-        for (int e = tid; e < m * m; e += 256) {
-            const int r = j + 1 + e / m, c = j + 1 + e % m;
-            F[r * k + c] = fma(-F[r * k + j] * dinv, F[j * k + c], F[r * k + c]);
+        // trailing update: thread (tid / 16, tid % 16) takes every 16th row
+        // and column, so no index needs a division
+        for (int r = j + 1 + (tid >> 4); r < k; r += 16) {
+            const T l = F[r * k + j] * dinv;
+            for (int c = j + 1 + (tid & 15); c < k; c += 16)
+                F[r * k + c] = fma(-l, F[j * k + c], F[r * k + c]);
         }
         block_sync();
         for (int r = j + 1 + tid; r < k; r += 256) F[r * k + j] *= dinv;
