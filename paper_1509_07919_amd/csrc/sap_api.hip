@@ -40,6 +40,14 @@ struct Layout {
 
 bool coupled_active(const sap_options &o) { return o.mode == SAP_COUPLED && o.p > 1 && o.k > 0; }
 
+// Workgroups per block of k_block_norm, which covers 64 columns each: the
+// grid and the partial-norm array are both sized by this one count.
+int norm_chunks(const sap_options &o)
+{
+    const int64_t maxnb = o.n / o.p + (o.n % o.p ? 1 : 0);
+    return (int)((maxnb + 63) / 64);
+}
+
 // Chains per block for the triangular sweeps (chunked form, sap_internal.h).
 // Automatic choice: about as many sweep workgroups as the chip keeps resident
 // (two per CU on 256 CUs: one wave per SIMD each, two waves per SIMD), with
@@ -98,8 +106,7 @@ Layout layout_for(const sap_options &o)
     const int64_t n = o.n;
     const int k = o.k, p = o.p;
     const size_t sf = o.factor_prec == SAP_PREC_FP32 ? 4 : 8;
-    const int64_t maxnb = n / p + (n % p ? 1 : 0);
-    const int nchunk = (int)((maxnb + 63) / 64);      // 64-column chunks (k_block_norm)
+    const int nchunk = norm_chunks(o);
     const bool cpl = coupled_active(o);
     const size_t kk = (size_t)k * k;
     size_t off = 0;
@@ -719,7 +726,7 @@ int sap_create(const sap_options *opt, void *workspace, size_t ws_bytes, sap_han
     h->pt.p = p;
     h->pt.maxnb = n / p + (n % p ? 1 : 0);
     h->pt.starts = h->ptr<int64_t>(L.starts);
-    h->nchunk = (int)((h->pt.maxnb + 255) / 256);
+    h->nchunk = norm_chunks(*opt);
     h->ck = chunking_for(*opt);
     auto cleanup = [&](int code, const std::string &m) {
         if (h->h_starts) (void)hipHostFree(h->h_starts);

@@ -289,6 +289,38 @@ def test_pivot_boosting():
     s2.close()
 
 
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_boost_threshold_covers_whole_block(prec):
+    """tau_i = eps * max|A_i| over every entry of the block (Sec. 2.2 pivot
+    boosting).  Block 2 gets its largest entry far past its first quarter and
+    an isolated row/column whose pivot lies between eps * max(first quarter)
+    and eps * max|A_i|: it is boosted only when the norm covers the whole
+    block, and the boosted-pivot count must equal the oracle's."""
+    n, k, p = 6000, 4, 6                       # blocks of 1000 rows
+    case("boost-norm", n, k, p, prec)
+    pb = sapgen.make_problem(n, k, seed=40)
+    band = pb.band.copy()
+    eps = 2.0 ** -23 if prec == "fp32" else 2.0 ** -52
+    s0 = 2000
+    big = 1e6 if prec == "fp32" else 1e12
+    band[k * n + s0 + 900] = big               # a_{rr} at row 900 of block 2
+    r = s0 + 300                               # isolated row and column
+    for q in range(2 * k + 1):
+        if q != k:
+            band[q * n + r] = 0.0              # column r off the diagonal
+            c = r - (q - k)                    # row r: entry (r, c) at q*n + c
+            band[q * n + c] = 0.0
+    band[k * n + r] = 1e3 * eps * 8.0          # >> eps * |first-quarter entries|
+    assert 1e3 * eps * 8.0 < eps * big
+    M = oracle.SapPrecond(band, n, k, p, True, boost_eps=eps)
+    assert M.n_boosted >= 2                    # the LU and the UL pivot of row r
+    s = solver(n, k, p, prec=prec)
+    s.factor(dev(band))
+    rc, nbst = s.status()
+    assert rc == 0 and nbst == M.n_boosted
+    s.close()
+
+
 def test_band_grad_parity():
     n, k, p = 3000, 5, 4
     case("band_grad", n, k, p)
