@@ -363,7 +363,7 @@ class Breakdown(RuntimeError):
 
 
 def bicgstab_l(matvec, precond, b, tol: float = 1e-10, maxit: int = 500,
-               ell: int = 2, reliable: float = 0.0) -> KrylovResult:
+               ell: int = 2, reliable: float = 0.0, observe=None) -> KrylovResult:
     """Left-preconditioned BiCGStab(l) (Sleijpen & Fokkema 1993), x0 = 0.
 
     Solves M^{-1} A x = M^{-1} b.  Exit points follow every BiCG step j (after
@@ -382,6 +382,12 @@ def bicgstab_l(matvec, precond, b, tol: float = 1e-10, maxit: int = 500,
     (re)start.  With a preconditioner applied in lower precision the recursive
     residual stops tracking the true one near that precision; restarting there
     lets the next steps reduce the true residual again.
+
+    observe (test hook, read-only): called at every exit point, before its
+    test, as observe(kind, napply, x, r, u) with kind "bicg" after a BiCG step
+    and "mr" after the minimal-residual part; r and u are the current lists
+    r_0..r_l and u_0..u_l (after the MR part, r_1..r_l are the vectors
+    orthogonalized by modified Gram-Schmidt).  Copies are passed.
     """
     b = np.asarray(b, dtype=np.float64)
     n = b.size
@@ -449,6 +455,9 @@ def bicgstab_l(matvec, precond, b, tol: float = 1e-10, maxit: int = 500,
             for i in range(j + 1):
                 r[i] = r[i] - st["alpha"] * u[i + 1]
             x = x + st["alpha"] * u[0]
+            if observe is not None:
+                observe("bicg", napply, x.copy(), [None if v is None else v.copy() for v in r],
+                        [None if v is None else v.copy() for v in u])
             if check():
                 return KrylovResult(x, napply / (2 * ell), True, rel_true,
                                     float(np.linalg.norm(st["r"][0])) / pnorm0,
@@ -486,6 +495,8 @@ def bicgstab_l(matvec, precond, b, tol: float = 1e-10, maxit: int = 500,
             u[0] = u[0] - g[j] * u[j]
             x = x + gpp[j] * r[j]
             r[0] = r[0] - gp[j] * r[j]
+        if observe is not None:
+            observe("mr", napply, x.copy(), [v.copy() for v in r], [v.copy() for v in u])
         if check():
             return KrylovResult(x, napply / (2 * ell), True, rel_true,
                                 float(np.linalg.norm(st["r"][0])) / pnorm0,

@@ -387,6 +387,68 @@ def test_bicgstab2_minimal_polynomial_degree_two():
     np.testing.assert_allclose(res.x, np.linalg.solve(a, b), atol=1e-12)
 
 
+def _similar_to_diag(n, eigs, seed):
+    """A = S diag(lam) S^{-1}, nonsymmetric, whose minimal polynomial has
+    degree len(set(eigs)) (each eigenvalue repeated)."""
+    rng = np.random.default_rng(seed)
+    lam = np.array([eigs[i % len(eigs)] for i in range(n)], dtype=np.float64)
+    S = np.eye(n) + 0.3 * rng.standard_normal((n, n)) / np.sqrt(n)
+    return S @ np.diag(lam) @ np.linalg.inv(S), rng.standard_normal(n)
+
+
+@pytest.mark.parametrize("eigs,exit_iters", [((1.0, 2.0, 4.0), 1.25),
+                                             ((1.0, 2.0, 3.0, 5.0), 1.75)])
+def test_bicgstab2_finite_termination_through_the_mr_part(eigs, exit_iters):
+    """BiCGStab(2) multiplies the BiCG residual polynomial by its MR
+    polynomial, so once the BiCG steps reach the degree d of the minimal
+    polynomial the residual is zero.  For d = 3 that is the first BiCG step
+    of the second iteration (1.25 iterations), for d = 4 the second (1.75):
+    both come after a minimal-residual part, whose updates of u_0 (gamma),
+    x (gamma_1, gamma''_1) and r_0 (gamma') must all be right for the third
+    and fourth BiCG steps to stay exact (Sleijpen-Fokkema 1993)."""
+    n = 40
+    a, b = _similar_to_diag(n, eigs, seed=11)
+    res = bicgstab_l(lambda v: a @ v, lambda v: v, b, tol=1e-11, ell=2)
+    assert res.converged and res.restarts == 0 and res.iters == exit_iters
+    np.testing.assert_allclose(res.x, np.linalg.solve(a, b), rtol=0,
+                               atol=1e-10 * np.abs(np.linalg.solve(a, b)).max())
+
+
+@pytest.mark.parametrize("precond", [False, True])
+def test_bicgstab2_recursion_invariant_and_mr_orthogonality(precond):
+    """Two properties of every BiCGStab(2) iterate, checked on a small
+    nonsymmetric system (with and without a left preconditioner):
+    * at every exit point the recursive residual equals the true one,
+      r_0 = M^{-1}(b - A x) (the x updates by alpha, gamma_1, gamma''_1 are
+      consistent with the r_0 updates);
+    * after each minimal-residual part, r_0 is orthogonal to the
+      Gram-Schmidt-orthogonalized r_1 and r_2: the MR coefficients gamma'
+      minimize ||r_0 - gamma'_1 r_1 - gamma'_2 r_2||."""
+    n = 60
+    rng = np.random.default_rng(3)
+    a = np.eye(n) * 3 + rng.standard_normal((n, n)) / np.sqrt(n)
+    a[0, :] *= 0.2                                   # spread the spectrum
+    b = rng.standard_normal(n)
+    minv = (np.linalg.inv(np.eye(n) + 0.2 * rng.standard_normal((n, n)) / np.sqrt(n))
+            if precond else np.eye(n))
+    seen = {"bicg": 0, "mr": 0}
+
+    def observe(kind, napply, x, r, u):
+        seen[kind] += 1
+        t = minv @ (b - a @ x)
+        assert np.linalg.norm(r[0] - t) <= 1e-12 * np.linalg.norm(minv @ b)
+        if kind == "mr":
+            for j in (1, 2):
+                c = abs(r[0] @ r[j]) / (np.linalg.norm(r[0]) * np.linalg.norm(r[j]))
+                assert c <= 1e-12
+            c12 = abs(r[1] @ r[2]) / (np.linalg.norm(r[1]) * np.linalg.norm(r[2]))
+            assert c12 <= 1e-12
+
+    res = bicgstab_l(lambda v: a @ v, lambda v: minv @ v, b, tol=1e-300, maxit=4,
+                     ell=2, observe=observe)
+    assert seen["mr"] == 4 and seen["bicg"] == 8 and res.restarts == 0
+
+
 def test_bicgstab2_scalar_operator_first_exit():
     n = 30
     b = np.arange(1.0, n + 1)
