@@ -129,13 +129,16 @@ EXPERIMENTS = {
 }
 
 
-def run_experiment(args):
+def run_experiment(args, configs=None):
+    """Runs the configurations of one study (or `configs`), prints one JSON
+    line per configuration and mode, and returns those records."""
     import numpy as np
     import torch
 
     import sapgen
     dev = torch.device("cuda:0")
-    for c in EXPERIMENTS[args.experiment]:
+    lines = []
+    for c in (EXPERIMENTS[args.experiment] if configs is None else configs):
         pb = sapgen.make_problem(c["n"], c["k"], d=c["d"], seed=args.seed)
         a = torch.from_numpy(pb.band).to(dev)
         b = torch.from_numpy(pb.b).to(dev)
@@ -157,7 +160,66 @@ def run_experiment(args):
             except Exception as e:      # e.g. not converged within maxit, or K unsupported
                 line["error"] = str(e)[:200]
             print(json.dumps(line), flush=True)
+            lines.append(line)
         del a, b
+    return lines
+
+
+def run_batch(args, prec, pb, a, m):
+    """Factor once and solve m right-hand sides with sap_solve_batch; the
+    same m columns one sap_solve at a time beside it (same factorization)."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import sapgen
+    from paper_1509_07919_amd import SapSolver
+
+    cfg = args.cfg
+    n, k = cfg["n"], cfg["k"]
+    xs = np.stack([sapgen.splitmix64_uniform(300 + c, sapgen.STREAM_XTRUE, np.arange(n))
+                   for c in range(m)])
+    B = torch.from_numpy(np.stack([oracle.bandmv(pb.band, n, k, xs[c]) for c in range(m)])).to(a.device)
+    s = SapSolver(n, k, cfg["p"], mode=cfg["mode"], factor_prec=prec, nrhs=m)
+    X = torch.empty_like(B)
+    s.factor(a)
+    for _ in range(args.warmup):
+        s.solve_batch(B, X, tol=cfg["tol"], maxit=args.maxit)
+        for c in range(m):
+            s.solve(B[c], X[c], tol=cfg["tol"], maxit=args.maxit)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        _, sts = s.solve_batch(B, X, tol=cfg["tol"], maxit=args.maxit)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    err = float(max(np.abs(X[c].cpu().numpy() - xs[c]).max() for c in range(m)))
+    for _ in range(args.steps):
+        for c in range(m):
+            s.solve(B[c], X[c], tol=cfg["tol"], maxit=args.maxit)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    s.close()
+    batch_ms = (t1 - t0) * 1e3 / args.steps
+    single_ms = (t2 - t1) * 1e3 / args.steps
+    return {"m": m, "factor_prec": prec, "batch_solve_ms": round(batch_ms, 4),
+            "batch_ms_per_rhs": round(batch_ms / m, 4),
+            "single_solves_ms": round(single_ms, 4),
+            "speedup_vs_single": round(single_ms / batch_ms, 3),
+            "iters": [st.iters for st in sts], "converged": all(st.converged for st in sts),
+            "max_abs_err_vs_xtrue": err}
+
+
+def cpu_model() -> str:
+    """Model name of the host CPU (from /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def cpu_baseline(cfg, pb, reps):
@@ -191,6 +253,9 @@ def main():
                     help="also race FP32 against FP64 factors on the same N, K, P at these "
                          "diagonal dominances (comma list; 0 or empty: skip)")
     ap.add_argument("--race-steps", type=int, default=5)
+    ap.add_argument("--batch-rhs", type=int, default=8,
+                    help="also time sap_solve_batch with this many right-hand sides on the "
+                         "same factorization (0: skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 1 GiB device copy (counter calibration)")
     ap.add_argument("--experiment", choices=sorted(EXPERIMENTS),
@@ -330,6 +395,8 @@ def main():
                 "steps": args.race_steps, "fp64": rw["fp64"], "fp32": rw["fp32"],
                 "fp32_speedup": round(rw["fp64"]["ms"] / rw["fp32"]["ms"], 3)})
             del aw, bw
+    if args.batch_rhs > 0:
+        out["multi_rhs"] = [run_batch(args, p_, pb, a, args.batch_rhs) for p_ in runs]
     if args.copy_calibration:
         src_t = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
         dst_t = torch.empty_like(src_t)
@@ -345,7 +412,7 @@ def main():
                       "BiCGStab(2) to %g), 1 thread" % (args.cpu_reps,
                                                         "C" if coupled else "D",
                                                         cfg["p"], cfg["tol"]),
-            "host_cpus": os.cpu_count()}
+            "host_cpus": os.cpu_count(), "cpu_model": cpu_model()}
         for p_ in runs:
             out["runs"][p_]["rel_err_vs_oracle"] = float(
                 np.linalg.norm(runs[p_]["x"] - xo) / np.linalg.norm(xo))

@@ -67,7 +67,7 @@ extern "C" {
 
 typedef struct sap_options {
     int64_t n;            /* matrix order N >= 1                            */
-    int32_t k;            /* half-bandwidth K, 0 <= K < N, K <= 255 (K <= 160 with FP64 factors) */
+    int32_t k;            /* half-bandwidth K, 0 <= K < N, K <= 255         */
     int32_t p;            /* partitions P, 1 <= P <= N (SaP-C: N/P >= 2K)   */
     int32_t mode;         /* SAP_DECOUPLED or SAP_COUPLED                   */
     int32_t factor_prec;  /* SAP_PREC_FP64 or SAP_PREC_FP32                 */
@@ -80,6 +80,9 @@ typedef struct sap_options {
                           /*  0 -> chosen by the library, 1 -> one chain    */
                           /*  per block, >= 2 -> at most this many (each    */
                           /*  chunk then holds >= 64 rows); must be >= 0    */
+    int32_t nrhs;         /* right-hand sides sap_solve_batch may take at   */
+                          /*  once, 0..64 (0 -> 1); the workspace grows     */
+                          /*  with it                                       */
 } sap_options;
 
 typedef struct sap_stats {
@@ -138,6 +141,35 @@ int sap_factor(sap_handle h, const double *a_band, void *stream);
 int sap_solve(sap_handle h, const double *b, double *x, double tol,
               int32_t maxit, void *stream, sap_stats *st);
 
+/* Solve A X = B for m right-hand sides at once (Sec. 4.1.1 discusses the
+ * factorization cost that several right-hand sides share), 1 <= m <= nrhs
+ * of the handle.  B and X are N x m, column-major (column c at + c*N), and
+ * must not overlap.  One factorization serves all columns: the banded SpMV
+ * reads A once per 4 columns, and for K <= 56 the triangular sweeps read
+ * each factor row once per 4 columns; wider bands sweep the columns one
+ * after another.  Every column runs BiCGStab(2) as sap_solve does, with its
+ * own scalars, in lockstep with the others: a converged column is frozen,
+ * and when a candidate exit of some column fails its true-residual test,
+ * all active columns restart from their true residuals (so iteration counts
+ * can differ from single solves; each converged column meets tol).  st
+ * (host, nullable) receives m statistics records.  Returns SAP_OK when
+ * every column converged, else as sap_solve. */
+int sap_solve_batch(sap_handle h, const double *B, double *X, int32_t m,
+                    double tol, int32_t maxit, void *stream, sap_stats *st);
+
+/* Solve A x = b for symmetric positive definite A with the preconditioned
+ * conjugate gradient method (the paper's outer loop when A is SPD,
+ * Sec. 2.1.1; Saad, Iterative Methods for Sparse Linear Systems, Alg. 9.1),
+ * x0 = 0, preconditioner from the last sap_factor (SaP-D keeps M symmetric
+ * up to rounding; SaP-C's truncated M is not symmetric, and CG then has no
+ * convergence guarantee).  The residual b - A x is updated in FP64; when its
+ * norm reaches tol ||b|| the true residual is tested, and CG restarts from
+ * it if the test fails.  st->iters counts CG steps (products A p), n_apply
+ * preconditioner applications.  p^T A p <= 0 returns SAP_ERR_BREAKDOWN (A
+ * not positive definite).  Otherwise as sap_solve. */
+int sap_solve_cg(sap_handle h, const double *b, double *x, double tol,
+                 int32_t maxit, void *stream, sap_stats *st);
+
 /* Adjoint solve A^T lambda = g with the same Krylov method, the transposed
  * banded SpMV and the exact transpose M^{-T} of the preconditioner built by
  * sap_factor (its factors and tips, no refactorization).  Needs
@@ -172,6 +204,17 @@ int sap_precond_apply(sap_handle h, const double *r, double *z,
  * W_{i+1}^(t) and Rbar_i.  Any pointer may be NULL.  Synchronises. */
 int sap_get_tips(sap_handle h, int32_t i, double *v, double *w, double *rbar,
                  void *stream);
+
+/* Copy rows j0 .. j0+count-1 of one factor coefficient array to the host,
+ * widened to double, K+1 entries per row (row-major), for checking the
+ * block LU of Sec. 3.1 directly.  which = 0: Lc, row j = [1, l(j+1,j) ..
+ * l(j+K,j)] (column j of L); 1: Uc, row j = [1/u(j,j), u(j-1,j) ..
+ * u(j-K,j)] (column j of U); 2: Lr, row j = [1, l(j,j-1) .. l(j,j-K)];
+ * 3: Ur, row j = [1/u(j,j), u(j,j+1) .. u(j,j+K)] (2 and 3 need
+ * adjoint = 1).  Entries that would leave the diagonal block are 0.  Needs
+ * a completed sap_factor; synchronises. */
+int sap_get_factor_rows(sap_handle h, int32_t which, int64_t j0, int64_t count,
+                        double *out /* host */, void *stream);
 
 /* Per-kernel device timing, for benchmarking.  sap_profile(h, 1) resets the
  * counters and starts bracketing every kernel launch of the handle with a

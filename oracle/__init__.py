@@ -345,6 +345,94 @@ class SapPrecond:
         return self.dinv(np.asarray(s, dtype=np.float64) + gbar, trans=True)
 
 
+# ------------------------------------------------- rounding-error model (FP32)
+
+def dinv_error_bound(M: "SapPrecond", r, u: float = 2.0 ** -24, blocks=None) -> np.ndarray:
+    """First-order componentwise bound on |g_hat - g| for g = D^{-1} r when
+    the block factorizations and the two triangular sweeps run in a format
+    with unit roundoff u (FP32: 2^-24) and A and r are rounded to it.
+
+    Standard backward-error results (Higham, Accuracy and Stability of
+    Numerical Algorithms, 2nd ed., Thm 8.5 for triangular solves, Thm 9.3 and
+    9.4 for LU without pivoting), with the inner-product length reduced to
+    the K+1 terms a band row or column has: the computed g_hat solves
+    (A_i + E_i) g_hat = r_i + dr_i with |dr_i| <= u|r_i| and
+    |E_i| <= u|A_i| + gamma_m |L_i||U_i|, gamma_m = m u / (1 - m u),
+    m = 3K + 8 (3(K+1) for the factorization and the two sweeps, plus the
+    rounding of 1/u_jj and of the product by it, which the sweeps use).  To
+    first order g_hat - g = A_i^{-1}(dr_i - E_i g), hence the bound
+    |A_i^{-1}| (u|r_i| + (u|A_i| + gamma_m |L_i||U_i|) |g_i|), evaluated here
+    with the FP64 factors and dense block inverses (small blocks only).  The
+    order in which the sums are taken does not enter, so the bound covers
+    any evaluation order of the same operations.  ``blocks`` limits the
+    evaluation to those block indices (the other entries are NaN)."""
+    k = M.k
+    m = 3 * k + 8
+    gam = m * u / (1.0 - m * u)
+    r = np.asarray(r, dtype=np.float64)
+    g = M.dinv(r)
+    out = np.full(M.n, np.nan)
+    w = 2 * k + 1
+    for i in (range(M.p) if blocks is None else blocks):
+        nb, s0 = int(M.sizes[i]), int(M.starts[i])
+        f = M.lu[i].reshape(nb, w)
+        L = np.eye(nb)
+        U = np.zeros((nb, nb))
+        A = np.zeros((nb, nb))
+        b2 = M.band.reshape(2 * k + 1, M.n)
+        for rr in range(nb):
+            lo, hi = max(0, rr - k), min(nb, rr + k + 1)
+            cs = np.arange(lo, hi)
+            v = f[rr, cs - rr + k]
+            L[rr, lo:rr] = v[:rr - lo]
+            U[rr, rr:hi] = v[rr - lo:]
+            A[rr, lo:hi] = b2[k + rr - cs, s0 + cs]
+        gi = np.abs(g[s0:s0 + nb])
+        v = u * np.abs(r[s0:s0 + nb]) + u * (np.abs(A) @ gi) + gam * (np.abs(L) @ (np.abs(U) @ gi))
+        out[s0:s0 + nb] = np.abs(np.linalg.inv(A)) @ v
+    return out
+
+
+def dinv_error_sigma(M: "SapPrecond", r, u: float = 2.0 ** -24, blocks=None) -> np.ndarray:
+    """Standard deviation of g_hat - g per component under the statistical
+    rounding model (each rounding a relative error of variance u^2/3,
+    independent of the others; Higham, op. cit., Sec. 2.8), applied to the
+    same first-order expression as ``dinv_error_bound``:
+    g_hat - g = A_i^{-1}(dr_i - E_i g) with E_i = dA_0 + dA_1 and the
+    entry (j, c) of dA_1 a sum over t of l_jt u_tc times up to m = 3K + 8
+    roundings.  Summing variances instead of magnitudes gives
+      var = (u^2/3) (A_i^{-1})^2 [r^2 + (A_i)^2 g^2 + m (L_i)^2 (U_i)^2 g^2]
+    with squares taken entrywise.  Worst-case signs (the bound above) grow
+    with the factor growth of the block and become vacuous for weakly
+    dominant blocks; this model stays within an order of magnitude of what
+    an FP32 evaluation actually shows.  ``blocks`` as for
+    ``dinv_error_bound``."""
+    k = M.k
+    m = 3 * k + 8
+    r = np.asarray(r, dtype=np.float64)
+    g = M.dinv(r)
+    out = np.full(M.n, np.nan)
+    w = 2 * k + 1
+    for i in (range(M.p) if blocks is None else blocks):
+        nb, s0 = int(M.sizes[i]), int(M.starts[i])
+        f = M.lu[i].reshape(nb, w)
+        L = np.eye(nb)
+        U = np.zeros((nb, nb))
+        A = np.zeros((nb, nb))
+        b2 = M.band.reshape(2 * k + 1, M.n)
+        for rr in range(nb):
+            lo, hi = max(0, rr - k), min(nb, rr + k + 1)
+            cs = np.arange(lo, hi)
+            v = f[rr, cs - rr + k]
+            L[rr, lo:rr] = v[:rr - lo]
+            U[rr, rr:hi] = v[rr - lo:]
+            A[rr, lo:hi] = b2[k + rr - cs, s0 + cs]
+        g2 = g[s0:s0 + nb] ** 2
+        v = r[s0:s0 + nb] ** 2 + (A ** 2) @ g2 + m * ((L ** 2) @ ((U ** 2) @ g2))
+        out[s0:s0 + nb] = np.sqrt((u * u / 3.0) * ((np.linalg.inv(A) ** 2) @ v))
+    return out
+
+
 # --------------------------------------------------------------- BiCGStab(l)
 
 @dataclass
@@ -505,6 +593,74 @@ def bicgstab_l(matvec, precond, b, tol: float = 1e-10, maxit: int = 500,
     return KrylovResult(x, napply / (2 * ell), False,
                         float(np.linalg.norm(t)) / bnorm,
                         float(np.linalg.norm(st["r"][0])) / pnorm0, restarts, history)
+
+
+# ------------------------------------------------------ conjugate gradient
+
+def cg(matvec, precond, b, tol: float = 1e-10, maxit: int = 500,
+       observe=None) -> KrylovResult:
+    """Preconditioned conjugate gradient (Saad, Iterative Methods for Sparse
+    Linear Systems, 2nd ed., Alg. 9.1), x0 = 0: the paper's outer loop when A
+    is symmetric positive definite (Sec. 2.1.1).  r is the unpreconditioned
+    residual b - A x, updated recursively; z = M^{-1} r.
+
+    Stopping as in ``bicgstab_l``: when ||r|| <= tol ||b|| the true residual
+    is computed; the solve stops if it meets the tolerance, otherwise CG
+    restarts from the current x with r = b - A x (p = z = M^{-1} r).
+    ``iters`` counts CG steps (products A p).  A step with p^T A p <= 0 (A
+    or the preconditioned operator not positive definite) raises Breakdown.
+    observe (test hook): called after every step as observe(it, x, r)."""
+    b = np.asarray(b, dtype=np.float64)
+    n = b.size
+    bnorm = float(np.linalg.norm(b))
+    x = np.zeros(n)
+    if bnorm == 0.0:
+        return KrylovResult(x, 0.0, True, 0.0, 0.0, 0, [])
+    r = b.copy()
+    z = precond(r)
+    p = z.copy()
+    rho = float(r @ z)
+    restarts, history = 0, []
+    rel_true = 1.0
+    for it in range(1, maxit + 1):
+        q = matvec(p)
+        pq = float(p @ q)
+        if not pq > 0.0:
+            raise Breakdown("p^T A p <= 0")
+        alpha = rho / pq
+        x = x + alpha * p
+        r = r - alpha * q
+        rn = float(np.linalg.norm(r))
+        history.append((it, rn / bnorm))
+        if observe is not None:
+            observe(it, x.copy(), r.copy())
+        if rn <= tol * bnorm:
+            t = b - matvec(x)
+            rel_true = float(np.linalg.norm(t)) / bnorm
+            if rel_true <= tol:
+                return KrylovResult(x, float(it), True, rel_true, rn / bnorm, restarts, history)
+            r = t
+            restarts += 1
+            z = precond(r)
+            p = z.copy()
+            rho = float(r @ z)
+            continue
+        z = precond(r)
+        rho_new = float(r @ z)
+        beta = rho_new / rho
+        rho = rho_new
+        p = z + beta * p
+    t = b - matvec(x)
+    return KrylovResult(x, float(maxit), False, float(np.linalg.norm(t)) / bnorm,
+                        float(np.linalg.norm(r)) / bnorm, restarts, history)
+
+
+def sap_solve_cg(band, n: int, k: int, b, p: int, coupled: bool, tol: float = 1e-10,
+                 maxit: int = 500, boost_eps: float = FP64_EPS):
+    """SaP preconditioner + CG on a symmetric positive definite A."""
+    M = SapPrecond(band, n, k, p, coupled, boost_eps)
+    res = cg(lambda v: bandmv(band, n, k, v), M.apply, b, tol, maxit)
+    return res.x, res, M
 
 
 # ------------------------------------------------------------ full solves

@@ -728,7 +728,7 @@ hipError_t launch_banded_lu<double>(const LuArgs<double> &a, hipStream_t s)
     if (k < 32) return launch_lu_cfg<double, 32, 32, 256>(a, s);
     if (k < 64) return launch_lu_cfg<double, 64, 32, 256>(a, s);
     if (k < 128) return launch_lu_cfg<double, 128, 16, 1024>(a, s);
-    return hipErrorInvalidValue;   // FP64 factors support K <= 160
+    return launch_lu_wide(a, a.wide, s);      // K > 160
 }
 
 template <>

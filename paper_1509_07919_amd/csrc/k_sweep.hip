@@ -56,16 +56,31 @@ constexpr int kSweepWaves = 4;
 // chunk c0 + dir (nlink + 1) (zero past K); STORE also writes every state
 // to a.st.  A non-null top gives chunk c0 the incoming state -top (K
 // entries), which adds the link of chunk c0 itself.
-template <typename T, bool FWD, int NW, bool STORE>
-__device__ void chain_states(const SweepArgs<T> &a, int blk, int nchb, int nlink, T *sh,
-                             const T *top = nullptr)
+//
+// The chain runs in FP64 whatever the factor precision: the transfer
+// matrices are FP64 and each link q(c) + X(c)^T p is formed in FP64.  A
+// transfer matrix and the terms of a link can be much larger than the state
+// they produce (weak dominance makes the homogeneous recurrence grow inside a
+// chunk), and FP32 rounding of those terms would then dominate the sweep's
+// own FP32 error.
+//
+// NR > 1: the states of right-hand sides col0 .. col0+nc-1 are chained at
+// once (multi-RHS sweeps), each transfer matrix read once for all of them;
+// sh[64 j ..] then holds column j's state.  q, st and top are per column
+// (strides p*nch*K, p*nch*K and p*K).
+template <typename T, bool FWD, int NW, bool STORE, int NR = 1>
+__device__ void chain_states(const SweepArgs<T> &a, int blk, int nchb, int nlink, double *sh,
+                             const T *top = nullptr, int col0 = 0, int nc = 1)
 {
     constexpr int IW = 64 / NW;
     const int k = a.pt.k;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int64_t base = (int64_t)blk * a.nch;
-    T *cur = sh;                 // [64] state entering the current chunk
-    T *part = sh + 64;           // [NW][64] partial sums
+    const int64_t qs = (int64_t)a.pt.p * a.nch * k;     // column stride of q and st
+    const int64_t ts = (int64_t)a.pt.p * k;             // column stride of top
+    const T *qc = a.q + col0 * qs;
+    double *cur = sh;            // [NR][64] state entering the current chunk
+    double *part = sh + 64 * NR; // [NW][NR][64] partial sums
     const int c0 = FWD ? 0 : nchb - 1;            // chunk whose q seeds the chain
     const int dir = FWD ? 1 : -1;
     // the state entering chunk c0 + dir is q(c0), or with an incoming state
@@ -73,55 +88,72 @@ __device__ void chain_states(const SweepArgs<T> &a, int blk, int nchb, int nlink
     const int first = top ? c0 : c0 + dir;        // chunk of the first link
     if (top) ++nlink;
     if (tid < 64) {
-        const T v = tid < k ? (top ? -top[tid] : a.q[(base + c0) * k + tid]) : T(0);
-        cur[tid] = v;
-        if (STORE && !top && tid < k) a.st[(base + c0 + dir) * k + tid] = v;
+#pragma unroll
+        for (int j = 0; j < NR; ++j) {
+            double v = 0.0;
+            if (j < nc && tid < k)
+                v = top ? -(double)top[j * ts + tid] : (double)qc[j * qs + (base + c0) * k + tid];
+            cur[j * 64 + tid] = v;
+            if (STORE && !top && j < nc && tid < k)
+                a.st[(col0 + j) * qs + (base + c0 + dir) * k + tid] = v;
+        }
     }
     // the transfer matrices of NG links are loaded at once, so their
     // latencies overlap; the links are then chained one after the other
-    constexpr int NG = sizeof(T) == 8 ? (STORE ? 2 : 3) : 4;
-    auto load_x = [&](int c, T *dst) {
-        const T *x = a.xf + (base + c) * k * k;
+    constexpr int NG = NR > 1 ? 2 : ((sizeof(T) == 8 || NW > 4) ? (STORE ? 2 : 3) : 4);
+    auto load_x = [&](int c, double *dst) {
+        const double *x = a.xf + (base + c) * k * k;
 #pragma unroll
         for (int e = 0; e < IW; ++e) {
             const int i = IW * wave + e;
-            dst[e] = (i < k && lane < k) ? x[i * k + lane] : T(0);
+            dst[e] = (i < k && lane < k) ? x[i * k + lane] : 0.0;
         }
     };
     __syncthreads();
     for (int g = 0; g < nlink; g += NG) {
-        T xg[NG][IW], qg[NG];
+        double xg[NG][IW], qg[NG][NR];
 #pragma unroll
         for (int j = 0; j < NG; ++j) {
             const int c = first + dir * (g + j);
             if (g + j < nlink) {
                 load_x(c, xg[j]);
-                qg[j] = (wave == 0 && lane < k) ? a.q[(base + c) * k + lane] : T(0);
+#pragma unroll
+                for (int r = 0; r < NR; ++r)
+                    qg[j][r] = (wave == 0 && lane < k && r < nc)
+                                   ? (double)qc[r * qs + (base + c) * k + lane] : 0.0;
             }
         }
 #pragma unroll
         for (int j = 0; j < NG; ++j) {
             if (g + j < nlink) {
                 const int c = first + dir * (g + j);         // chunk of this link
-                T s0 = T(0), s1 = T(0);
 #pragma unroll
-                for (int e = 0; e < IW; e += 2) {
-                    s0 = fma(xg[j][e], cur[IW * wave + e], s0);
-                    s1 = fma(xg[j][e + 1], cur[IW * wave + e + 1], s1);
+                for (int r = 0; r < NR; ++r) {
+                    const double *cr = cur + r * 64 + IW * wave;
+                    double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+                    for (int e = 0; e < IW; e += 2) {
+                        s0 = fma(xg[j][e], cr[e], s0);
+                        s1 = fma(xg[j][e + 1], cr[e + 1], s1);
+                    }
+                    part[(wave * NR + r) * 64 + lane] = s0 + s1;
                 }
-                part[wave * 64 + lane] = s0 + s1;
                 __syncthreads();
                 if (wave == 0) {
-                    T ps[NW];
 #pragma unroll
-                    for (int w = 0; w < NW; ++w) ps[w] = part[w * 64 + lane];
+                    for (int r = 0; r < NR; ++r) {
+                        double ps[NW];
 #pragma unroll
-                    for (int h = NW / 2; h >= 1; h /= 2)
+                        for (int w = 0; w < NW; ++w) ps[w] = part[(w * NR + r) * 64 + lane];
 #pragma unroll
-                        for (int w = 0; w < h; ++w) ps[w] += ps[w + h];
-                    const T v = qg[j] + ps[0];
-                    cur[lane] = lane < k ? v : T(0);
-                    if (STORE && lane < k) a.st[(base + c + dir) * k + lane] = v;
+                        for (int h = NW / 2; h >= 1; h /= 2)
+#pragma unroll
+                            for (int w = 0; w < h; ++w) ps[w] += ps[w + h];
+                        const double v = qg[j][r] + ps[0];
+                        cur[r * 64 + lane] = lane < k ? v : 0.0;
+                        if (STORE && lane < k && r < nc)
+                            a.st[(col0 + r) * qs + (base + c + dir) * k + lane] = v;
+                    }
                 }
                 __syncthreads();
             }
@@ -132,7 +164,7 @@ __device__ void chain_states(const SweepArgs<T> &a, int blk, int nchb, int nlink
 // End of a zero-state workgroup: the last of a block's workgroups to arrive
 // (atomic ticket) chains the block's chunk states.
 template <typename T, bool FWD, int NW>
-__device__ void chain_if_last(const SweepArgs<T> &a, int blk, int nchb, T *scratch)
+__device__ void chain_if_last(const SweepArgs<T> &a, int blk, int nchb, double *scratch)
 {
     __shared__ int last_sh;
     __syncthreads();
@@ -156,7 +188,7 @@ template <typename T>
 static size_t sweep_lds_bytes(int cp, int nbuf)
 {
     const size_t b = ((size_t)nbuf * kSweepRows * cp + (size_t)nbuf * kSweepRows) * sizeof(T);
-    const size_t chain = (size_t)64 * (kSweepWaves + 1) * sizeof(T);   // chain_states scratch
+    const size_t chain = (size_t)64 * (kSweepWaves + 1) * sizeof(double);   // chain_states scratch
     return b > chain ? b : chain;
 }
 
@@ -266,7 +298,7 @@ __global__ __launch_bounds__(64 * kSweepWaves, kSweepWaves / 2) void k_sweep(Swe
         // P, hence the XCD when P is a multiple of the XCD count).
         T pf = T(0);
         if (PH == SWEEP_ZERO_STATE && passes && receives) {
-            const int64_t xbytes = (int64_t)k * k * (int64_t)sizeof(T);
+            const int64_t xbytes = (int64_t)k * k * (int64_t)sizeof(double);
             const int64_t off = (int64_t)(lw * 64 + lane) * 128;
             if (off < xbytes)
                 pf = *reinterpret_cast<const T *>(
@@ -305,7 +337,7 @@ __global__ __launch_bounds__(64 * kSweepWaves, kSweepWaves / 2) void k_sweep(Swe
             // a chunk that receives a state starts from acc = -p_in
             const int m = 64 * s + lane;
             acc[s] = (PH == SWEEP_FROM_STATE && receives && m < k)
-                         ? -a.st[((int64_t)blk * a.nch + ch) * k + m] : T(0);
+                         ? (T)(-a.st[((int64_t)blk * a.nch + ch) * k + m]) : T(0);
         }
 
         T dl = T(0), vdl = T(0);                      // step `lane` of the 64-block
@@ -381,7 +413,7 @@ __global__ __launch_bounds__(64 * kSweepWaves, kSweepWaves / 2) void k_sweep(Swe
         }
     }
     if (PH != SWEEP_ZERO_STATE) return;
-    chain_if_last<T, FWD, kSweepWaves>(a, blk, nchb, stage);
+    chain_if_last<T, FWD, kSweepWaves>(a, blk, nchb, reinterpret_cast<double *>(stage));
 }
 
 // ------------------------------------------------ circular form, K <= 56
@@ -405,16 +437,20 @@ constexpr int kCircG = 8;
 template <typename T>
 constexpr int circ_waves() { return sizeof(T) == 8 ? 4 : 8; }   // one compute wave, the rest load
 template <typename T>
-static size_t circ_lds_bytes(int cp)
+static size_t circ_lds_bytes(int cp, int nr)
 {
     constexpr int NS = circ_waves<T>() - 1;           // one staging buffer per loader
-    // [2][S][64] rotated lines, [2][S] v*d, [2][S] d, [NW+1][64] chain
-    // scratch and [NS][S][CP] staged rows
-    return ((size_t)2 * kSweepRows * 64 + 4 * kSweepRows + (size_t)64 * (circ_waves<T>() + 1) +
-            (size_t)NS * kSweepRows * cp) * sizeof(T);
+    // [2][S][64] rotated lines, [NR][2][S] v*d, [2][S] d, [NR][NW+1][64] FP64
+    // chain scratch and [NS][S][CP] staged rows
+    return ((size_t)2 * kSweepRows * 64 + 2 * (size_t)(nr + 1) * kSweepRows +
+            (size_t)NS * kSweepRows * cp) * sizeof(T) +
+           (size_t)64 * nr * (circ_waves<T>() + 1) * sizeof(double);
 }
 
-template <typename T, bool FWD, bool DIAG, int PH>
+// NR > 1: right-hand sides c0 .. c0+NR-1 (c0 = NR * blockIdx.y, those below
+// a.m) in one workgroup: every staged coefficient row serves all of them and
+// the compute wave runs NR independent chains, interleaved step by step.
+template <typename T, bool FWD, bool DIAG, int PH, int NR>
 __global__ __launch_bounds__(64 * circ_waves<T>(), circ_waves<T>() / 2) void k_sweep_circ(SweepArgs<T> a)
 {
     constexpr int S = kSweepRows;
@@ -426,10 +462,13 @@ __global__ __launch_bounds__(64 * circ_waves<T>(), circ_waves<T>() / 2) void k_s
     const int k = a.pt.k;
     const int CP = coef_pitch(k, (int)sizeof(T));
     T *gsh = reinterpret_cast<T *>(smem_raw);         // [2][S][64]
-    T *vst = gsh + 2 * S * 64;                        // [2][S]
-    T *dsh = vst + 2 * S;                             // [2][S]
-    T *csh = dsh + 2 * S;                             // [NW+1][64] chain scratch
-    T *stage = csh + (NW + 1) * 64;                   // [NL][S][CP], 16-byte aligned
+    T *vst = gsh + 2 * S * 64;                        // [NR][2][S]
+    T *dsh = vst + 2 * S * NR;                        // [2][S]
+    double *csh = reinterpret_cast<double *>(dsh + 2 * S);   // [NR][NW+1][64] FP64 chain scratch
+    T *stage = reinterpret_cast<T *>(csh + NR * (NW + 1) * 64);   // [NL][S][CP], 16-byte aligned
+    const int c0 = NR * (int)blockIdx.y;              // first right-hand side
+    const int nc = min(NR, a.m - c0);                 // right-hand sides here
+    const int64_t ldv = a.ldv;
 
     const int blk = PH == SWEEP_WHOLE ? (int)blockIdx.x : (int)(blockIdx.x % a.pt.p);
     const int ch = PH == SWEEP_WHOLE ? 0 : (int)(blockIdx.x / a.pt.p);
@@ -446,19 +485,23 @@ __global__ __launch_bounds__(64 * circ_waves<T>(), circ_waves<T>() / 2) void k_s
     const bool receives = ch < nchb && (FWD ? ch > 0 : ch + 1 < nchb);
     if (PH == SWEEP_FROM_STATE && ch >= nchb) return;
     const int nchunks = (PH == SWEEP_ZERO_STATE && !passes) ? 0 : (int)((nst + S - 1) / S);
-    const T *dtop = (a.dtop && blk > 0) ? a.dtop + (int64_t)blk * k : nullptr;
-    const T *dbot = (a.dbot && blk < a.pt.p - 1) ? a.dbot + (int64_t)blk * k : nullptr;
+    // boundary deltas of right-hand side c0 + j: dtop/dbot + j * dstr
+    const int64_t dstr = (int64_t)a.pt.p * k;
+    const T *dtop = (a.dtop && blk > 0) ? a.dtop + (int64_t)c0 * dstr + (int64_t)blk * k : nullptr;
+    const T *dbot = (a.dbot && blk < a.pt.p - 1) ? a.dbot + (int64_t)c0 * dstr + (int64_t)blk * k : nullptr;
     auto row_of = [&](int64_t t) -> int64_t { return FWD ? r0 + t : r1 - 1 - t; };
     auto ridx = [&](int uc) { return FWD ? uc : S - 1 - uc; };
     auto count = [&](int t) { return (int)min((int64_t)S, nst - (int64_t)t * S); };
     // The state entering this chunk, chained by the whole workgroup from the
     // outgoing states q of the chunks before it in the sweep direction and
     // their transfer matrices (all written by earlier launches), while the
-    // first staging copies are in flight; it lands in csh[0..64).
+    // first staging copies are in flight; it lands in csh[64 j ..] for
+    // right-hand side c0 + j.
     // dtop as the incoming state -dtop of the block's first chunk (forward)
     const T *top = (FWD && a.top_as_state) ? dtop : nullptr;
     auto entering_state = [&]() {
-        chain_states<T, FWD, NW, false>(a, blk, nchb, FWD ? ch - 1 : nchb - 2 - ch, csh, top);
+        chain_states<T, FWD, NW, false, NR>(a, blk, nchb, FWD ? ch - 1 : nchb - 2 - ch, csh, top,
+                                            c0, nc);
     };
 
     if (wave != 0) {
@@ -472,7 +515,7 @@ __global__ __launch_bounds__(64 * circ_waves<T>(), circ_waves<T>() / 2) void k_s
         // chunk t + NL, off that critical path.
         const int lw = __builtin_amdgcn_readfirstlane(wave - 1);
         T *sbuf = stage + (size_t)lw * S * CP;
-        T vin = T(0);
+        T vin[NR];
         auto issue = [&](int t) {
             const int cnt = count(t);
             const int64_t rlo = FWD ? r0 + (int64_t)t * S : r1 - (int64_t)t * S - cnt;
@@ -487,20 +530,26 @@ __global__ __launch_bounds__(64 * circ_waves<T>(), circ_waves<T>() / 2) void k_s
                         (const void *)(src + off),
                         (__attribute__((address_space(3))) void *)(dst + q * 1024), 16, 0, 0);
             }
-            vin = T(0);
+#pragma unroll
+            for (int j = 0; j < NR; ++j) vin[j] = T(0);
             if (lane < cnt) {
                 const int64_t r = row_of((int64_t)t * S + lane);
                 const T *dt = top ? nullptr : dtop;    // top enters as a state
-                if (a.xin) {
-                    double x = a.xin[s0 + r];
-                    if (dt && r < k) x += (double)dt[r];
-                    if (dbot && r >= nb - k) x += (double)dbot[r - (nb - k)];
-                    vin = (T)x;
-                } else {
-                    T x = a.tin[s0 + r];
-                    if (dt && r < k) x += dt[r];
-                    if (dbot && r >= nb - k) x += dbot[r - (nb - k)];
-                    vin = x;
+#pragma unroll
+                for (int j = 0; j < NR; ++j) {
+                    if (j >= nc) break;
+                    const int64_t o = (int64_t)(c0 + j) * ldv + s0 + r;
+                    if (a.xin) {
+                        double x = a.xin[o];
+                        if (dt && r < k) x += (double)dt[j * dstr + r];
+                        if (dbot && r >= nb - k) x += (double)dbot[j * dstr + r - (nb - k)];
+                        vin[j] = (T)x;
+                    } else {
+                        T x = a.tin[o];
+                        if (dt && r < k) x += dt[j * dstr + r];
+                        if (dbot && r >= nb - k) x += dbot[j * dstr + r - (nb - k)];
+                        vin[j] = x;
+                    }
                 }
             }
         };
@@ -521,7 +570,8 @@ __global__ __launch_bounds__(64 * circ_waves<T>(), circ_waves<T>() / 2) void k_s
             if (lane < S) {
                 // steps past the chunk's end get d = 0 and v*d = 0: x = 0
                 const T d = lane < cnt ? (DIAG ? sbuf[ridx(lane) * CP] : T(1)) : T(0);
-                vst[(t & 1) * S + lane] = vin * d;
+#pragma unroll
+                for (int j = 0; j < NR; ++j) vst[(j * 2 + (t & 1)) * S + lane] = vin[j] * d;
                 dsh[(t & 1) * S + lane] = d;
             }
         };
@@ -542,9 +592,16 @@ __global__ __launch_bounds__(64 * circ_waves<T>(), circ_waves<T>() / 2) void k_s
         if (PH == SWEEP_FROM_STATE && receives) entering_state();
         // acc = -(incoming pending sums): the chained state, or top in the
         // first chunk of a block
-        T acc = (PH == SWEEP_FROM_STATE && receives) ? -csh[lane]
-              : (PH == SWEEP_FROM_STATE && top && lane < k) ? top[lane] : T(0);
-        T dl = T(0), vdl = T(0), xo = T(0);
+        T acc[NR], vdl[NR], xo[NR];
+#pragma unroll
+        for (int j = 0; j < NR; ++j) {
+            acc[j] = (PH == SWEEP_FROM_STATE && receives) ? (T)(-csh[j * 64 + lane])
+                   : (PH == SWEEP_FROM_STATE && top && lane < k && j < nc) ? top[j * dstr + lane]
+                                                                           : T(0);
+            vdl[j] = T(0);
+            xo[j] = T(0);
+        }
+        T dl = T(0);
         for (int t = 0; t < nchunks; ++t) {
             __syncthreads();                          // chunk t rotated
             const T *g = gsh + (t & 1) * S * 64 + lane;
@@ -552,7 +609,8 @@ __global__ __launch_bounds__(64 * circ_waves<T>(), circ_waves<T>() / 2) void k_s
             const int cnt = count(t);
             if (lane >= ub && lane < ub + S) {
                 dl = dsh[(t & 1) * S + lane - ub];
-                vdl = vst[(t & 1) * S + lane - ub];
+#pragma unroll
+                for (int j = 0; j < NR; ++j) vdl[j] = vst[(j * 2 + (t & 1)) * S + lane - ub];
             }
             T ca[G], cb[G];
             auto load = [&](int u0, T (&c)[G]) {
@@ -562,15 +620,21 @@ __global__ __launch_bounds__(64 * circ_waves<T>(), circ_waves<T>() / 2) void k_s
             auto run = [&](int u0, const T (&c)[G]) {
 #pragma unroll
                 for (int e = 0; e < G; ++e) {
-                    const T x = fma(acc, dl, vdl);           // x_u in lane u (acc = -pending)
-                    const T xb = lane_bcast(x, ub + u0 + e);
-                    acc = fma(-c[e], xb, acc);
+#pragma unroll
+                    for (int j = 0; j < NR; ++j) {
+                        const T x = fma(acc[j], dl, vdl[j]);     // x_u in lane u (acc = -pending)
+                        const T xb = lane_bcast(x, ub + u0 + e);
+                        acc[j] = fma(-c[e], xb, acc[j]);
+                    }
                 }
                 // the group's lanes take their outputs and free their slots
                 const int d = lane - ub - u0;
                 if ((unsigned)d < (unsigned)G && u0 + d < cnt) {
-                    xo = fma(acc, dl, vdl);
-                    acc = T(0);
+#pragma unroll
+                    for (int j = 0; j < NR; ++j) {
+                        xo[j] = fma(acc[j], dl, vdl[j]);
+                        acc[j] = T(0);
+                    }
                 }
             };
             load(0, ca);
@@ -583,31 +647,48 @@ __global__ __launch_bounds__(64 * circ_waves<T>(), circ_waves<T>() / 2) void k_s
             }
             if (PH != SWEEP_ZERO_STATE && lane >= ub && lane < ub + cnt) {
                 const int64_t r = s0 + row_of((int64_t)t * S + lane - ub);
-                if (a.dout) a.dout[r] = (double)xo;
-                else a.tout[r] = xo;
+#pragma unroll
+                for (int j = 0; j < NR; ++j) {
+                    if (j >= nc) break;
+                    const int64_t o = (int64_t)(c0 + j) * ldv + r;
+                    if (a.dout) a.dout[o] = (double)xo[j];
+                    else a.tout[o] = xo[j];
+                }
             }
         }
         if (PH == SWEEP_ZERO_STATE && nchunks > 0) {
             // outgoing state: the pending sums of the K steps after the chunk,
             // step nst + m in lane (nst + m) mod 64
             const int m = (lane - (int)(nst & 63)) & 63;
-            if (m < k) a.q[((int64_t)blk * a.nch + ch) * k + m] = -acc;
+            const int64_t qs = (int64_t)a.pt.p * a.nch * k;
+            if (m < k)
+#pragma unroll
+                for (int j = 0; j < NR; ++j)
+                    if (j < nc) a.q[(c0 + j) * qs + ((int64_t)blk * a.nch + ch) * k + m] = -acc[j];
         }
     }
+}
+
+template <typename T, bool FWD, bool DIAG, int PH, int NR>
+static hipError_t launch_circ_nr(const SweepArgs<T> &a, hipStream_t s)
+{
+    const unsigned grid = PH == SWEEP_WHOLE ? a.pt.p : a.pt.p * a.nch;
+    const size_t lds = circ_lds_bytes<T>(coef_pitch(a.pt.k, (int)sizeof(T)), NR);
+    if (lds > kMaxLds) return hipErrorInvalidValue;
+    auto kern = k_sweep_circ<T, FWD, DIAG, PH, NR>;
+    hipError_t e = hipFuncSetAttribute((const void *)kern,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kern, dim3(grid, (unsigned)((a.m + NR - 1) / NR)), dim3(64 * circ_waves<T>()),
+                       lds, s, a);
+    return hipGetLastError();
 }
 
 template <typename T, bool FWD, bool DIAG, int PH>
 static hipError_t launch_circ_ph(const SweepArgs<T> &a, hipStream_t s)
 {
-    const unsigned grid = PH == SWEEP_WHOLE ? a.pt.p : a.pt.p * a.nch;
-    const size_t lds = circ_lds_bytes<T>(coef_pitch(a.pt.k, (int)sizeof(T)));
-    if (lds > kMaxLds) return hipErrorInvalidValue;
-    auto kern = k_sweep_circ<T, FWD, DIAG, PH>;
-    hipError_t e = hipFuncSetAttribute((const void *)kern,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * circ_waves<T>()), lds, s, a);
-    return hipGetLastError();
+    if (a.m == 1) return launch_circ_nr<T, FWD, DIAG, PH, 1>(a, s);
+    return launch_circ_nr<T, FWD, DIAG, PH, kMultiRhs>(a, s);
 }
 
 template <typename T, bool FWD, bool DIAG>
@@ -675,10 +756,14 @@ static hipError_t launch_sweep_kr(const SweepArgs<T> &a, hipStream_t s)
 }
 
 template <>
-hipError_t launch_sweep<float>(const SweepArgs<float> &a, hipStream_t s)
+hipError_t launch_sweep<float>(const SweepArgs<float> &a0, hipStream_t s)
 {
+    SweepArgs<float> a = a0;          // one right-hand side unless stated
+    if (a.m < 1) a.m = 1;
+    if (a.ldv == 0) a.ldv = a.pt.n;
     const int k = a.pt.k;
     if (k <= kCircMaxK) return launch_circ<float>(a, s);
+    if (a.m > 1) return hipErrorInvalidValue;     // multi-RHS sweeps need K <= 56
     if (k < 64) return launch_sweep_kr<float, 2>(a, s);
     if (k < 128) return launch_sweep_kr<float, 3>(a, s);
     if (k < 192) return launch_sweep_kr<float, 4>(a, s);
@@ -686,10 +771,14 @@ hipError_t launch_sweep<float>(const SweepArgs<float> &a, hipStream_t s)
 }
 
 template <>
-hipError_t launch_sweep<double>(const SweepArgs<double> &a, hipStream_t s)
+hipError_t launch_sweep<double>(const SweepArgs<double> &a0, hipStream_t s)
 {
+    SweepArgs<double> a = a0;          // one right-hand side unless stated
+    if (a.m < 1) a.m = 1;
+    if (a.ldv == 0) a.ldv = a.pt.n;
     const int k = a.pt.k;
     if (k <= kCircMaxK) return launch_circ<double>(a, s);
+    if (a.m > 1) return hipErrorInvalidValue;     // multi-RHS sweeps need K <= 56
     if (k < 64) return launch_sweep_kr<double, 2>(a, s);
     if (k < 128) return launch_sweep_kr<double, 3>(a, s);
     if (k < 192) return launch_sweep_kr<double, 4>(a, s);
@@ -706,13 +795,15 @@ hipError_t launch_sweep<double>(const SweepArgs<double> &a, hipStream_t s)
 // p[m-1] = p[m] + F[j][m]*x.  Coefficient rows are loaded one per lane
 // (coefficient m in lane m), eight rows ahead, and broadcast with
 // v_readlane.  The chunk's transfer is the product X_0 X_1 X_2 X_3 (a state
-// s maps to s X), formed through two LDS slots.
+// s maps to s X), formed through two LDS slots.  All of it is FP64 for either
+// factor precision (FP32 coefficients are widened exactly): see chain_states.
 template <typename T, int KM>
 __global__ __launch_bounds__(256) void k_sweep_xfer(XferArgs<T> a)
 {
     static_assert(KM <= 64, "coefficients are spread one per lane");
+    using DT = double;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    T *Xs = reinterpret_cast<T *>(smem_raw);   // [2][K][K]
+    DT *Xs = reinterpret_cast<DT *>(smem_raw);   // [2][K][K]
     const int k = a.pt.k;
     const int CP = coef_pitch(k, (int)sizeof(T));   // row pitch in HBM
     const int kk = k * k;
@@ -730,9 +821,9 @@ __global__ __launch_bounds__(256) void k_sweep_xfer(XferArgs<T> a)
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int64_t t_lo = nst * wave / 4, t_hi = nst * (wave + 1) / 4;
 
-    T p[KM];
+    DT p[KM];
 #pragma unroll
-    for (int m = 0; m < KM; ++m) p[m] = (m == lane) ? T(1) : T(0);
+    for (int m = 0; m < KM; ++m) p[m] = (m == lane) ? 1.0 : 0.0;
     constexpr int D = 8;
     T fr[D], fn[D];
     auto load = [&](int64_t t0, T *dst) {
@@ -749,11 +840,11 @@ __global__ __launch_bounds__(256) void k_sweep_xfer(XferArgs<T> a)
 #pragma unroll
         for (int e = 0; e < D; ++e) {
             if (t0 + e < t_hi) {
-                const T d = diag ? lane_bcast(fr[e], 0) : T(1);
-                const T x = -p[0] * d;
+                const DT d = diag ? (DT)lane_bcast(fr[e], 0) : 1.0;
+                const DT x = -p[0] * d;
 #pragma unroll
-                for (int m = 1; m < KM; ++m) p[m - 1] = fma(lane_bcast(fr[e], m), x, p[m]);
-                p[KM - 1] = T(0);
+                for (int m = 1; m < KM; ++m) p[m - 1] = fma((DT)lane_bcast(fr[e], m), x, p[m]);
+                p[KM - 1] = 0.0;
             }
         }
 #pragma unroll
@@ -764,17 +855,17 @@ __global__ __launch_bounds__(256) void k_sweep_xfer(XferArgs<T> a)
     // LDS and three workgroups fit on a CU beside the tips kernel; each
     // thread forms a 4 x 4 output block (8 LDS reads per 16 FMAs; rows and
     // columns past K are clamped on read and not written)
-    T *A = Xs, *Bm = Xs + kk;
-    auto put = [&](int w, T *dst) {
+    DT *A = Xs, *Bm = Xs + kk;
+    auto put = [&](int w, DT *dst) {
         if (wave == w && lane < k) {
-            T *xw = dst + lane * k;
+            DT *xw = dst + lane * k;
 #pragma unroll
             for (int m = 0; m < KM; ++m)
                 if (m < k) xw[m] = p[m];
         }
     };
     const int nbk = (k + 3) / 4, nblk = nbk * nbk;     // <= 256 for K <= 64
-    auto block_mul = [&](int b, T (&acc)[4][4]) {
+    auto block_mul = [&](int b, DT (&acc)[4][4]) {
         const int i0 = 4 * (b / nbk), m0 = 4 * (b - (b / nbk) * nbk);
         int ir[4], mc[4];
 #pragma unroll
@@ -785,9 +876,9 @@ __global__ __launch_bounds__(256) void k_sweep_xfer(XferArgs<T> a)
 #pragma unroll
         for (int r = 0; r < 4; ++r)
 #pragma unroll
-            for (int q = 0; q < 4; ++q) acc[r][q] = T(0);
+            for (int q = 0; q < 4; ++q) acc[r][q] = 0.0;
         for (int c = 0; c < k; ++c) {
-            T av[4], bv[4];
+            DT av[4], bv[4];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 av[q] = A[ir[q] + c];
@@ -799,23 +890,23 @@ __global__ __launch_bounds__(256) void k_sweep_xfer(XferArgs<T> a)
                 for (int q = 0; q < 4; ++q) acc[r][q] = fma(av[r], bv[q], acc[r][q]);
         }
     };
-    auto block_store = [&](T *D, int b, const T (&acc)[4][4]) {
+    auto block_store = [&](DT *dst, int b, const DT (&acc)[4][4]) {
         const int i0 = 4 * (b / nbk), m0 = 4 * (b - (b / nbk) * nbk);
 #pragma unroll
         for (int r = 0; r < 4; ++r)
 #pragma unroll
             for (int q = 0; q < 4; ++q)
-                if (i0 + r < k && m0 + q < k) D[(i0 + r) * k + m0 + q] = acc[r][q];
+                if (i0 + r < k && m0 + q < k) dst[(i0 + r) * k + m0 + q] = acc[r][q];
     };
     // waves 2 and 3 park X_2 and X_3 in global scratch (their registers are
     // then free: the kernel keeps few enough VGPRs for three workgroups per
     // CU); they are copied back into slot B when their product comes
-    T *scr = a.scratch + (((int64_t)arr * a.pt.p + blk) * a.nch + ch) * 2 * kk;
+    DT *scr = a.scratch + (((int64_t)arr * a.pt.p + blk) * a.nch + ch) * 2 * kk;
     put(0, A);
     put(1, Bm);
     put(2, scr);
     put(3, scr + kk);
-    T acc[4][4];
+    DT acc[4][4];
     for (int w = 2; w <= 4; ++w) {
         __threadfence_block();                    // the parked partials, to this workgroup
         __syncthreads();                          // A and B complete
@@ -825,14 +916,14 @@ __global__ __launch_bounds__(256) void k_sweep_xfer(XferArgs<T> a)
         if (tid < nblk) block_store(A, tid, acc);
         for (int e = tid; e < kk; e += 256) Bm[e] = scr[(w - 2) * kk + e];
     }
-    T *out = a.xf[arr] + ((int64_t)blk * a.nch + ch) * kk;
+    DT *out = a.xf[arr] + ((int64_t)blk * a.nch + ch) * kk;
     if (tid < nblk) block_store(out, tid, acc);
 }
 
 template <typename T, int KM>
 static hipError_t launch_xfer_km(const XferArgs<T> &a, hipStream_t s)
 {
-    const size_t lds = 2 * (size_t)a.pt.k * a.pt.k * sizeof(T);
+    const size_t lds = 2 * (size_t)a.pt.k * a.pt.k * sizeof(double);
     if (lds > kMaxLds) return hipErrorInvalidValue;
     auto kern = k_sweep_xfer<T, KM>;
     hipError_t e = hipFuncSetAttribute((const void *)kern,

@@ -14,23 +14,37 @@ namespace sap {
 // flight for HBM.  The v tile [r0-K, r0+64+K) is staged once in LDS and the
 // four partial sums are added in LDS.  Optional residual form b - A v.
 constexpr int kSpmvRows = 64;
+// NR right-hand sides at once (multi-RHS solves): every band entry read
+// serves NR columns; v columns c0 .. c0+NR-1 of a column-major block with
+// leading dimension ld (columns past m are skipped).
+template <int NR>
 __global__ __launch_bounds__(256) void k_spmv(const double *__restrict__ band, int64_t n,
                                               int k, const double *__restrict__ v,
                                               const double *__restrict__ b,
-                                              double *__restrict__ y, int trans)
+                                              double *__restrict__ y, int trans, int64_t ld,
+                                              int m)
 {
-    __shared__ double vt[kSpmvRows + 2 * kMaxK];
-    __shared__ double part[3][kSpmvRows];
+    __shared__ double vt[NR][kSpmvRows + 2 * kMaxK];
+    __shared__ double part[3][NR][kSpmvRows];
+    const int c0 = (int)blockIdx.y * NR;
+    const int nc = min(NR, m - c0);
     const int64_t r0 = (int64_t)blockIdx.x * kSpmvRows;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    for (int i = tid; i < kSpmvRows + 2 * k; i += 256) {
-        const int64_t g = r0 - k + i;
-        vt[i] = (g >= 0 && g < n) ? v[g] : 0.0;
+#pragma unroll
+    for (int j = 0; j < NR; ++j) {
+        if (j >= nc) break;
+        const double *vj = v + (int64_t)(c0 + j) * ld;
+        for (int i = tid; i < kSpmvRows + 2 * k; i += 256) {
+            const int64_t g = r0 - k + i;
+            vt[j][i] = (g >= 0 && g < n) ? vj[g] : 0.0;
+        }
     }
     __syncthreads();
     const int64_t r = r0 + lane;
     const int w = 2 * k + 1;
-    double acc0 = 0.0, acc1 = 0.0;
+    double acc0[NR], acc1[NR];
+#pragma unroll
+    for (int j = 0; j < NR; ++j) acc0[j] = acc1[j] = 0.0;
     if (r < n) {
         if (!trans) {
             // a[r][c] at band[(k + r - c)*n + c]; c = r + k - q in [0, n)
@@ -38,28 +52,53 @@ __global__ __launch_bounds__(256) void k_spmv(const double *__restrict__ band, i
             const int qhi = (int)min((int64_t)(w - 1), r + k);
             int q = qlo + ((wave - qlo) & 3);
             for (; q + 4 <= qhi; q += 8) {
-                acc0 = fma(band[(int64_t)q * n + (r + k - q)], vt[lane + 2 * k - q], acc0);
-                acc1 = fma(band[(int64_t)(q + 4) * n + (r + k - q - 4)], vt[lane + 2 * k - q - 4], acc1);
+                const double a0 = band[(int64_t)q * n + (r + k - q)];
+                const double a1 = band[(int64_t)(q + 4) * n + (r + k - q - 4)];
+#pragma unroll
+                for (int j = 0; j < NR; ++j) {
+                    acc0[j] = fma(a0, vt[j][lane + 2 * k - q], acc0[j]);
+                    acc1[j] = fma(a1, vt[j][lane + 2 * k - q - 4], acc1[j]);
+                }
             }
-            if (q <= qhi) acc0 = fma(band[(int64_t)q * n + (r + k - q)], vt[lane + 2 * k - q], acc0);
+            if (q <= qhi) {
+                const double a0 = band[(int64_t)q * n + (r + k - q)];
+#pragma unroll
+                for (int j = 0; j < NR; ++j) acc0[j] = fma(a0, vt[j][lane + 2 * k - q], acc0[j]);
+            }
         } else {
             // a[rr][r] at band[q*n + r] with rr = r + q - k in [0, n)
             const int qlo = (int)max((int64_t)0, (int64_t)k - r);
             const int qhi = (int)min((int64_t)(w - 1), n - 1 - r + k);
             int q = qlo + ((wave - qlo) & 3);
             for (; q + 4 <= qhi; q += 8) {
-                acc0 = fma(band[(int64_t)q * n + r], vt[lane + q], acc0);
-                acc1 = fma(band[(int64_t)(q + 4) * n + r], vt[lane + q + 4], acc1);
+                const double a0 = band[(int64_t)q * n + r];
+                const double a1 = band[(int64_t)(q + 4) * n + r];
+#pragma unroll
+                for (int j = 0; j < NR; ++j) {
+                    acc0[j] = fma(a0, vt[j][lane + q], acc0[j]);
+                    acc1[j] = fma(a1, vt[j][lane + q + 4], acc1[j]);
+                }
             }
-            if (q <= qhi) acc0 = fma(band[(int64_t)q * n + r], vt[lane + q], acc0);
+            if (q <= qhi) {
+                const double a0 = band[(int64_t)q * n + r];
+#pragma unroll
+                for (int j = 0; j < NR; ++j) acc0[j] = fma(a0, vt[j][lane + q], acc0[j]);
+            }
         }
     }
-    const double acc = acc0 + acc1;
-    if (wave > 0) part[wave - 1][lane] = acc;
+#pragma unroll
+    for (int j = 0; j < NR; ++j)
+        if (wave > 0) part[wave - 1][j][lane] = acc0[j] + acc1[j];
     __syncthreads();
     if (wave == 0 && r < n) {
-        const double tot = (acc + part[0][lane]) + (part[1][lane] + part[2][lane]);
-        y[r] = b ? b[r] - tot : tot;
+#pragma unroll
+        for (int j = 0; j < NR; ++j) {
+            if (j >= nc) break;
+            const double acc = acc0[j] + acc1[j];
+            const double tot = (acc + part[0][j][lane]) + (part[1][j][lane] + part[2][j][lane]);
+            const int64_t o = (int64_t)(c0 + j) * ld + r;
+            y[o] = b ? b[o] - tot : tot;
+        }
     }
 }
 
@@ -67,7 +106,19 @@ hipError_t launch_spmv(const double *band, int64_t n, int k, const double *v,
                        const double *b, double *y, int trans, hipStream_t s)
 {
     const int64_t nblk = (n + kSpmvRows - 1) / kSpmvRows;
-    hipLaunchKernelGGL(k_spmv, dim3((unsigned)nblk), dim3(256), 0, s, band, n, k, v, b, y, trans);
+    hipLaunchKernelGGL(k_spmv<1>, dim3((unsigned)nblk), dim3(256), 0, s, band, n, k, v, b, y,
+                       trans, n, 1);
+    return hipGetLastError();
+}
+
+hipError_t launch_spmv_multi(const double *band, int64_t n, int k, const double *v,
+                             const double *b, double *y, int trans, int m, hipStream_t s)
+{
+    if (m < 1) return hipErrorInvalidValue;
+    if (m == 1) return launch_spmv(band, n, k, v, b, y, trans, s);
+    const int64_t nblk = (n + kSpmvRows - 1) / kSpmvRows;
+    hipLaunchKernelGGL(k_spmv<kMultiRhs>, dim3((unsigned)nblk, (unsigned)((m + kMultiRhs - 1) / kMultiRhs)),
+                       dim3(256), 0, s, band, n, k, v, b, y, trans, n, m);
     return hipGetLastError();
 }
 
@@ -113,13 +164,15 @@ __global__ __launch_bounds__(256) void k_correction(CorrArgs<T> a)
     const T *RI = a.Rinv + i * kk;
     __shared__ T vb[kMaxK], vt[kMaxK], w1[kMaxK], w2[kMaxK], w3[kMaxK];
     const int t = threadIdx.x;
+    const int64_t col = blockIdx.y;             // right-hand side
+    const T *g = a.g + col * a.ldg;
     if (t < k) {
-        vb[t] = a.g[s1 - k + t];
-        vt[t] = a.g[s1 + t];
+        vb[t] = g[s1 - k + t];
+        vt[t] = g[s1 + t];
     }
     __syncthreads();
-    T *dbot = a.dbot + (int64_t)i * k;          // bottom rows of block i
-    T *dtop = a.dtop + (int64_t)(i + 1) * k;    // top rows of block i+1
+    T *dbot = a.dbot + (col * a.pt.p + i) * k;       // bottom rows of block i
+    T *dtop = a.dtop + (col * a.pt.p + i + 1) * k;   // top rows of block i+1
     if (!a.trans) {
         if (t < k) {
             T s = vt[t];
@@ -202,9 +255,11 @@ __global__ __launch_bounds__(256) void k_correction_lds(CorrArgs<T> a)
         const T b = a.B[ikk + e], c = a.C[ikk + e];
         Ws[e] = w; Rs[e] = r; Vs[e] = v; Bs[e] = b; Cs[e] = c;
     }
+    const int64_t col = blockIdx.y;             // right-hand side
+    const T *g = a.g + col * a.ldg;
     if (t < k) {
-        vb[t] = a.g[s1 - k + t];
-        vt[t] = a.g[s1 + t];
+        vb[t] = g[s1 - k + t];
+        vt[t] = g[s1 + t];
     }
     __syncthreads();
     const int r = t >> 2, q = t & 3;
@@ -218,8 +273,8 @@ __global__ __launch_bounds__(256) void k_correction_lds(CorrArgs<T> a)
         s += __shfl_xor(s, 2, 64);
         return s;
     };
-    T *dbot = a.dbot + (int64_t)i * k;          // bottom rows of block i
-    T *dtop = a.dtop + (int64_t)(i + 1) * k;    // top rows of block i+1
+    T *dbot = a.dbot + (col * a.pt.p + i) * k;       // bottom rows of block i
+    T *dtop = a.dtop + (col * a.pt.p + i + 1) * k;   // top rows of block i+1
     const bool lead = act && q == 0;
     if (!a.trans) {
         T s = mv(Ws, false, vb);
@@ -258,8 +313,10 @@ __global__ __launch_bounds__(256) void k_correction_lds(CorrArgs<T> a)
 }
 
 template <typename T>
-hipError_t launch_correction(const CorrArgs<T> &a, hipStream_t s)
+hipError_t launch_correction(const CorrArgs<T> &a0, hipStream_t s)
 {
+    CorrArgs<T> a = a0;              // one right-hand side unless stated
+    if (a.m < 1) a.m = 1;
     if (a.pt.p < 2 || a.pt.k == 0) return hipSuccess;
     const size_t kk = (size_t)a.pt.k * a.pt.k;
     const size_t lds = (5 * kk + 5 * (size_t)a.pt.k) * sizeof(T);
@@ -268,9 +325,9 @@ hipError_t launch_correction(const CorrArgs<T> &a, hipStream_t s)
         hipError_t e = hipFuncSetAttribute((const void *)kern,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(kern, dim3(a.pt.p - 1), dim3(256), lds, s, a);
+        hipLaunchKernelGGL(kern, dim3(a.pt.p - 1, a.m), dim3(256), lds, s, a);
     } else {
-        hipLaunchKernelGGL(k_correction<T>, dim3(a.pt.p - 1), dim3(256), 0, s, a);
+        hipLaunchKernelGGL(k_correction<T>, dim3(a.pt.p - 1, a.m), dim3(256), 0, s, a);
     }
     return hipGetLastError();
 }
@@ -346,17 +403,38 @@ __device__ void scalar_op(int op, const double *d, double *sc, double *host)
         sc[S_NRM2] = d[0]; publish = true;
         prep_j0(d[1]);
         break;
+    case OP_CG_INIT:
+        sc[S_BREAK] = 0.0;
+        sc[S_RHO0] = d[0];
+        sc[S_NRM2] = d[1]; publish = true;
+        break;
+    case OP_CG_ALPHA:
+        if (!(d[0] > 0.0)) brk(4.0);
+        sc[S_ALPHA] = sc[S_RHO0] / d[0];
+        break;
+    case OP_CG_BETA:
+        if (sc[S_RHO0] == 0.0) brk(1.0);
+        sc[S_BETA] = d[0] / sc[S_RHO0];
+        sc[S_RHO0] = d[0];
+        break;
     default:
         break;
     }
     if (host) {
         if (publish) host[H_NRM2] = sc[S_NRM2];
-        if (op == OP_INIT) host[H_NRM0] = sc[S_NRM2];
+        if (op == OP_INIT || op == OP_CG_INIT) host[H_NRM0] = sc[S_NRM2];
         host[H_BREAK] = sc[S_BREAK];
     }
 }
 
 // Block-reduce up to three per-thread sums and store this block's partials.
+// Multi-RHS form: column col of the vectors (ld apart) has its own partials,
+// scalars and host slots; frozen columns (bit col of a.frozen) are skipped.
+__device__ __forceinline__ bool col_frozen(const DotArgs &a, int col)
+{
+    return col < 64 && ((a.frozen >> col) & 1ull);
+}
+
 __device__ void finish_dots(const DotArgs &a, double l0, double l1, double l2)
 {
     __shared__ double red[3][4];
@@ -366,7 +444,8 @@ __device__ void finish_dots(const DotArgs &a, double l0, double l1, double l2)
     __syncthreads();
     if (tid == 0)
         for (int d = 0; d < 3; ++d)
-            a.partial[blockIdx.x * 3 + d] = (red[d][0] + red[d][1]) + (red[d][2] + red[d][3]);
+            a.partial[((int64_t)blockIdx.y * kDotBlocks + blockIdx.x) * 3 + d] =
+                (red[d][0] + red[d][1]) + (red[d][2] + red[d][3]);
 }
 
 // One workgroup combines the kDotBlocks partials of the preceding launch in a
@@ -377,9 +456,12 @@ __global__ __launch_bounds__(256) void k_dots_final(DotArgs a)
 {
     __shared__ double tot[3][256];
     const int tid = threadIdx.x;
+    const int col = blockIdx.x;
+    if (col_frozen(a, col)) return;
+    const double *part = a.partial + (int64_t)col * kDotBlocks * 3;
     for (int d = 0; d < 3; ++d) {
         double s = 0.0;
-        for (int b = tid; b < kDotBlocks; b += 256) s += a.partial[b * 3 + d];
+        for (int b = tid; b < kDotBlocks; b += 256) s += part[b * 3 + d];
         tot[d][tid] = s;
     }
     __syncthreads();
@@ -390,8 +472,9 @@ __global__ __launch_bounds__(256) void k_dots_final(DotArgs a)
     }
     if (tid == 0) {
         const double dd[3] = {tot[0][0], tot[1][0], tot[2][0]};
-        scalar_op(a.op, dd, a.sc, a.host);
-        if (a.status && a.host) {
+        scalar_op(a.op, dd, a.sc + (int64_t)col * kScalars,
+                  a.host ? a.host + (int64_t)col * kHostSlots : nullptr);
+        if (a.status && a.host && col == 0) {
             a.host[H_NBOOST] = (double)a.status[0];
             a.host[H_SING] = (double)a.status[1];
         }
@@ -401,25 +484,37 @@ __global__ __launch_bounds__(256) void k_dots_final(DotArgs a)
 
 __global__ __launch_bounds__(256) void k_dots(DotArgs a)
 {
+    const int col = blockIdx.y;
+    if (col_frozen(a, col)) return;
+    const int64_t off = (int64_t)col * a.ld;
     double l[3] = {0.0, 0.0, 0.0};
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < a.n;
          i += (int64_t)gridDim.x * 256) {
         for (int d = 0; d < 3; ++d)
-            if (d < a.nd) l[d] = fma(a.x[d][i], a.y[d][i], l[d]);
+            if (d < a.nd) l[d] = fma(a.x[d][off + i], a.y[d][off + i], l[d]);
     }
     finish_dots(a, l[0], l[1], l[2]);
 }
 
-hipError_t launch_dots(const DotArgs &a, hipStream_t s)
+hipError_t launch_dots(const DotArgs &a0, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_dots, dim3(kDotBlocks), dim3(256), 0, s, a);
-    hipLaunchKernelGGL(k_dots_final, dim3(1), dim3(256), 0, s, a);
+    DotArgs a = a0;
+    if (a.m < 1) a.m = 1;
+    hipLaunchKernelGGL(k_dots, dim3(kDotBlocks, a.m), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_dots_final, dim3(a.m), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
 __global__ __launch_bounds__(256) void k_update(UpdArgs a)
 {
-    const double *sc = a.dots.sc;
+    const int col = blockIdx.y;
+    if (col_frozen(a.dots, col)) return;
+    if (col > 0) {               // column col of every vector, its own scalars
+        const int64_t off = (int64_t)col * a.dots.ld;
+        for (double **v : {&a.x, &a.r0, &a.r1, &a.r2, &a.u0, &a.u1, &a.u2, &a.rt})
+            if (*v) *v += off;
+    }
+    const double *sc = a.dots.sc + (int64_t)col * kScalars;
     const double beta = sc[S_BETA], alpha = sc[S_ALPHA], tau12 = sc[S_TAU12];
     const double g1 = sc[S_G1], g2 = sc[S_G2], gp1 = sc[S_GP1], gp2 = sc[S_GP2],
                  gpp1 = sc[S_GPP1];
@@ -473,6 +568,23 @@ __global__ __launch_bounds__(256) void k_update(UpdArgs a)
             l0 = fma(r, r, l0);        // (r0, rt) = (r0, r0)
             break;
         }
+        case UPD_CG_INIT: {
+            const double r = a.r0[i], z = a.r1[i];
+            a.u0[i] = z;
+            l0 = fma(r, z, l0);
+            l1 = fma(r, r, l1);
+            break;
+        }
+        case UPD_CG_XR: {
+            a.x[i] += alpha * a.u0[i];
+            const double r = a.r0[i] - alpha * a.u1[i];
+            a.r0[i] = r;
+            l0 = fma(r, r, l0);
+            break;
+        }
+        case UPD_CG_P:
+            a.u0[i] = a.r1[i] + beta * a.u0[i];
+            break;
         default:
             break;
         }
@@ -480,14 +592,17 @@ __global__ __launch_bounds__(256) void k_update(UpdArgs a)
     if (a.dots.nd == 0) return;
     if (a.kind == UPD_RESTART) l1 = l0;
     // dot order per kind: J0/J1 -> (r0,r0); MR2 -> (r2,r2),(r0,r2);
-    // FINAL -> (r0,r0),(r0,rt); RESTART -> (r0,rt),(r0,r0)
+    // FINAL -> (r0,r0),(r0,rt); RESTART -> (r0,rt),(r0,r0);
+    // CG_INIT -> (r,z),(r,r); CG_XR -> (r,r)
     finish_dots(a.dots, l0, l1, 0.0);
 }
 
-hipError_t launch_update(const UpdArgs &a, hipStream_t s)
+hipError_t launch_update(const UpdArgs &a0, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_update, dim3(kDotBlocks), dim3(256), 0, s, a);
-    if (a.dots.nd > 0) hipLaunchKernelGGL(k_dots_final, dim3(1), dim3(256), 0, s, a.dots);
+    UpdArgs a = a0;
+    if (a.dots.m < 1) a.dots.m = 1;
+    hipLaunchKernelGGL(k_update, dim3(kDotBlocks, a.dots.m), dim3(256), 0, s, a);
+    if (a.dots.nd > 0) hipLaunchKernelGGL(k_dots_final, dim3(a.dots.m), dim3(256), 0, s, a.dots);
     return hipGetLastError();
 }
 
@@ -501,6 +616,42 @@ __global__ void k_fill(double *v, double val, int64_t n)
 hipError_t launch_fill(double *v, double val, int64_t n, hipStream_t s)
 {
     hipLaunchKernelGGL(k_fill, dim3(kDotBlocks), dim3(256), 0, s, v, val, n);
+    return hipGetLastError();
+}
+
+// zero `words` 32-bit words (used instead of a memset node, so the callers
+// stay capturable into a graph)
+__global__ void k_zero32(unsigned *v, int64_t words)
+{
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < words;
+         i += (int64_t)gridDim.x * 256)
+        v[i] = 0u;
+}
+
+hipError_t launch_zero(void *p, size_t bytes, hipStream_t s)
+{
+    if (bytes % 4) return hipErrorInvalidValue;
+    const int64_t words = (int64_t)(bytes / 4);
+    if (words == 0) return hipSuccess;
+    const int64_t want = (words + 255) / 256;
+    const int grid = (int)(want < kDotBlocks ? want : kDotBlocks);
+    hipLaunchKernelGGL(k_zero32, dim3(grid), dim3(256), 0, s, static_cast<unsigned *>(p), words);
+    return hipGetLastError();
+}
+
+// Block boundaries of Sec. 3.1 (first P_r = N - P floor(N/P) blocks one row
+// longer), computed on the device so that no host buffer is involved.
+__global__ void k_partition_starts(int64_t *starts, int64_t n, int p)
+{
+    const int64_t q = n / p, pr = n - (int64_t)p * q;
+    for (int i = (int)(blockIdx.x * 256 + threadIdx.x); i <= p; i += (int)(gridDim.x * 256))
+        starts[i] = (int64_t)i * q + (i < pr ? i : pr);
+}
+
+hipError_t launch_partition_starts(int64_t *starts, int64_t n, int p, hipStream_t s)
+{
+    const int grid = (p + 1 + 255) / 256;
+    hipLaunchKernelGGL(k_partition_starts, dim3(grid), dim3(256), 0, s, starts, n, p);
     return hipGetLastError();
 }
 

@@ -4,6 +4,7 @@
 #include "sap.h"
 #include "sap_internal.h"
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -34,11 +35,15 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-    size_t starts, partial, status, Lc, Uc, Lr, Ur, corner, B, C, V, W, Rbar, Rlu, Rinv, piv,
+    size_t starts, partial, status, Lc, Uc, Lr, Ur, corner, lwin, B, C, V, W, Rbar, Rlu, Rinv, piv,
         gT, yT, dtop, dbot, kv, dpart, sc, xLc, xUc, xLr, xUr, xscr, sq, sst, ticket, total;
 };
 
 bool coupled_active(const sap_options &o) { return o.mode == SAP_COUPLED && o.p > 1 && o.k > 0; }
+
+// right-hand sides a batched solve may take at once (the workspace holds
+// that many of every per-right-hand-side vector)
+int rhs_cap(const sap_options &o) { return o.nrhs > 1 ? o.nrhs : 1; }
 
 // Workgroups per block of k_block_norm, which covers 64 columns each: the
 // grid and the partial-norm array are both sized by this one count.
@@ -92,8 +97,7 @@ int validate(const sap_options *o)
     if (o->factor_prec != SAP_PREC_FP64 && o->factor_prec != SAP_PREC_FP32)
         return fail(SAP_ERR_INVALID, "factor_prec must be SAP_PREC_FP64 or SAP_PREC_FP32");
     if (o->sweep_chunks < 0) return fail(SAP_ERR_INVALID, "sweep_chunks must be >= 0");
-    if (o->factor_prec == SAP_PREC_FP64 && o->k > 160)
-        return fail(SAP_ERR_INVALID, "FP64 factors support K <= 160");
+    if (o->nrhs < 0 || o->nrhs > kMaxRhs) return fail(SAP_ERR_INVALID, "nrhs must be in [0, 64]");
     if (o->mode == SAP_COUPLED && o->p > 1 && o->n / o->p < 2 * (int64_t)o->k)
         return fail(SAP_ERR_INVALID, "coupled mode needs floor(N/P) >= 2K");
     if (std::isnan(o->boost_eps)) return fail(SAP_ERR_INVALID, "boost_eps is NaN");
@@ -125,6 +129,8 @@ Layout layout_for(const sap_options &o)
     L.Ur = o.adjoint ? take(fb) : 0;
     const size_t ni = cpl ? (size_t)(p - 1) : 0;
     L.corner = cpl ? take(sf * p * kk) : 0;
+    // window slabs of the FP64 wide-band LU, one per LU/UL workgroup
+    L.lwin = (sf == 8 && k >= kLuWideMinK) ? take(lu_wide_window_bytes(k) * (cpl ? 2 : 1) * p) : 0;
     L.B = cpl ? take(sf * ni * kk) : 0;
     L.C = cpl ? take(sf * ni * kk) : 0;
     L.V = cpl ? take(sf * ni * kk) : 0;
@@ -133,23 +139,24 @@ Layout layout_for(const sap_options &o)
     L.Rlu = cpl ? take(sf * ni * kk) : 0;
     L.Rinv = cpl ? take(sf * ni * kk) : 0;
     L.piv = cpl ? take(sizeof(int) * ni * k) : 0;
-    L.gT = take(sf * n);
-    L.yT = take(sf * n);
-    L.dtop = cpl ? take(sf * (size_t)p * k) : 0;
-    L.dbot = cpl ? take(sf * (size_t)p * k) : 0;
-    L.kv = take(sizeof(double) * 8 * (size_t)n);
-    L.dpart = take(sizeof(double) * 3 * kDotBlocks);
-    L.sc = take(sizeof(double) * kScalars);
+    const size_t m = rhs_cap(o);
+    L.gT = take(sf * n * m);
+    L.yT = take(sf * n * m);
+    L.dtop = cpl ? take(sf * (size_t)p * k * m) : 0;
+    L.dbot = cpl ? take(sf * (size_t)p * k * m) : 0;
+    L.kv = take(sizeof(double) * 8 * (size_t)n * m);
+    L.dpart = take(sizeof(double) * 3 * kDotBlocks * m);
+    L.sc = take(sizeof(double) * kScalars * m);
     const Chunking ck = chunking_for(o);
     if (ck.nch >= 2) {
-        const size_t xb = sf * (size_t)p * ck.nch * kk;
+        const size_t xb = sizeof(double) * (size_t)p * ck.nch * kk;   // FP64 transfer matrices
         L.xLc = take(xb);
         L.xUc = take(xb);
         L.xLr = o.adjoint ? take(xb) : 0;
         L.xUr = o.adjoint ? take(xb) : 0;
         L.xscr = take(2 * xb * (o.adjoint ? 4 : 2));     // k_sweep_xfer partials
-        L.sq = take(2 * sf * (size_t)p * ck.nch * k);     // first and second sweep of a D^{-1}
-        L.sst = take(sf * (size_t)p * ck.nch * k);
+        L.sq = take(2 * sf * (size_t)p * ck.nch * k * m);     // first and second sweep of a D^{-1}
+        L.sst = take(sizeof(double) * (size_t)p * ck.nch * k);
         L.ticket = take(sizeof(unsigned) * (size_t)p);
     }
     L.total = off;
@@ -166,10 +173,15 @@ struct sap_handle_ {
     Chunking ck;             // sweep chains per block
     unsigned char *ws;
     Layout L;
-    int64_t *h_starts;       // pinned copy of the partition
-    double *h_slots;         // pinned, mapped: written by reduction kernels
-    double *d_slots;         // device alias of h_slots
-    int32_t *h_status;       // pinned
+    double *h_slots;         // host view of the result slots
+    double *d_slots;         // device address the reduction kernels write them to
+    int32_t *h_status;       // host copy of the factorization's status words
+    // mapped: h_slots is pinned host memory mapped at d_slots (sap_create);
+    // otherwise d_slots is device memory and sync_read copies it into
+    // slot_copy (handles without host allocations)
+    bool mapped;
+    double slot_copy[kHostSlots];
+    int32_t status_copy[2];
     const double *a_band;
     bool factored, starts_uploaded;
     hipEvent_t ev[5];        // factor start / after LU / end, solve start / end
@@ -184,7 +196,8 @@ struct sap_handle_ {
     int64_t prof_n[SAP_KERNEL_COUNT];
 
     template <typename T> T *ptr(size_t off) { return reinterpret_cast<T *>(ws + off); }
-    double *kvec(int i) { return ptr<double>(L.kv) + (size_t)i * opt.n; }
+    // Krylov vector i: an N x nrhs block (column c at + c*N); single solves use column 0
+    double *kvec(int i) { return ptr<double>(L.kv) + (size_t)i * opt.n * rhs_cap(opt); }
 };
 
 namespace {
@@ -224,15 +237,31 @@ enum KVec { KV_R0 = 0, KV_R1, KV_R2, KV_U0, KV_U1, KV_U2, KV_RT, KV_T };
 // enters the first chunk of each block as its incoming state.
 template <typename T>
 int dinv(sap_handle h, int trans, const double *xin, const T *dtop, const T *dbot,
-         double *dout, T *tout, hipStream_t s, bool reuse_q = false)
+         double *dout, T *tout, hipStream_t s, bool reuse_q = false, int m = 1)
 {
+    if (m > 1 && !sweep_top_state_supported(h->opt.k)) {
+        // the ring kernels of wide bands sweep one right-hand side at a time
+        // (they never reuse a zero-state pass, so the columns are independent)
+        const int64_t n = h->opt.n, pk = (int64_t)h->opt.p * h->opt.k;
+        for (int c = 0; c < m; ++c) {
+            const int rc = dinv<T>(h, trans, xin + c * n, dtop ? dtop + c * pk : nullptr,
+                                   dbot ? dbot + c * pk : nullptr, dout ? dout + c * n : nullptr,
+                                   tout ? tout + c * n : nullptr, s, false, 1);
+            if (rc) return rc;
+        }
+        return SAP_OK;
+    }
     SweepArgs<T> a1{};
+    a1.m = m;
+    a1.ldv = h->opt.n;
     a1.pt = h->pt;
     a1.xin = xin;
     a1.dtop = dtop;
     a1.dbot = dbot;
     a1.tout = h->ptr<T>(h->L.yT);
     SweepArgs<T> a2{};
+    a2.m = m;
+    a2.ldv = h->opt.n;
     a2.pt = h->pt;
     a2.tin = h->ptr<T>(h->L.yT);
     a2.dout = dout;
@@ -245,11 +274,11 @@ int dinv(sap_handle h, int trans, const double *xin, const T *dtop, const T *dbo
         a2.F = h->ptr<T>(h->L.Lr); a2.fwd = 0; a2.diag = 0;
     }
     if (trans) {
-        a1.xf = h->ptr<T>(h->L.xUr);
-        a2.xf = h->ptr<T>(h->L.xLr);
+        a1.xf = h->ptr<double>(h->L.xUr);
+        a2.xf = h->ptr<double>(h->L.xLr);
     } else {
-        a1.xf = h->ptr<T>(h->L.xLc);
-        a2.xf = h->ptr<T>(h->L.xUc);
+        a1.xf = h->ptr<double>(h->L.xLc);
+        a2.xf = h->ptr<double>(h->L.xUc);
     }
     for (SweepArgs<T> *a : {&a1, &a2}) {
         if (h->ck.nch < 2) {
@@ -261,8 +290,9 @@ int dinv(sap_handle h, int trans, const double *xin, const T *dtop, const T *dbo
         }
         a->nch = h->ck.nch;
         a->clen = h->ck.clen;
-        a->q = h->ptr<T>(h->L.sq) + (a == &a1 ? 0 : (size_t)h->opt.p * h->ck.nch * h->opt.k);
-        a->st = h->ptr<T>(h->L.sst);
+        a->q = h->ptr<T>(h->L.sq) +
+               (a == &a1 ? 0 : (size_t)h->opt.p * h->ck.nch * h->opt.k * rhs_cap(h->opt));
+        a->st = h->ptr<double>(h->L.sst);
         a->ticket = h->ptr<unsigned>(h->L.ticket);
         // dbot must stay inside each block's last chunk, whose q is not used
         const bool reuse = reuse_q && a == &a1 && sweep_top_state_supported(h->opt.k) &&
@@ -283,12 +313,12 @@ int dinv(sap_handle h, int trans, const double *xin, const T *dtop, const T *dbo
 }
 
 template <typename T>
-int precond_t(sap_handle h, int trans, const double *r, double *z, hipStream_t s)
+int precond_t(sap_handle h, int trans, const double *r, double *z, hipStream_t s, int m)
 {
-    if (!h->coupled) return dinv<T>(h, trans, r, nullptr, nullptr, z, nullptr, s);
+    if (!h->coupled) return dinv<T>(h, trans, r, nullptr, nullptr, z, nullptr, s, false, m);
     T *g = h->ptr<T>(h->L.gT);
     T *dtop = h->ptr<T>(h->L.dtop), *dbot = h->ptr<T>(h->L.dbot);
-    int rc = dinv<T>(h, trans, r, nullptr, nullptr, nullptr, g, s);
+    int rc = dinv<T>(h, trans, r, nullptr, nullptr, nullptr, g, s, false, m);
     if (rc) return rc;
     CorrArgs<T> c{};
     c.pt = h->pt;
@@ -298,32 +328,45 @@ int precond_t(sap_handle h, int trans, const double *r, double *z, hipStream_t s
     c.Rinv = h->ptr<T>(h->L.Rinv);
     c.dtop = dtop; c.dbot = dbot;
     c.trans = trans;
+    c.m = m;
+    c.ldg = h->opt.n;
     {
         ProfScope ps(h, SAP_KERNEL_CORR, s);
         HIP_TRY(launch_correction<T>(c, s));
     }
-    return dinv<T>(h, trans, r, dtop, dbot, z, nullptr, s, true);
+    return dinv<T>(h, trans, r, dtop, dbot, z, nullptr, s, true, m);
 }
 
-int precond(sap_handle h, int trans, const double *r, double *z, hipStream_t s)
+// z = M^{-1} r for m right-hand sides (N x m blocks, column c at + c*N)
+int precond(sap_handle h, int trans, const double *r, double *z, hipStream_t s, int m = 1)
 {
-    return h->fp32 ? precond_t<float>(h, trans, r, z, s) : precond_t<double>(h, trans, r, z, s);
+    return h->fp32 ? precond_t<float>(h, trans, r, z, s, m)
+                   : precond_t<double>(h, trans, r, z, s, m);
 }
 
-// Krylov operator  v -> M^{-1} A v  (or M^{-T} A^T v)
-int apply_op(sap_handle h, int trans, const double *v, double *out, hipStream_t s)
+// Krylov operator  v -> M^{-1} A v  (or M^{-T} A^T v), m right-hand sides
+int apply_op(sap_handle h, int trans, const double *v, double *out, hipStream_t s, int m = 1)
 {
     double *t = h->kvec(KV_T);
     {
         ProfScope ps(h, SAP_KERNEL_SPMV, s);
-        HIP_TRY(launch_spmv(h->a_band, h->opt.n, h->opt.k, v, nullptr, t, trans, s));
+        HIP_TRY(launch_spmv_multi(h->a_band, h->opt.n, h->opt.k, v, nullptr, t, trans, m, s));
     }
-    return precond(h, trans, t, out, s);
+    return precond(h, trans, t, out, s, m);
 }
 
-DotArgs dot_args(sap_handle h, int op)
+// columns of the current batched solve (1 and none frozen for single solves)
+struct Batch {
+    int m = 1;
+    uint64_t frozen = 0;
+};
+
+DotArgs dot_args(sap_handle h, int op, const Batch &bt = Batch())
 {
     DotArgs d{};
+    d.m = bt.m;
+    d.ld = h->opt.n;
+    d.frozen = bt.frozen;
     d.n = h->opt.n;
     d.partial = h->ptr<double>(h->L.dpart);
     d.sc = h->ptr<double>(h->L.sc);
@@ -333,9 +376,9 @@ DotArgs dot_args(sap_handle h, int op)
 }
 
 int dots(sap_handle h, int op, std::initializer_list<std::pair<const double *, const double *>> pr,
-         hipStream_t s, const int *status = nullptr)
+         hipStream_t s, const int *status = nullptr, const Batch &bt = Batch())
 {
-    DotArgs d = dot_args(h, op);
+    DotArgs d = dot_args(h, op, bt);
     d.status = status;
     int i = 0;
     for (auto &p : pr) { d.x[i] = p.first; d.y[i] = p.second; ++i; }
@@ -345,7 +388,8 @@ int dots(sap_handle h, int op, std::initializer_list<std::pair<const double *, c
     return SAP_OK;
 }
 
-int update(sap_handle h, int kind, double *x, int op, int nd, hipStream_t s)
+int update(sap_handle h, int kind, double *x, int op, int nd, hipStream_t s,
+           const Batch &bt = Batch())
 {
     UpdArgs u{};
     u.kind = kind;
@@ -354,7 +398,7 @@ int update(sap_handle h, int kind, double *x, int op, int nd, hipStream_t s)
     u.r0 = h->kvec(KV_R0); u.r1 = h->kvec(KV_R1); u.r2 = h->kvec(KV_R2);
     u.u0 = h->kvec(KV_U0); u.u1 = h->kvec(KV_U1); u.u2 = h->kvec(KV_U2);
     u.rt = h->kvec(KV_RT);
-    u.dots = dot_args(h, op);
+    u.dots = dot_args(h, op, bt);
     u.dots.nd = nd;
     ProfScope ps(h, SAP_KERNEL_KRYLOV, s);
     HIP_TRY(launch_update(u, s));
@@ -363,6 +407,9 @@ int update(sap_handle h, int kind, double *x, int op, int nd, hipStream_t s)
 
 int sync_read(sap_handle h, hipStream_t s, double *nrm2, double *brk)
 {
+    if (!h->mapped)
+        HIP_TRY(hipMemcpyAsync(h->h_slots, h->d_slots, sizeof(double) * kHostSlots * rhs_cap(h->opt),
+                               hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     *nrm2 = h->h_slots[H_NRM2];
     *brk = h->h_slots[H_BREAK];
@@ -389,7 +436,7 @@ int read_factor_status(sap_handle h, hipStream_t s, int32_t *nboost, int32_t *si
 // (the factorization finished before it), so it adds no host round trip.
 static void collect_factor_times(sap_handle h)
 {
-    if (h->t_factor >= 0.0f) return;
+    if (h->t_factor >= 0.0f || !h->ev[2]) return;
     if (hipEventSynchronize(h->ev[2]) != hipSuccess) return;
     (void)hipEventElapsedTime(&h->t_factor, h->ev[0], h->ev[2]);
     (void)hipEventElapsedTime(&h->t_lu, h->ev[0], h->ev[1]);
@@ -411,7 +458,7 @@ int krylov(sap_handle h, int trans, const double *b, double *x, double tol, int3
         return fail(SAP_ERR_INVALID, "b and x overlap");
 
     sap_stats loc{};
-    HIP_TRY(hipEventRecord(h->ev[3], s));
+    if (h->ev[3]) HIP_TRY(hipEventRecord(h->ev[3], s));
     double *r0 = h->kvec(KV_R0), *r1 = h->kvec(KV_R1), *r2 = h->kvec(KV_R2);
     double *u0 = h->kvec(KV_U0), *u1 = h->kvec(KV_U1), *u2 = h->kvec(KV_U2);
     double *rt = h->kvec(KV_RT), *t = h->kvec(KV_T);
@@ -432,9 +479,13 @@ int krylov(sap_handle h, int trans, const double *b, double *x, double tol, int3
     const double bnorm = std::sqrt(nrm2);
     HIP_TRY(launch_fill(x, 0.0, n, s));
     auto finish = [&](int code, const char *msg) {
-        HIP_TRY(hipEventRecord(h->ev[4], s));
-        HIP_TRY(hipEventSynchronize(h->ev[4]));
-        HIP_TRY(hipEventElapsedTime(&loc.t_solve_ms, h->ev[3], h->ev[4]));
+        if (h->ev[4]) {
+            HIP_TRY(hipEventRecord(h->ev[4], s));
+            HIP_TRY(hipEventSynchronize(h->ev[4]));
+            HIP_TRY(hipEventElapsedTime(&loc.t_solve_ms, h->ev[3], h->ev[4]));
+        } else {
+            HIP_TRY(hipStreamSynchronize(s));
+        }
         collect_factor_times(h);
         loc.t_factor_ms = h->t_factor;
         loc.t_lu_ms = h->t_lu;
@@ -610,6 +661,309 @@ int krylov(sap_handle h, int trans, const double *b, double *x, double tol, int3
     return finish(SAP_NOT_CONVERGED, "maximum number of iterations reached");
 }
 
+// BiCGStab(2) on m right-hand sides at once (columns of B and X, N apart),
+// x0 = 0.  Every operator application, dot product and vector update runs
+// once for all columns (the SpMV and the sweeps read A and the factors once
+// per kMultiRhs columns); each column keeps its own recurrence scalars.  The
+// columns run in lockstep: a converged column is frozen (its x is final and
+// its updates are skipped), and when a candidate exit of any column fails its
+// true-residual test, every active column restarts from its own true
+// residual, so that all stay at the same step of the cycle.  A column's
+// iteration count is the number of operator applications made while it was
+// active, over 4.
+int krylov_batch(sap_handle h, const double *B, double *X, int m, double tol, int32_t maxit,
+                 hipStream_t s, sap_stats *st)
+{
+    if (!h->factored) return fail(SAP_ERR_STATE, "sap_factor has not been called");
+    if (!B || !X) return fail(SAP_ERR_INVALID, "null matrix pointer");
+    if (m < 1 || m > rhs_cap(h->opt))
+        return fail(SAP_ERR_INVALID, "m must be in [1, nrhs of the handle]");
+    if (!(tol > 0.0)) return fail(SAP_ERR_INVALID, "tol must be > 0");
+    if (maxit < 1) return fail(SAP_ERR_INVALID, "maxit must be >= 1");
+    const int64_t n = h->opt.n;
+    const int64_t tot = n * m;
+    if ((const void *)B < (const void *)(X + tot) && (const void *)X < (const void *)(B + tot))
+        return fail(SAP_ERR_INVALID, "B and X overlap");
+    std::vector<sap_stats> loc(m);
+    if (h->ev[3]) HIP_TRY(hipEventRecord(h->ev[3], s));
+    double *r0 = h->kvec(KV_R0), *r1 = h->kvec(KV_R1), *r2 = h->kvec(KV_R2);
+    double *u0 = h->kvec(KV_U0), *u1 = h->kvec(KV_U1), *u2 = h->kvec(KV_U2);
+    double *rt = h->kvec(KV_RT), *t = h->kvec(KV_T);
+    const double *A = h->a_band;
+    const int k = h->opt.k;
+    Batch bt;
+    bt.m = m;
+    auto slot = [&](int c, int i) { return h->h_slots[(size_t)c * kHostSlots + i]; };
+    double nrm2 = 0, brk = 0;
+    TRY(dots(h, OP_NORM, {{B, B}}, s, h->ptr<int>(h->L.status), bt));
+    TRY(sync_read(h, s, &nrm2, &brk));
+    for (int c = 0; c < m; ++c) loc[c].n_boosted = (int32_t)slot(0, H_NBOOST);
+    if (const int32_t singular = (int32_t)slot(0, H_SING)) {
+        if (st) std::copy(loc.begin(), loc.end(), st);
+        return fail(SAP_ERR_SINGULAR, singular == 1 ? "zero pivot in a diagonal block (boosting disabled)"
+                                                    : "singular reduced matrix Rbar");
+    }
+    std::vector<double> bnorm(m), pnorm0(m), thr(m), pstart(m), tnr(m);
+    std::vector<int> napply(m, 0), started(m, 0), first(m, 1);
+    for (int c = 0; c < m; ++c) {
+        bnorm[c] = std::sqrt(slot(c, H_NRM2));
+        if (bnorm[c] == 0.0) {                 // x = 0 solves it
+            loc[c].converged = 1;
+            bt.frozen |= 1ull << c;
+        }
+    }
+    HIP_TRY(launch_fill(X, 0.0, tot, s));
+    const double reliable = h->fp32 ? 1e-4 : 0.0;
+    int code = SAP_NOT_CONVERGED;
+    const char *msg = "maximum number of iterations reached";
+    auto all_frozen = [&]() { return bt.frozen == (m == 64 ? ~0ull : ((1ull << m) - 1)); };
+    auto count_apply = [&]() {
+        for (int c = 0; c < m; ++c)
+            if (!((bt.frozen >> c) & 1)) ++napply[c];
+    };
+    auto finish = [&](int rc, const char *why) {
+        if (h->ev[4]) {
+            HIP_TRY(hipEventRecord(h->ev[4], s));
+            HIP_TRY(hipEventSynchronize(h->ev[4]));
+        } else {
+            HIP_TRY(hipStreamSynchronize(s));
+        }
+        float ms = 0.0f;
+        if (h->ev[4]) HIP_TRY(hipEventElapsedTime(&ms, h->ev[3], h->ev[4]));
+        collect_factor_times(h);
+        for (int c = 0; c < m; ++c) {
+            loc[c].t_solve_ms = ms;
+            loc[c].t_factor_ms = h->t_factor;
+            loc[c].t_lu_ms = h->t_lu;
+            loc[c].t_tips_ms = h->t_tips;
+            loc[c].n_apply = napply[c];
+            loc[c].iters = napply[c] / 4.0;
+        }
+        if (st) std::copy(loc.begin(), loc.end(), st);
+        if (rc != SAP_OK && rc != SAP_NOT_CONVERGED) return fail(rc, why);
+        if (rc == SAP_NOT_CONVERGED) g_err = why;
+        return rc;
+    };
+    if (all_frozen()) return finish(SAP_OK, "");
+    // restart every active column from R (the initial start: R = B)
+    auto restart = [&](const double *R) -> int {
+        TRY(precond(h, 0, R, r0, s, m));
+        count_apply();
+        TRY(update(h, UPD_RESTART, X, OP_INIT, 2, s, bt));
+        for (int c = 0; c < m; ++c) started[c] = 0;
+        return SAP_OK;
+    };
+    TRY(restart(B));
+    for (int c = 0; c < m; ++c) napply[c] = 0;            // the first M^{-1} b is not counted
+    // exit test of all active columns: 1 all converged, 2 restarted, 0 go on
+    auto exit_test = [&]() -> int {
+        TRY(sync_read(h, s, &nrm2, &brk));
+        bool any_cand = false;
+        std::vector<int> cand(m, 0);
+        for (int c = 0; c < m; ++c) {
+            if ((bt.frozen >> c) & 1) continue;
+            if (!started[c]) {
+                pstart[c] = std::sqrt(slot(c, H_NRM0));
+                if (first[c]) {
+                    pnorm0[c] = pstart[c];
+                    thr[c] = tol * pnorm0[c];
+                    first[c] = 0;
+                } else {
+                    thr[c] = tol * bnorm[c] * pstart[c] / tnr[c];
+                }
+                started[c] = 1;
+            }
+            const double bk = slot(c, H_BREAK), pn2 = slot(c, H_NRM2);
+            if (bk != 0.0 || !std::isfinite(pn2)) return SAP_ERR_BREAKDOWN;
+            const double pn = std::sqrt(pn2);
+            loc[c].rel_resid_precond = pn / pnorm0[c];
+            if (pn <= thr[c] || (reliable > 0.0 && pn <= reliable * pstart[c])) {
+                cand[c] = 1;
+                any_cand = true;
+            }
+        }
+        if (!any_cand) return 0;
+        {
+            ProfScope ps(h, SAP_KERNEL_SPMV, s);                  // T = B - A X
+            HIP_TRY(launch_spmv_multi(A, n, k, X, B, t, 0, m, s));
+        }
+        TRY(dots(h, OP_NORM, {{t, t}}, s, nullptr, bt));
+        TRY(sync_read(h, s, &nrm2, &brk));
+        bool restart_needed = false;
+        for (int c = 0; c < m; ++c) {
+            if ((bt.frozen >> c) & 1) continue;
+            tnr[c] = std::sqrt(slot(c, H_NRM2));
+            loc[c].rel_resid_true = tnr[c] / bnorm[c];
+            if (cand[c] && loc[c].rel_resid_true <= tol) {
+                loc[c].converged = 1;
+                bt.frozen |= 1ull << c;
+            } else if (cand[c]) {
+                restart_needed = true;
+            }
+        }
+        if (all_frozen()) return 1;
+        if (!restart_needed) return 0;
+        for (int c = 0; c < m; ++c)
+            if (!((bt.frozen >> c) & 1)) ++loc[c].restarts;
+        TRY(restart(t));
+        return 2;
+    };
+    for (int32_t it = 0; it < maxit; ++it) {
+        int e;
+        TRY(update(h, UPD_U0, X, 0, 0, s, bt));
+        TRY(apply_op(h, 0, u0, u1, s, m)); count_apply();
+        TRY(dots(h, OP_GAMMA, {{u1, rt}}, s, nullptr, bt));
+        TRY(update(h, UPD_J0, X, OP_EXIT, 1, s, bt));
+        e = exit_test();
+        if (e < 0) { code = e; msg = "breakdown in BiCGStab(2)"; break; }
+        if (e == 1) { code = SAP_OK; break; }
+        if (e == 2) continue;
+        TRY(apply_op(h, 0, r0, r1, s, m)); count_apply();
+        TRY(dots(h, OP_RHO, {{r1, rt}}, s, nullptr, bt));
+        TRY(update(h, UPD_U01, X, 0, 0, s, bt));
+        TRY(apply_op(h, 0, u1, u2, s, m)); count_apply();
+        TRY(dots(h, OP_GAMMA, {{u2, rt}}, s, nullptr, bt));
+        TRY(update(h, UPD_J1, X, OP_EXIT, 1, s, bt));
+        e = exit_test();
+        if (e < 0) { code = e; msg = "breakdown in BiCGStab(2)"; break; }
+        if (e == 1) { code = SAP_OK; break; }
+        if (e == 2) continue;
+        TRY(apply_op(h, 0, r1, r2, s, m)); count_apply();
+        TRY(dots(h, OP_MR1, {{r1, r1}, {r0, r1}, {r2, r1}}, s, nullptr, bt));
+        TRY(update(h, UPD_MR2, X, OP_MR2, 2, s, bt));
+        TRY(update(h, UPD_FINAL, X, OP_FINAL, 2, s, bt));
+        e = exit_test();
+        if (e < 0) { code = e; msg = "breakdown in BiCGStab(2)"; break; }
+        if (e == 1) { code = SAP_OK; break; }
+    }
+    if (code == SAP_NOT_CONVERGED) {
+        // true residuals of the columns still active
+        {
+            ProfScope ps(h, SAP_KERNEL_SPMV, s);
+            HIP_TRY(launch_spmv_multi(A, n, k, X, B, t, 0, m, s));
+        }
+        TRY(dots(h, OP_NORM, {{t, t}}, s, nullptr, bt));
+        TRY(sync_read(h, s, &nrm2, &brk));
+        for (int c = 0; c < m; ++c)
+            if (!((bt.frozen >> c) & 1)) loc[c].rel_resid_true = std::sqrt(slot(c, H_NRM2)) / bnorm[c];
+    }
+    return finish(code, code == SAP_OK ? "" : msg);
+}
+
+// Preconditioned conjugate gradient (Saad, Alg. 9.1), x0 = 0: the outer loop
+// for symmetric positive definite A.  r = b - A x is updated recursively in
+// FP64 and z = M^{-1} r uses the handle's preconditioner; one host round
+// trip per step reads ||r||^2.  When ||r|| <= tol ||b|| the true residual is
+// tested; if it fails, CG restarts from it.
+int krylov_cg(sap_handle h, const double *b, double *x, double tol, int32_t maxit, hipStream_t s,
+              sap_stats *st)
+{
+    if (!h->factored) return fail(SAP_ERR_STATE, "sap_factor has not been called");
+    if (!b || !x) return fail(SAP_ERR_INVALID, "null vector pointer");
+    if (!(tol > 0.0)) return fail(SAP_ERR_INVALID, "tol must be > 0");
+    if (maxit < 1) return fail(SAP_ERR_INVALID, "maxit must be >= 1");
+    const int64_t n = h->opt.n;
+    if ((const void *)b < (const void *)(x + n) && (const void *)x < (const void *)(b + n))
+        return fail(SAP_ERR_INVALID, "b and x overlap");
+    sap_stats loc{};
+    if (h->ev[3]) HIP_TRY(hipEventRecord(h->ev[3], s));
+    double *r = h->kvec(KV_R0), *z = h->kvec(KV_R1), *pv = h->kvec(KV_U0), *q = h->kvec(KV_U1);
+    double *t = h->kvec(KV_T);
+    const double *A = h->a_band;
+    const int k = h->opt.k;
+    double nrm2 = 0, brk = 0;
+    TRY(dots(h, OP_NORM, {{b, b}}, s, h->ptr<int>(h->L.status)));
+    TRY(sync_read(h, s, &nrm2, &brk));
+    loc.n_boosted = (int32_t)h->h_slots[H_NBOOST];
+    if (const int32_t singular = (int32_t)h->h_slots[H_SING]) {
+        if (st) *st = loc;
+        return fail(SAP_ERR_SINGULAR, singular == 1 ? "zero pivot in a diagonal block (boosting disabled)"
+                                                    : "singular reduced matrix Rbar");
+    }
+    const double bnorm = std::sqrt(nrm2);
+    HIP_TRY(launch_fill(x, 0.0, n, s));
+    int napply = 0, steps = 0;
+    auto finish = [&](int code, const char *msg) {
+        if (h->ev[4]) {
+            HIP_TRY(hipEventRecord(h->ev[4], s));
+            HIP_TRY(hipEventSynchronize(h->ev[4]));
+            HIP_TRY(hipEventElapsedTime(&loc.t_solve_ms, h->ev[3], h->ev[4]));
+        } else {
+            HIP_TRY(hipStreamSynchronize(s));
+        }
+        collect_factor_times(h);
+        loc.t_factor_ms = h->t_factor;
+        loc.t_lu_ms = h->t_lu;
+        loc.t_tips_ms = h->t_tips;
+        loc.iters = steps;
+        loc.n_apply = napply;
+        if (st) *st = loc;
+        if (code != SAP_OK && code != SAP_NOT_CONVERGED) return fail(code, msg);
+        if (code == SAP_NOT_CONVERGED) g_err = msg;
+        return code;
+    };
+    if (bnorm == 0.0) {
+        loc.converged = 1;
+        return finish(SAP_OK, "");
+    }
+    // r = b, z = M^{-1} r, p = z, rho = (r, z)
+    HIP_TRY(hipMemcpyAsync(r, b, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    TRY(precond(h, 0, r, z, s));
+    ++napply;
+    TRY(update(h, UPD_CG_INIT, x, OP_CG_INIT, 2, s));
+    int code = SAP_NOT_CONVERGED;
+    for (int32_t it = 0; it < maxit; ++it) {
+        {
+            ProfScope ps(h, SAP_KERNEL_SPMV, s);
+            HIP_TRY(launch_spmv(A, n, k, pv, nullptr, q, 0, s));        // q = A p
+        }
+        TRY(dots(h, OP_CG_ALPHA, {{pv, q}}, s));
+        TRY(update(h, UPD_CG_XR, x, OP_EXIT, 1, s));
+        ++steps;
+        TRY(sync_read(h, s, &nrm2, &brk));
+        if (brk != 0.0 || !std::isfinite(nrm2))
+            return finish(SAP_ERR_BREAKDOWN, "breakdown in CG (A or M not positive definite)");
+        loc.rel_resid_precond = std::sqrt(nrm2) / bnorm;
+        if (std::sqrt(nrm2) <= tol * bnorm) {
+            {
+                ProfScope ps(h, SAP_KERNEL_SPMV, s);
+                HIP_TRY(launch_spmv(A, n, k, x, b, t, 0, s));              // t = b - A x
+            }
+            TRY(dots(h, OP_NORM, {{t, t}}, s));
+            double tn2 = 0, b2 = 0;
+            TRY(sync_read(h, s, &tn2, &b2));
+            loc.rel_resid_true = std::sqrt(tn2) / bnorm;
+            if (loc.rel_resid_true <= tol) {
+                code = SAP_OK;
+                break;
+            }
+            HIP_TRY(hipMemcpyAsync(r, t, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+            TRY(precond(h, 0, r, z, s));
+            ++napply;
+            ++loc.restarts;
+            TRY(update(h, UPD_CG_INIT, x, OP_CG_INIT, 2, s));
+            continue;
+        }
+        TRY(precond(h, 0, r, z, s));
+        ++napply;
+        TRY(dots(h, OP_CG_BETA, {{r, z}}, s));
+        TRY(update(h, UPD_CG_P, x, 0, 0, s));
+    }
+    if (code == SAP_OK) {
+        loc.converged = 1;
+        return finish(SAP_OK, "");
+    }
+    {
+        ProfScope ps(h, SAP_KERNEL_SPMV, s);
+        HIP_TRY(launch_spmv(A, n, k, x, b, t, 0, s));
+    }
+    TRY(dots(h, OP_NORM, {{t, t}}, s));
+    double tn2 = 0;
+    TRY(sync_read(h, s, &tn2, &brk));
+    loc.rel_resid_true = std::sqrt(tn2) / bnorm;
+    return finish(SAP_NOT_CONVERGED, "maximum number of iterations reached");
+}
+
 template <typename T>
 int factor_t(sap_handle h, const double *a_band, hipStream_t s)
 {
@@ -628,32 +982,33 @@ int factor_t(sap_handle h, const double *a_band, hipStream_t s)
     lu.corner = h->coupled ? h->ptr<T>(h->L.corner) : nullptr;
     lu.status = h->ptr<int>(h->L.status);
     lu.with_ul = h->coupled ? 1 : 0;
+    lu.wide = h->L.lwin ? h->ptr<double>(h->L.lwin) : nullptr;
     {
         ProfScope ps(h, SAP_KERNEL_LU, s);
         HIP_TRY(launch_banded_lu<T>(lu, s));
     }
     // the transfer matrices of the chunked sweeps (sap_internal.h) depend only
     // on the factors: they run on the side stream beside the tips
-    const bool side = h->ck.nch >= 2 && h->coupled;
+    const bool side = h->ck.nch >= 2 && h->coupled && h->side;
     hipStream_t xs = side ? h->side : s;
     // ev[1] (the LU's end, for its time) also forks the side stream
-    HIP_TRY(hipEventRecord(h->ev[1], s));
+    if (h->ev[1]) HIP_TRY(hipEventRecord(h->ev[1], s));
     if (side) HIP_TRY(hipStreamWaitEvent(h->side, h->ev[1], 0));
     if (h->ck.nch >= 2) {
         if (!sweep_top_state_supported(h->opt.k))      // ring kernel: per-block tickets
-            HIP_TRY(hipMemsetAsync(h->ptr<unsigned>(h->L.ticket), 0, sizeof(unsigned) * h->opt.p, xs));
+            HIP_TRY(launch_zero(h->ptr<unsigned>(h->L.ticket), sizeof(unsigned) * h->opt.p, xs));
         struct Arr { T *F; size_t xf; int fwd, diag; };
         const Arr arrs[4] = {{lu.Lc, h->L.xLc, 1, 0}, {lu.Uc, h->L.xUc, 0, 1},
                              {lu.Ur, h->L.xUr, 1, 1}, {lu.Lr, h->L.xLr, 0, 0}};
         XferArgs<T> xa{};
         xa.pt = h->pt;
-        xa.scratch = h->ptr<T>(h->L.xscr);
+        xa.scratch = h->ptr<double>(h->L.xscr);
         xa.nch = h->ck.nch;
         xa.clen = h->ck.clen;
         for (const Arr &r : arrs) {
             if (!r.F) continue;
             xa.F[xa.narr] = r.F;
-            xa.xf[xa.narr] = h->ptr<T>(r.xf);
+            xa.xf[xa.narr] = h->ptr<double>(r.xf);
             xa.fwd[xa.narr] = r.fwd;
             xa.diag[xa.narr] = r.diag;
             ++xa.narr;
@@ -679,6 +1034,52 @@ int factor_t(sap_handle h, const double *a_band, hipStream_t s)
         HIP_TRY(hipEventRecord(h->join, h->side));
         HIP_TRY(hipStreamWaitEvent(s, h->join, 0));
     }
+    return SAP_OK;
+}
+
+// Host state of a handle over a carved workspace.  Allocates nothing; the
+// host result slots, events and side stream are added by sap_create.
+void init_handle(sap_handle h, const sap_options &o, unsigned char *ws, const Layout &L)
+{
+    h->opt = o;
+    h->coupled = coupled_active(o);
+    h->fp32 = o.factor_prec == SAP_PREC_FP32;
+    h->ws = ws;
+    h->L = L;
+    h->pt.n = o.n;
+    h->pt.k = o.k;
+    h->pt.p = o.p;
+    h->pt.maxnb = o.n / o.p + (o.n % o.p ? 1 : 0);
+    h->pt.starts = h->ptr<int64_t>(L.starts);
+    h->nchunk = norm_chunks(o);
+    h->ck = chunking_for(o);
+}
+
+int factor_impl(sap_handle h, const double *a_band, hipStream_t s)
+{
+    if (!h->starts_uploaded) {
+        // the partition of Sec. 3.1, and the zero slots after each factor
+        // row, which no kernel writes afterwards (fill kernels, not memset
+        // nodes, so that the sequence can be captured into a graph)
+        HIP_TRY(launch_partition_starts(h->ptr<int64_t>(h->L.starts), h->opt.n, h->opt.p, s));
+        const size_t fb = (h->fp32 ? 4 : 8) * (size_t)h->opt.n *
+                          coef_pitch(h->opt.k, h->fp32 ? 4 : 8);
+        for (size_t off : {h->L.Lc, h->L.Uc, h->L.Lr, h->L.Ur})
+            if (off) HIP_TRY(launch_zero(h->ws + off, fb, s));
+        h->starts_uploaded = true;
+    }
+    if (h->ev[0]) HIP_TRY(hipEventRecord(h->ev[0], s));
+    {
+        ProfScope ps(h, SAP_KERNEL_NORM, s);       // also zeroes the status words
+        HIP_TRY(launch_block_norm(a_band, h->pt, h->ptr<double>(h->L.partial), h->nchunk,
+                                  h->ptr<int>(h->L.status), s));
+    }
+    int rc = h->fp32 ? factor_t<float>(h, a_band, s) : factor_t<double>(h, a_band, s);
+    if (rc) return rc;
+    if (h->ev[2]) HIP_TRY(hipEventRecord(h->ev[2], s));
+    h->a_band = a_band;
+    h->factored = true;
+    h->t_factor = h->t_lu = h->t_tips = -1.0f;
     return SAP_OK;
 }
 
@@ -714,22 +1115,8 @@ int sap_create(const sap_options *opt, void *workspace, size_t ws_bytes, sap_han
                                          " bytes, got " + std::to_string(ws_bytes));
     sap_handle h = new (std::nothrow) sap_handle_();
     if (!h) return fail(SAP_ERR_INVALID, "out of host memory");
-    h->opt = *opt;
-    h->coupled = coupled_active(*opt);
-    h->fp32 = opt->factor_prec == SAP_PREC_FP32;
-    h->ws = static_cast<unsigned char *>(workspace);
-    h->L = L;
-    const int64_t n = opt->n;
-    const int p = opt->p;
-    h->pt.n = n;
-    h->pt.k = opt->k;
-    h->pt.p = p;
-    h->pt.maxnb = n / p + (n % p ? 1 : 0);
-    h->pt.starts = h->ptr<int64_t>(L.starts);
-    h->nchunk = norm_chunks(*opt);
-    h->ck = chunking_for(*opt);
+    init_handle(h, *opt, static_cast<unsigned char *>(workspace), L);
     auto cleanup = [&](int code, const std::string &m) {
-        if (h->h_starts) (void)hipHostFree(h->h_starts);
         if (h->h_slots) (void)hipHostFree(h->h_slots);
         if (h->h_status) (void)hipHostFree(h->h_status);
         for (auto &e : h->ev)
@@ -739,21 +1126,18 @@ int sap_create(const sap_options *opt, void *workspace, size_t ws_bytes, sap_han
         delete h;
         return fail(code, m);
     };
-    if (hipHostMalloc((void **)&h->h_starts, sizeof(int64_t) * (p + 1), hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc((void **)&h->h_slots, sizeof(double) * kHostSlots, hipHostMallocMapped) != hipSuccess ||
+    if (hipHostMalloc((void **)&h->h_slots, sizeof(double) * kHostSlots * rhs_cap(*opt),
+                      hipHostMallocMapped) != hipSuccess ||
         hipHostMalloc((void **)&h->h_status, 64, hipHostMallocDefault) != hipSuccess)
         return cleanup(SAP_ERR_HIP, "hipHostMalloc failed");
     if (hipHostGetDevicePointer((void **)&h->d_slots, h->h_slots, 0) != hipSuccess)
         return cleanup(SAP_ERR_HIP, "hipHostGetDevicePointer failed");
+    h->mapped = true;
     for (auto &e : h->ev)
         if (hipEventCreate(&e) != hipSuccess) return cleanup(SAP_ERR_HIP, "hipEventCreate failed");
     if (hipEventCreateWithFlags(&h->join, hipEventDisableTiming) != hipSuccess ||
         hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking) != hipSuccess)
         return cleanup(SAP_ERR_HIP, "creating the side stream failed");
-    // Sec. 3.1: first P_r = N - P*floor(N/P) blocks get floor(N/P) + 1 rows
-    const int64_t q = n / p, pr = n - (int64_t)p * q;
-    h->h_starts[0] = 0;
-    for (int i = 0; i < p; ++i) h->h_starts[i + 1] = h->h_starts[i] + q + (i < pr ? 1 : 0);
     *out = h;
     return SAP_OK;
 }
@@ -762,30 +1146,7 @@ int sap_factor(sap_handle h, const double *a_band, void *stream)
 {
     if (!h) return fail(SAP_ERR_INVALID, "null handle");
     if (!a_band) return fail(SAP_ERR_INVALID, "a_band is null");
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    if (!h->starts_uploaded) {
-        HIP_TRY(hipMemcpyAsync(h->ptr<int64_t>(h->L.starts), h->h_starts,
-                               sizeof(int64_t) * (h->opt.p + 1), hipMemcpyHostToDevice, s));
-        // the zero slots after each factor row are never written by a kernel
-        const size_t fb = (h->fp32 ? 4 : 8) * (size_t)h->opt.n *
-                          coef_pitch(h->opt.k, h->fp32 ? 4 : 8);
-        for (size_t off : {h->L.Lc, h->L.Uc, h->L.Lr, h->L.Ur})
-            if (off) HIP_TRY(hipMemsetAsync(h->ws + off, 0, fb, s));
-        h->starts_uploaded = true;
-    }
-    HIP_TRY(hipEventRecord(h->ev[0], s));
-    {
-        ProfScope ps(h, SAP_KERNEL_NORM, s);       // also zeroes the status words
-        HIP_TRY(launch_block_norm(a_band, h->pt, h->ptr<double>(h->L.partial), h->nchunk,
-                                  h->ptr<int>(h->L.status), s));
-    }
-    int rc = h->fp32 ? factor_t<float>(h, a_band, s) : factor_t<double>(h, a_band, s);
-    if (rc) return rc;
-    HIP_TRY(hipEventRecord(h->ev[2], s));
-    h->a_band = a_band;
-    h->factored = true;
-    h->t_factor = h->t_lu = h->t_tips = -1.0f;
-    return SAP_OK;
+    return factor_impl(h, a_band, static_cast<hipStream_t>(stream));
 }
 
 int sap_solve(sap_handle h, const double *b, double *x, double tol, int32_t maxit, void *stream,
@@ -800,6 +1161,20 @@ int sap_solve_adjoint(sap_handle h, const double *g, double *lambda, double tol,
 {
     if (!h) return fail(SAP_ERR_INVALID, "null handle");
     return krylov(h, 1, g, lambda, tol, maxit, static_cast<hipStream_t>(stream), st);
+}
+
+int sap_solve_batch(sap_handle h, const double *B, double *X, int32_t m, double tol,
+                    int32_t maxit, void *stream, sap_stats *st)
+{
+    if (!h) return fail(SAP_ERR_INVALID, "null handle");
+    return krylov_batch(h, B, X, m, tol, maxit, static_cast<hipStream_t>(stream), st);
+}
+
+int sap_solve_cg(sap_handle h, const double *b, double *x, double tol, int32_t maxit,
+                 void *stream, sap_stats *st)
+{
+    if (!h) return fail(SAP_ERR_INVALID, "null handle");
+    return krylov_cg(h, b, x, tol, maxit, static_cast<hipStream_t>(stream), st);
 }
 
 int sap_band_grad(sap_handle h, const double *lambda, const double *x, double *g_band,
@@ -868,6 +1243,36 @@ int sap_get_tips(sap_handle h, int32_t i, double *v, double *w, double *rbar, vo
     return SAP_OK;
 }
 
+int sap_get_factor_rows(sap_handle h, int32_t which, int64_t j0, int64_t count, double *out,
+                        void *stream)
+{
+    if (!h) return fail(SAP_ERR_INVALID, "null handle");
+    if (!h->factored) return fail(SAP_ERR_STATE, "sap_factor has not been called");
+    if (which < 0 || which > 3) return fail(SAP_ERR_INVALID, "which must be 0..3");
+    const size_t offs[4] = {h->L.Lc, h->L.Uc, h->L.Lr, h->L.Ur};
+    if (which >= 2 && !h->opt.adjoint)
+        return fail(SAP_ERR_STATE, "handle was created without adjoint = 1");
+    if (j0 < 0 || count < 0 || j0 + count > h->opt.n || (count > 0 && !out))
+        return fail(SAP_ERR_INVALID, "row range out of bounds");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const size_t sf = h->fp32 ? 4 : 8;
+    const int k = h->opt.k;
+    const int cp = coef_pitch(k, (int)sf);
+    std::vector<unsigned char> tmp((size_t)count * cp * sf);
+    if (count > 0) {
+        HIP_TRY(hipMemcpyAsync(tmp.data(), h->ws + offs[which] + (size_t)j0 * cp * sf, tmp.size(),
+                               hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+    }
+    for (int64_t r = 0; r < count; ++r)
+        for (int m = 0; m <= k; ++m) {
+            const size_t e = (size_t)r * cp + m;
+            out[r * (k + 1) + m] = h->fp32 ? (double)reinterpret_cast<float *>(tmp.data())[e]
+                                           : reinterpret_cast<double *>(tmp.data())[e];
+        }
+    return SAP_OK;
+}
+
 int sap_profile(sap_handle h, int32_t enable)
 {
     if (!h) return fail(SAP_ERR_INVALID, "null handle");
@@ -905,9 +1310,10 @@ int sap_destroy(sap_handle h)
 {
     if (!h) return SAP_OK;
     for (auto &e : h->pev) (void)hipEventDestroy(e);
-    (void)hipHostFree(h->h_starts);
-    (void)hipHostFree(h->h_slots);
-    (void)hipHostFree(h->h_status);
+    if (h->mapped) {
+        (void)hipHostFree(h->h_slots);
+        (void)hipHostFree(h->h_status);
+    }
     for (auto &e : h->ev)
         if (e) (void)hipEventDestroy(e);
     if (h->side) {

@@ -34,6 +34,8 @@ namespace sap {
 constexpr int kMaxK = 255;
 constexpr size_t kMaxLds = 160 * 1024;    // LDS bytes per workgroup on gfx950
 constexpr int kDotBlocks = 512;   // fixed grid of the reduction kernels
+constexpr int kMultiRhs = 4;      // right-hand sides per workgroup in multi-RHS kernels
+constexpr int kMaxRhs = 64;       // right-hand sides per batched solve
 
 // row pitch (entries) of the factor coefficient arrays: K + 1 coefficients,
 // at least one zero, rounded up to a multiple of 16 bytes
@@ -54,6 +56,10 @@ enum KrylovOp : int {
     OP_NORM,       // d0=(v,v): publish only
     OP_TRUE,       // d0=(t,t): the true residual at a restart, to host slot H_TRUE
     OP_SPEC,       // d0=(t,t): the true residual ahead of an exit test, to H_SPEC
+    // preconditioned conjugate gradient (SPD A)
+    OP_CG_INIT,    // d0=(r,z) d1=(r,r): rho = (r,z), publish ||r||^2
+    OP_CG_ALPHA,   // d0=(p,Ap): alpha = rho / (p,Ap), breakdown unless > 0
+    OP_CG_BETA,    // d0=(r,z): beta = (r,z) / rho, rho = (r,z)
 };
 
 // device scalar slots of the BiCGStab(2) recurrences (double sc[kScalars])
@@ -94,6 +100,7 @@ struct LuArgs {
     T *corner;               // [p][K*K], UL direction only (may be null)
     int *status;             // [0] boosted pivots, [1] singular flag
     int with_ul;             // grid = 2P: blocks >= P run the UL direction
+    double *wide;            // FP64 K > 160: one window slab per workgroup
 };
 template <typename T>
 hipError_t launch_banded_lu(const LuArgs<T> &a, hipStream_t s);
@@ -101,6 +108,11 @@ hipError_t launch_banded_lu(const LuArgs<T> &a, hipStream_t s);
 template <typename T>
 hipError_t launch_lu_mfma(const LuArgs<T> &a, hipStream_t s);
 bool lu_mfma_supported(int k, bool fp32);
+// FP64 factors of bands wider than the register windows (K > 160): the
+// window in a workspace slab of lu_wide_window_bytes(K) per workgroup
+constexpr int kLuWideMinK = 161;
+size_t lu_wide_window_bytes(int k);
+hipError_t launch_lu_wide(const LuArgs<double> &a, double *slabs, hipStream_t s);
 
 template <typename T>
 struct TipsArgs {
@@ -134,8 +146,11 @@ hipError_t launch_tips(const TipsArgs<T> &a, hipStream_t s);
 // first chunk (K <= 56: every workgroup for its own chunk, at its start;
 // larger K: the last phase-1 workgroup of each block, through st) and
 // reruns the chunk from it, writing the outputs.
-// Storage: q, st [p][nch][K]; X [p][nch][K][K] with X[c][i][m] = d p_out[m]
-// / d p_in[i] (row i contiguous in m); ticket [p] (zero between launches).
+// Storage: q (type T), st (FP64) [p][nch][K]; X (FP64) [p][nch][K][K] with
+// X[c][i][m] = d p_out[m] / d p_in[i] (row i contiguous in m); ticket [p]
+// (zero between launches).  The states are chained in FP64 for either factor
+// precision: with weak diagonal dominance the transfer matrices and the two
+// terms of a link can exceed the state they form by orders of magnitude.
 enum SweepPhase : int { SWEEP_WHOLE = 0, SWEEP_ZERO_STATE = 1, SWEEP_FROM_STATE = 2 };
 
 template <typename T>
@@ -150,14 +165,20 @@ struct SweepArgs {
     T *tout;
     int phase;               // SweepPhase
     int nch, clen;           // chunks per block (grid p*nch), rows per chunk
-    T *q, *st;
-    const T *xf;
+    T *q;                    // zero-state outgoing states [p][nch][K]
+    double *st;              // chained entering states [p][nch][K] (FP64)
+    const double *xf;        // transfer matrices (FP64 for either precision)
     unsigned *ticket;
     // From-state pass of a forward sweep (K <= 56): dtop enters as the
     // incoming state -dtop of each block's first chunk instead of being added
     // to its first K inputs (the same sums), so the zero-state pass of an
     // earlier sweep of the same input without dtop supplies q.
     int top_as_state;
+    // right-hand sides (columns of xin/tin/dout/tout with leading dimension
+    // ldv; dtop/dbot, q and st hold one slab per column).  m > 1 needs
+    // K <= 56 (the circular kernels).
+    int m;
+    int64_t ldv;
 };
 template <typename T>
 hipError_t launch_sweep(const SweepArgs<T> &a, hipStream_t s);
@@ -172,9 +193,9 @@ struct XferArgs {
     int nch, clen;
     int narr;
     const T *F[4];
-    T *xf[4];
+    double *xf[4];           // FP64 whatever T is
     int fwd[4], diag[4];
-    T *scratch;              // [narr][p][nch][2][K][K]: partial transfers X_2, X_3
+    double *scratch;         // [narr][p][nch][2][K][K]: partial transfers X_2, X_3
 };
 template <typename T>
 hipError_t launch_sweep_xfer(const XferArgs<T> &a, hipStream_t s);
@@ -191,6 +212,8 @@ struct CorrArgs {
     const T *B, *C, *V, *W, *Rinv;
     T *dtop, *dbot;
     int trans;
+    int m;                   // right-hand sides: g columns ld ldg apart,
+    int64_t ldg;             // dtop/dbot one [p][K] slab per column
 };
 template <typename T>
 hipError_t launch_correction(const CorrArgs<T> &a, hipStream_t s);
@@ -199,6 +222,10 @@ hipError_t launch_correction(const CorrArgs<T> &a, hipStream_t s);
 // y = A v (trans 0) or A^T v; if b != null: y = b - A v (residual form).
 hipError_t launch_spmv(const double *band, int64_t n, int k, const double *v,
                        const double *b, double *y, int trans, hipStream_t s);
+// the same for m column-major right-hand sides (leading dimension n), read
+// band entries serving kMultiRhs columns at once
+hipError_t launch_spmv_multi(const double *band, int64_t n, int k, const double *v,
+                             const double *b, double *y, int trans, int m, hipStream_t s);
 hipError_t launch_band_grad(int64_t n, int k, const double *lam,
                             const double *x, double *g, hipStream_t s);
 
@@ -213,6 +240,13 @@ struct DotArgs {
     double *host;            // mapped pinned host slots (may be null)
     const int *status;       // if set, copied to host slots H_NBOOST, H_SING
     int op;
+    // several right-hand sides: column c of every vector at c * ld; its
+    // partials at partial + c*kDotBlocks*3, scalars at sc + c*kScalars, host
+    // slots at host + c*kHostSlots; frozen columns (bit c, c < 64) are left
+    // alone.  m = 0 means 1.
+    int m;
+    int64_t ld;
+    uint64_t frozen;
 };
 hipError_t launch_dots(const DotArgs &a, hipStream_t s);
 
@@ -227,6 +261,10 @@ enum UpdKind : int {
     UPD_FINAL,       // x += g1 r0 + gpp1 r1; r0 -= gp2 r2 + gp1 r1;
                      // u0 -= g2 u2 + g1 u1
     UPD_RESTART,     // rt = r0; u0 = 0
+    // conjugate gradient: r = r0, z = r1, p = u0, q = A p = u1
+    UPD_CG_INIT,     // p = z; dots (r,z), (r,r)
+    UPD_CG_XR,       // x += alpha p; r -= alpha q; dot (r,r)
+    UPD_CG_P,        // p = z + beta p
 };
 struct UpdArgs {
     int kind;
@@ -237,5 +275,7 @@ struct UpdArgs {
 hipError_t launch_update(const UpdArgs &a, hipStream_t s);
 
 hipError_t launch_fill(double *v, double val, int64_t n, hipStream_t s);
+hipError_t launch_zero(void *p, size_t bytes, hipStream_t s);   // bytes % 4 == 0
+hipError_t launch_partition_starts(int64_t *starts, int64_t n, int p, hipStream_t s);
 
 }  // namespace sap

@@ -34,7 +34,8 @@ SAP_PREC_FP32 = 1
 EXPORTED = ("sap_workspace_bytes", "sap_create", "sap_factor", "sap_solve",
             "sap_solve_adjoint", "sap_band_grad", "sap_handle_status", "sap_spmv",
             "sap_precond_apply", "sap_get_tips", "sap_profile", "sap_kernel_time",
-            "sap_destroy", "sap_last_error")
+            "sap_destroy", "sap_last_error", "sap_solve_cg", "sap_solve_batch",
+            "sap_get_factor_rows")
 
 KERNELS = ("norm", "lu", "tips", "sweep", "corr", "spmv", "krylov", "xfer")
 
@@ -53,7 +54,7 @@ class sap_options(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("k", ctypes.c_int32), ("p", ctypes.c_int32),
                 ("mode", ctypes.c_int32), ("factor_prec", ctypes.c_int32),
                 ("boost_eps", ctypes.c_double), ("adjoint", ctypes.c_int32),
-                ("sweep_chunks", ctypes.c_int32)]
+                ("sweep_chunks", ctypes.c_int32), ("nrhs", ctypes.c_int32)]
 
 
 class sap_stats(ctypes.Structure):
@@ -87,11 +88,14 @@ def load_library(path: str = LIB_PATH):
     lib.sap_factor.argtypes = [vp, vp, vp]
     lib.sap_solve.argtypes = [vp, vp, vp, dbl, i32, vp, P(sap_stats)]
     lib.sap_solve_adjoint.argtypes = [vp, vp, vp, dbl, i32, vp, P(sap_stats)]
+    lib.sap_solve_cg.argtypes = [vp, vp, vp, dbl, i32, vp, P(sap_stats)]
+    lib.sap_solve_batch.argtypes = [vp, vp, vp, i32, dbl, i32, vp, P(sap_stats)]
     lib.sap_band_grad.argtypes = [vp, vp, vp, vp, vp]
     lib.sap_handle_status.argtypes = [vp, vp, P(i32)]
     lib.sap_spmv.argtypes = [vp, vp, vp, i32, vp]
     lib.sap_precond_apply.argtypes = [vp, vp, vp, i32, vp]
     lib.sap_get_tips.argtypes = [vp, i32, vp, vp, vp, vp]
+    lib.sap_get_factor_rows.argtypes = [vp, i32, i64, i64, vp, vp]
     lib.sap_profile.argtypes = [vp, i32]
     lib.sap_kernel_time.argtypes = [vp, i32, P(dbl), P(i64)]
     lib.sap_destroy.argtypes = [vp]
@@ -121,11 +125,11 @@ def _stream() -> ctypes.c_void_p:
 
 def make_options(n: int, k: int, p: int, mode: str = "coupled", factor_prec: str = "fp64",
                  boost_eps: float = 0.0, adjoint: bool = False,
-                 sweep_chunks: int = 0) -> sap_options:
+                 sweep_chunks: int = 0, nrhs: int = 0) -> sap_options:
     m = {"decoupled": SAP_DECOUPLED, "coupled": SAP_COUPLED}[mode]
     f = {"fp64": SAP_PREC_FP64, "fp32": SAP_PREC_FP32}[factor_prec]
     return sap_options(n=n, k=k, p=p, mode=m, factor_prec=f, boost_eps=boost_eps,
-                       adjoint=1 if adjoint else 0, sweep_chunks=sweep_chunks)
+                       adjoint=1 if adjoint else 0, sweep_chunks=sweep_chunks, nrhs=nrhs)
 
 
 # ------------------------------------------------------------ thin wrappers
@@ -157,9 +161,11 @@ class SapSolver:
 
     def __init__(self, n: int, k: int, p: int, mode: str = "coupled",
                  factor_prec: str = "fp64", boost_eps: float = 0.0, adjoint: bool = False,
-                 device=None, sweep_chunks: int = 0):
+                 device=None, sweep_chunks: int = 0, nrhs: int = 0):
         lib = load_library()
-        self.opt = make_options(n, k, p, mode, factor_prec, boost_eps, adjoint, sweep_chunks)
+        self.opt = make_options(n, k, p, mode, factor_prec, boost_eps, adjoint, sweep_chunks,
+                                nrhs)
+        self.nrhs = max(1, nrhs)
         self.n, self.k, self.p = n, k, p
         nbytes = sap_workspace_bytes(self.opt)
         dev = torch.device("cuda") if device is None else torch.device(device)
@@ -169,6 +175,7 @@ class SapSolver:
                               nbytes, ctypes.byref(h)))
         self.handle = h
         self.a_band = None
+        self.generation = 0          # bumped by every factor(): which A the factors belong to
 
     # -- life cycle --
     def close(self):
@@ -189,6 +196,7 @@ class SapSolver:
                                          _dptr(a_band, (2 * self.k + 1) * self.n, "a_band"),
                                          _stream()))
         self.a_band = a_band
+        self.generation += 1
 
     def _solve(self, fn, b, x, tol, maxit, raise_nc):
         st = sap_stats()
@@ -202,6 +210,28 @@ class SapSolver:
               maxit: int = 200, raise_nc: bool = False):
         x = torch.empty_like(b) if x is None else x
         return x, self._solve(load_library().sap_solve, b, x, tol, maxit, raise_nc)
+
+    def solve_batch(self, B: torch.Tensor, X: torch.Tensor | None = None, tol: float = 1e-10,
+                    maxit: int = 200, raise_nc: bool = False):
+        """sap_solve_batch: B is (m, N) (row c = right-hand side c, contiguous),
+        i.e. the N x m column-major block of the C ABI.  Returns (X, [SapStats])."""
+        if B.dim() != 2 or B.shape[1] != self.n:
+            raise ValueError("B must be (m, N)")
+        m = B.shape[0]
+        X = torch.empty_like(B) if X is None else X
+        sts = (sap_stats * m)()
+        rc = load_library().sap_solve_batch(self.handle, _dptr(B, m * self.n, "B"),
+                                            _dptr(X, m * self.n, "X"), m, float(tol), int(maxit),
+                                            _stream(), sts)
+        if rc not in (SAP_OK, SAP_NOT_CONVERGED) or (rc == SAP_NOT_CONVERGED and raise_nc):
+            _check(rc)
+        return X, [SapStats(**st.as_dict(), status=rc) for st in sts]
+
+    def solve_cg(self, b: torch.Tensor, x: torch.Tensor | None = None, tol: float = 1e-10,
+                 maxit: int = 500, raise_nc: bool = False):
+        """sap_solve_cg: preconditioned conjugate gradient for SPD A."""
+        x = torch.empty_like(b) if x is None else x
+        return x, self._solve(load_library().sap_solve_cg, b, x, tol, maxit, raise_nc)
 
     def solve_adjoint(self, g: torch.Tensor, lam: torch.Tensor | None = None,
                       tol: float = 1e-10, maxit: int = 200, raise_nc: bool = False):
@@ -248,6 +278,17 @@ class SapSolver:
             out[name] = (ms.value, cnt.value)
         return out
 
+    def factor_rows(self, which: str, j0: int = 0, count: int | None = None):
+        """Rows of a factor coefficient array ("Lc", "Uc", "Lr", "Ur") as a
+        (count, K+1) float64 array (sap_get_factor_rows)."""
+        import numpy as np
+        w = {"Lc": 0, "Uc": 1, "Lr": 2, "Ur": 3}[which]
+        count = self.n - j0 if count is None else count
+        out = np.zeros((count, self.k + 1))
+        _check(load_library().sap_get_factor_rows(self.handle, w, j0, count,
+                                                  out.ctypes.data_as(ctypes.c_void_p), _stream()))
+        return out
+
     def tips(self, i: int):
         import numpy as np
         kk = self.k * self.k
@@ -261,7 +302,12 @@ class SapSolver:
 class SapSolve(torch.autograd.Function):
     """x = A^{-1} b with A in band layout.  Backward: lambda = A^{-T} dL/dx by
     the adjoint solve on the same factors; dL/db = lambda and dL/dA_band =
-    band(-lambda x^T)."""
+    band(-lambda x^T).
+
+    The band is saved for backward (autograd then rejects an in-place change
+    to it).  If the solver has factored another matrix since this forward,
+    backward factors the saved band again before the adjoint solve, so the
+    gradient always belongs to the A of its own forward."""
 
     @staticmethod
     def forward(ctx, a_band, b, solver: SapSolver, tol: float = 1e-10, maxit: int = 200):
@@ -269,12 +315,16 @@ class SapSolve(torch.autograd.Function):
         x, st = solver.solve(b, tol=tol, maxit=maxit, raise_nc=True)
         ctx.solver, ctx.tol, ctx.maxit = solver, tol, maxit
         ctx.stats = st
-        ctx.save_for_backward(x)
+        ctx.generation = solver.generation
+        ctx.save_for_backward(a_band, x)
         return x
 
     @staticmethod
     def backward(ctx, gx):
-        (x,) = ctx.saved_tensors
+        a_band, x = ctx.saved_tensors
+        if ctx.solver.generation != ctx.generation:
+            ctx.solver.factor(a_band)
+            ctx.generation = ctx.solver.generation
         lam, _ = ctx.solver.solve_adjoint(gx.contiguous(), tol=ctx.tol, maxit=ctx.maxit,
                                           raise_nc=True)
         ga = ctx.solver.band_grad(lam, x) if ctx.needs_input_grad[0] else None

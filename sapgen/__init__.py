@@ -22,6 +22,12 @@ and Sec. 4.1):
   off-diagonals) a[r, r] = s_r * d;
 * optional row scaling: row r multiplied by 10**(2*u_r), u_r from stream 3,
   applied after the diagonal is set (so every row keeps its dominance d);
+* symmetric variant (the SPD workload of the conjugate-gradient outer
+  loop): a[r, c] = a[c, r] is the stream-0 draw of the lower entry,
+  index max(r,c)*(2K+1) + (min(r,c) - max(r,c) + K), and the diagonal is
+  +d * sum_{c != r} |a[r, c]| (no random sign): with d > 1 the matrix is
+  symmetric and strictly diagonally dominant with a positive diagonal,
+  hence positive definite;
 * x_true ~ U[-1, 1) from stream 2; b = A x_true;
 * x_target ~ N(0, 1) from stream 4 by the Box-Muller transform.
 
@@ -118,8 +124,10 @@ class BandedProblem:
 
 def make_problem(n: int, k: int, d: float = 1.0, seed: int = 0,
                  row_scale_decades: float = 0.0, pad: float = 0.0,
-                 with_rhs: bool = True) -> BandedProblem:
+                 with_rhs: bool = True, symmetric: bool = False) -> BandedProblem:
     """Build A (band layout), x_true and b = A x_true for one workload."""
+    if symmetric and row_scale_decades > 0.0:
+        raise ValueError("row scaling would break the symmetry")
     if n < 1 or k < 0 or k >= n:
         raise ValueError("need n >= 1 and 0 <= k < n")
     w = 2 * k + 1
@@ -132,13 +140,19 @@ def make_problem(n: int, k: int, d: float = 1.0, seed: int = 0,
             continue
         c = cols[max(0, -delta):n - max(0, delta)]
         r = c + delta
-        vals = splitmix64_uniform(seed, STREAM_OFFDIAG,
-                                  (r * w + (c - r + k)).astype(np.uint64))
+        if symmetric:          # the draw of the lower entry (max(r,c), min(r,c))
+            hi, lo = np.maximum(r, c), np.minimum(r, c)
+            idx = hi * w + (lo - hi + k)
+        else:
+            idx = r * w + (c - r + k)
+        vals = splitmix64_uniform(seed, STREAM_OFFDIAG, idx.astype(np.uint64))
         band[q, c] = vals
         rowabs[r] += np.abs(vals)
     sign = np.where(splitmix64_uniform(seed, STREAM_SIGN,
                                        np.arange(n, dtype=np.uint64)) < 0.0,
                     -1.0, 1.0)
+    if symmetric:
+        sign = np.ones(n)
     band[k, :] = sign * d * (rowabs if k > 0 else 1.0)
     scale = None
     if row_scale_decades > 0.0:
@@ -198,4 +212,13 @@ WORKLOADS = {
     "sapc_n200k_k100_weak": dict(n=200_000, k=100, d=0.1, p=64, mode="coupled",
                                  factor_prec="fp32", tol=1e-8,
                                  row_scale_decades=2.0),
+}
+
+# Symmetric positive definite workloads for the conjugate-gradient outer loop
+# (not among the five benchmark configurations): the benchmark's size and
+# band with a symmetric, strictly dominant matrix.
+SPD_WORKLOADS = {
+    "spd_n200k_k50": dict(n=200_000, k=50, d=1.05, p=64, mode="decoupled",
+                          factor_prec="fp64", tol=1e-10, row_scale_decades=0.0,
+                          symmetric=True),
 }

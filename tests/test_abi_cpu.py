@@ -47,7 +47,6 @@ def ws(lib, **kw):
     (dict(n=100, k=2, p=0), "P must be"),
     (dict(n=100, k=2, p=101), "P must be"),
     (dict(n=100, k=10, p=6, mode="coupled"), "floor(N/P) >= 2K"),
-    (dict(n=10000, k=161, p=4, factor_prec="fp64"), "FP64 factors"),
 ])
 def test_invalid_options(lib, kw, msg):
     rc, _, err = ws(lib, **kw)
@@ -90,3 +89,20 @@ def test_null_handle_calls_fail_cleanly(lib):
     assert lib.sap_factor(None, None, None) == binding.SAP_ERR_INVALID
     assert lib.sap_solve(None, None, None, 1e-10, 10, None, None) == binding.SAP_ERR_INVALID
     assert lib.sap_destroy(None) == 0
+
+
+def test_workspace_too_small_is_nospace(lib):
+    """sap_create checks the workspace size before it touches the device:
+    a too-small workspace returns SAP_ERR_NOSPACE and no handle."""
+    opt = binding.make_options(n=20_000, k=10, p=8, mode="coupled")
+    need = ctypes.c_size_t(0)
+    assert lib.sap_workspace_bytes(ctypes.byref(opt), ctypes.byref(need)) == 0
+    h = ctypes.c_void_p(1234)
+    fake = ctypes.c_void_p(1 << 20)               # 256-byte aligned, never dereferenced
+    rc = lib.sap_create(ctypes.byref(opt), fake, need.value - 1, ctypes.byref(h))
+    assert rc == binding.SAP_ERR_NOSPACE
+    assert "workspace too small" in lib.sap_last_error().decode()
+    assert not h.value
+    rc = lib.sap_create(ctypes.byref(opt), ctypes.c_void_p((1 << 20) + 8), need.value,
+                        ctypes.byref(h))
+    assert rc == binding.SAP_ERR_INVALID and "aligned" in lib.sap_last_error().decode()

@@ -1,0 +1,111 @@
+"""Conjugate-gradient outer loop (sap_solve_cg) for symmetric positive
+definite A, through the C ABI, against the oracle: the solution against the
+FP64 direct solve, element by element; the number of CG steps against the
+oracle's CG (FP64 preconditioner: same step or a neighbour); the special
+cases (exact preconditioner: one step; an indefinite direction: breakdown)."""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import sapgen
+
+pytestmark = pytest.mark.gpu
+
+DEV = torch.device("cuda:0")
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64)).to(DEV)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def solver(n, k, p, **kw):
+    from paper_1509_07919_amd import SapSolver
+    return SapSolver(n, k, p, device=DEV, **kw)
+
+
+def close(z, ref, tol):
+    assert np.abs(z - ref).max() <= tol * np.abs(ref).max()
+    assert np.linalg.norm(z - ref) <= tol * np.linalg.norm(ref)
+
+
+CG_CASES = [
+    # n, k, p, mode, prec, d
+    (20000, 20, 16, "decoupled", "fp64", 1.05),
+    (20000, 20, 16, "decoupled", "fp32", 1.05),
+    (30011, 45, 24, "decoupled", "fp64", 1.01),
+    (12000, 8, 12, "coupled", "fp64", 1.2),
+    (9000, 70, 9, "decoupled", "fp32", 1.1),
+]
+
+
+@pytest.mark.parametrize("n,k,p,mode,prec,d", CG_CASES)
+def test_cg_parity(n, k, p, mode, prec, d):
+    print("CASE cg", n, k, p, mode, prec, d, flush=True)
+    pb = sapgen.make_problem(n, k, d=d, seed=55, symmetric=True)
+    s = solver(n, k, p, mode=mode, factor_prec=prec)
+    s.factor(dev(pb.band))
+    x, st = s.solve_cg(dev(pb.b), tol=1e-10, maxit=500)
+    x = host(x)
+    assert st.converged and st.rel_resid_true <= 1e-10
+    r = pb.b - oracle.bandmv(pb.band, n, k, x)
+    assert np.linalg.norm(r) <= 1.0001e-10 * np.linalg.norm(pb.b)
+    close(x, oracle.solve_direct(pb.band, n, k, pb.b), 1e-8)
+    if prec == "fp64":
+        _, ref, _ = oracle.sap_solve_cg(pb.band, n, k, pb.b, p, mode == "coupled",
+                                        tol=1e-10, maxit=500)
+        assert ref.converged and abs(st.iters - ref.iters) <= 1, (st.iters, ref.iters)
+    s.close()
+
+
+def test_cg_spd_workload_full_size():
+    """N=200k, K=50, P=64 (the benchmark's size), symmetric with d = 1.05,
+    SaP-D with FP64 factors."""
+    cfg = sapgen.SPD_WORKLOADS["spd_n200k_k50"]
+    n, k, p = cfg["n"], cfg["k"], cfg["p"]
+    print("CASE cg full", flush=True)
+    pb = sapgen.make_problem(n, k, d=cfg["d"], seed=0, symmetric=True)
+    for prec in ("fp64", "fp32"):
+        s = solver(n, k, p, mode=cfg["mode"], factor_prec=prec)
+        s.factor(dev(pb.band))
+        x, st = s.solve_cg(dev(pb.b), tol=cfg["tol"], maxit=500)
+        x = host(x)
+        assert st.converged
+        close(x, pb.x_true, 1e-8)
+        s.close()
+    close(x, oracle.solve_direct(pb.band, n, k, pb.b), 1e-8)
+
+
+def test_cg_exact_preconditioner_one_step():
+    n, k = 5000, 9
+    print("CASE cg exact", flush=True)
+    pb = sapgen.make_problem(n, k, d=1.1, seed=56, symmetric=True)
+    s = solver(n, k, 1, mode="decoupled", factor_prec="fp64")
+    s.factor(dev(pb.band))
+    x, st = s.solve_cg(dev(pb.b), tol=1e-12)
+    assert st.converged and st.iters == 1.0 and st.restarts == 0
+    close(host(x), pb.x_true, 1e-12)
+    s.close()
+
+
+def test_cg_breakdown_on_indefinite_matrix():
+    """A = diag(1, -1), b = (1, 1), exact preconditioner: p = (1, -1) and
+    p^T A p = 0, a breakdown of CG (the oracle breaks down too)."""
+    from paper_1509_07919_amd import SapError, sap
+    print("CASE cg breakdown", flush=True)
+    band = np.array([1.0, -1.0])
+    with pytest.raises(oracle.Breakdown):
+        oracle.cg(lambda v: oracle.bandmv(band, 2, 0, v),
+                  oracle.SapPrecond(band, 2, 0, 1, False).apply, np.ones(2))
+    s = solver(2, 0, 1, mode="decoupled", factor_prec="fp64")
+    s.factor(dev(band))
+    with pytest.raises(SapError) as e:
+        s.solve_cg(dev(np.ones(2)), tol=1e-10, maxit=5)
+    assert e.value.code == sap.SAP_ERR_BREAKDOWN
+    s.close()

@@ -42,6 +42,20 @@ def rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
+def assert_close(z, ref, tol, what=""):
+    """Element by element: |z - ref| <= tol * max|ref| for every entry (a
+    block-boundary entry cannot hide in a norm), and the 2-norm relative
+    error <= tol as well."""
+    z, ref = np.asarray(z).reshape(-1), np.asarray(ref).reshape(-1)
+    assert z.shape == ref.shape, what
+    scale = max(float(np.abs(ref).max()), 1e-300)
+    err = np.abs(z - ref)
+    worst = int(np.argmax(err))
+    assert err[worst] <= tol * scale, "%s: entry %d off by %.3e (tol %.1e x max|ref| %.3e)" % (
+        what, worst, err[worst], tol, scale)
+    assert rel(z, ref) <= tol, "%s: norm-wise %.3e > %.1e" % (what, rel(z, ref), tol)
+
+
 def case(*a):
     print("CASE", *a, flush=True)
 
@@ -90,23 +104,25 @@ def test_precond_parity(n, k, p, mode, prec):
     z = host(s.precond(dev(r)))
     zt = host(s.precond(dev(r), trans=True))
     tol = 1e-12 if prec == "fp64" else 2e-5
-    assert rel(z, M.apply(r)) <= tol
-    assert rel(zt, M.apply_t(r)) <= tol
+    assert_close(z, M.apply(r), tol, "z")
+    assert_close(zt, M.apply_t(r), tol, "zt")
     rc, nb = s.status()
     assert rc == 0 and nb == M.n_boosted
     s.close()
 
 
 # wide bands: the matrix-core blocked LU (K >= 64; several window sizes, a
-# partial last panel), the register-ring LU (FP64 97..127, FP32 > 208) and
-# the global-memory tips kernel (when the LDS one does not fit: FP64 K >= 71,
-# where its static arrays tip the total over 160 KB)
+# partial last panel), the register-ring LU (FP64 97..127, FP32 > 208), the
+# FP64 LU with its window in a workspace slab (K > 160) and the global-memory
+# tips kernel (when the LDS one does not fit: FP64 K >= 71, where its static
+# arrays tip the total over 160 KB)
 WIDE_CASES = [
     (4001, 58, 4, "fp64"), (4001, 62, 4, "fp32"), (4001, 64, 4, "fp32"),
     (4001, 64, 4, "fp64"), (4501, 71, 4, "fp64"), (5003, 96, 5, "fp64"),
     (5003, 100, 5, "fp32"), (6007, 127, 5, "fp64"), (6007, 128, 5, "fp64"),
     (6007, 150, 7, "fp32"), (6400, 160, 8, "fp64"), (6400, 200, 8, "fp32"),
-    (6400, 208, 8, "fp32"), (7001, 255, 6, "fp32"),
+    (6400, 208, 8, "fp32"), (7001, 255, 6, "fp32"), (6400, 161, 8, "fp64"),
+    (6400, 200, 8, "fp64"), (6400, 208, 8, "fp64"), (7001, 255, 6, "fp64"),
 ]
 
 
@@ -120,11 +136,11 @@ def test_wide_band_precond(n, k, p, prec):
     s.factor(dev(pb.band))
     r = sapgen.splitmix64_uniform(6, 7, np.arange(n))
     tol = 1e-12 if prec == "fp64" else 2e-5
-    assert rel(host(s.precond(dev(r))), M.apply(r)) <= tol
-    assert rel(host(s.precond(dev(r), trans=True)), M.apply_t(r)) <= tol
+    assert_close(host(s.precond(dev(r))), M.apply(r), tol, "host(s.precond(dev(r)))")
+    assert_close(host(s.precond(dev(r), trans=True)), M.apply_t(r), tol, "host(s.precond(dev(r), trans=T")
     v, w, rb = s.tips(p - 2)
-    assert rel(v, M.V[p - 2]) <= 10 * tol
-    assert rel(w, M.W[p - 2]) <= 10 * tol
+    assert_close(v, M.V[p - 2], 10 * tol, "v")
+    assert_close(w, M.W[p - 2], 10 * tol, "w")
     rc, nbst = s.status()
     assert rc == 0 and nbst == M.n_boosted
     s.close()
@@ -162,8 +178,8 @@ def test_chunked_sweeps(n, k, p, mode, chunks, prec):
         z1 = host(one.precond(dev(r), trans=trans))
         zc = host(many.precond(dev(r), trans=trans))
         want = M.apply_t(r) if trans else M.apply(r)
-        assert rel(zc, want) <= tol
-        assert rel(zc, z1) <= tol
+        assert_close(zc, want, tol, "zc")
+        assert_close(zc, z1, tol, "zc")
     # twice in a row: the per-block tickets must be back at zero
     zc2 = host(many.precond(dev(r)))
     assert np.array_equal(zc2, host(many.precond(dev(r))))
@@ -183,9 +199,9 @@ def test_tips_parity(prec):
     tol = 1e-11 if prec == "fp64" else 5e-5
     for i in (0, 4, p - 2):
         v, w, rb = s.tips(i)
-        assert rel(v, M.V[i]) <= tol
-        assert rel(w, M.W[i]) <= tol
-        assert rel(rb, M.Rbar[i]) <= tol
+        assert_close(v, M.V[i], tol, "v")
+        assert_close(w, M.W[i], tol, "w")
+        assert_close(rb, M.Rbar[i], tol, "rb")
     s.close()
 
 
@@ -201,6 +217,8 @@ SOLVE_CASES = [
     (30000, 70, 60, "coupled", "fp32", 1.0, 1e-10, 1e-8),
     (30000, 70, 60, "coupled", "fp64", 1.0, 1e-10, 1e-8),
     (8000, 12, 16, "coupled", "fp64", 0.1, 1e-10, 1e-6),
+    (16000, 30, 20, "coupled", "fp64", 0.3, 1e-10, 1e-8),
+    (16000, 30, 20, "decoupled", "fp64", 0.5, 1e-10, 1e-8),
 ]
 
 
@@ -217,13 +235,27 @@ def test_solve_parity(n, k, p, mode, prec, d, tol, err_tol):
     assert st.iters == int(round(st.iters * 4)) / 4.0
     r = pb.b - oracle.bandmv(pb.band, n, k, x)
     assert np.linalg.norm(r) / np.linalg.norm(pb.b) <= tol * 1.0001
-    assert rel(x, xr) <= err_tol
+    assert_close(x, xr, err_tol, "x")
+    if prec == "fp64":
+        # the same method in the oracle exits at the same exit point, or at a
+        # neighbouring one (rounding can move a threshold crossing by one).
+        # Where BiCGStab(2) needs many iterations its residual history is far
+        # from monotone and depends on rounding: at d = 0.1 a relative
+        # perturbation of 1e-15 in the preconditioner output moves the
+        # oracle's own count from 14.5 to anywhere in 13..15.25, and 1e-11
+        # (the size of the GPU's reassociation differences there) to 16.25.
+        # Beyond two iterations the allowance grows to 35 % of the count.
+        _, ref, _ = oracle.sap_solve(pb.band, n, k, pb.b, p, mode == "coupled", tol=tol,
+                                     maxit=300)
+        assert ref.converged
+        allow = 0.5 if ref.iters <= 2.0 else 0.5 + 0.35 * ref.iters
+        assert abs(st.iters - ref.iters) <= allow, (st.iters, ref.iters)
     # adjoint: A^T lambda = g with the transposed preconditioner
     g = sapgen.splitmix64_uniform(5, 7, np.arange(n))
     lam, st2 = s.solve_adjoint(dev(g), tol=tol, maxit=300)
     lam = host(lam)
     assert st2.converged
-    assert rel(lam, oracle.solve_direct(pb.band, n, k, g, trans=True)) <= err_tol
+    assert_close(lam, oracle.solve_direct(pb.band, n, k, g, trans=True), err_tol, "lam")
     s.close()
 
 
@@ -238,7 +270,7 @@ def test_exact_cases_first_exit(p, mode):
     s.factor(dev(pb.band))
     x, st = s.solve(dev(pb.b), tol=1e-12)
     assert st.converged and st.iters == 0.25 and st.restarts == 0
-    assert rel(host(x), pb.x_true) <= 1e-12
+    assert_close(host(x), pb.x_true, 1e-12, "host(x)")
     s.close()
 
 
@@ -278,7 +310,7 @@ def test_pivot_boosting():
     assert rc == 0 and nbst == M.n_boosted and nbst >= 3
     x, st = s.solve(dev(b), tol=1e-10, maxit=200)
     assert st.converged
-    assert rel(host(x), oracle.solve_direct(band, n, k, b)) <= 1e-7
+    assert_close(host(x), oracle.solve_direct(band, n, k, b), 1e-7, "host(x)")
     s.close()
     s2 = solver(n, k, p, prec="fp64", boost_eps=-1.0)
     s2.factor(dev(band))
@@ -349,8 +381,8 @@ def test_autograd_matches_oracle_gradient():
     loss = 0.5 * ((x - dev(xt)) ** 2).sum()
     loss.backward()
     _, gb, ga = oracle.gradients(pb.band, n, k, pb.b, xt)
-    assert rel(host(b.grad), gb) <= 1e-9
-    assert rel(host(a.grad), ga) <= 1e-9
+    assert_close(host(b.grad), gb, 1e-9, "host(b.grad)")
+    assert_close(host(a.grad), ga, 1e-9, "host(a.grad)")
 
     def lossf(band, rhs):
         y = oracle.solve_direct(band, n, k, rhs)
@@ -368,4 +400,79 @@ def test_autograd_matches_oracle_gradient():
         bp[pos] += h; bm[pos] -= h
         fd = (lossf(bp, pb.b) - lossf(bm, pb.b)) / (2 * h)
         assert abs(fd - gah[pos]) <= 1e-5 * max(1.0, abs(gah[pos]))
+    s.close()
+
+
+def test_autograd_two_forwards_one_solver():
+    """Two forwards with different A on one solver, then one backward through
+    both: each gradient belongs to its own A (the second forward's factors
+    are not used for the first one's adjoint solve)."""
+    from paper_1509_07919_amd import sap_solve_autograd
+    n, k, p = 600, 4, 3
+    case("autograd-two", n, k, p)
+    pb1 = sapgen.make_problem(n, k, seed=45)
+    pb2 = sapgen.make_problem(n, k, d=0.7, seed=46)
+    xt = sapgen.normal_draws(45, sapgen.STREAM_XTARGET, n)
+    s = solver(n, k, p, prec="fp64", adjoint=True)
+    a1 = dev(pb1.band).requires_grad_(True)
+    b1 = dev(pb1.b).requires_grad_(True)
+    a2 = dev(pb2.band).requires_grad_(True)
+    b2 = dev(pb2.b).requires_grad_(True)
+    x1 = sap_solve_autograd(a1, b1, s, tol=1e-13)
+    x2 = sap_solve_autograd(a2, b2, s, tol=1e-13)
+    loss = 0.5 * ((x1 - dev(xt)) ** 2).sum() + 0.5 * ((x2 - dev(xt)) ** 2).sum()
+    loss.backward()
+    for a, b, pb in ((a1, b1, pb1), (a2, b2, pb2)):
+        _, gb, ga = oracle.gradients(pb.band, n, k, pb.b, xt)
+        assert_close(host(b.grad), gb, 1e-9, "dL/db")
+        assert_close(host(a.grad), ga, 1e-9, "dL/dA")
+    s.close()
+
+
+def oracle_factor_rows(M, which):
+    """The coefficient rows the library stores (Lc or Uc), built from the
+    oracle's block LU (row window f[r, c - r + K] of each block)."""
+    n, k = M.n, M.k
+    out = np.zeros((n, k + 1))
+    for i in range(M.p):
+        nb, s0 = int(M.sizes[i]), int(M.starts[i])
+        f = M.lu[i].reshape(nb, 2 * k + 1)
+        jj = np.arange(nb)
+        if which == "Lc":
+            out[s0:s0 + nb, 0] = 1.0
+            for m in range(1, k + 1):
+                ok = jj + m < nb
+                out[s0 + jj[ok], m] = f[jj[ok] + m, k - m]
+        else:
+            out[s0:s0 + nb, 0] = 1.0 / f[:, k]
+            for m in range(1, k + 1):
+                ok = jj - m >= 0
+                out[s0 + jj[ok], m] = f[jj[ok] - m, k + m]
+    return out
+
+
+# every LU kernel: the blocked LDS window (B = 8 and 4), the matrix-core
+# kernel (several window sizes), the register ring (FP64 97..127, FP32 > 208)
+LU_ROW_CASES = [
+    (3001, 10, 3, "fp64"), (3001, 10, 3, "fp32"), (4001, 58, 4, "fp64"), (4001, 62, 4, "fp32"),
+    (4001, 64, 4, "fp64"), (5003, 96, 5, "fp64"), (5003, 100, 5, "fp64"), (6007, 127, 5, "fp64"),
+    (6007, 150, 7, "fp32"), (6400, 160, 8, "fp64"), (6400, 208, 8, "fp32"), (7001, 255, 6, "fp32"),
+    (6400, 161, 8, "fp64"), (6401, 200, 8, "fp64"), (7001, 255, 6, "fp64"),
+]
+
+
+@pytest.mark.parametrize("n,k,p,prec", LU_ROW_CASES)
+def test_lu_rows_parity(n, k, p, prec):
+    """The block LU itself (Sec. 3.1, no pivoting, boosting): the stored L
+    and U coefficient rows against the oracle's factors, element by element
+    (FP64: 1e-12; FP32: 1e-4 of each array's largest entry, d = 1)."""
+    case("lu-rows", n, k, p, prec)
+    pb = sapgen.make_problem(n, k, d=1.0, seed=59)
+    eps = 2.0 ** -23 if prec == "fp32" else 2.0 ** -52
+    M = oracle.SapPrecond(pb.band, n, k, p, False, boost_eps=eps)
+    s = solver(n, k, p, mode="decoupled", prec=prec)
+    s.factor(dev(pb.band))
+    tol = 1e-12 if prec == "fp64" else 1e-4
+    for which in ("Lc", "Uc"):
+        assert_close(s.factor_rows(which), oracle_factor_rows(M, which), tol, which)
     s.close()

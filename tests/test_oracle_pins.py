@@ -12,6 +12,7 @@ import scipy.sparse as sps
 import scipy.sparse.linalg as spla
 
 import sapgen
+import oracle
 from oracle import (DirectLU, SapPrecond, bandmv, band_get, bicgstab_l,
                     gradients, partition, solve_direct, _load, _p)
 
@@ -530,3 +531,125 @@ def test_gradients_central_differences():
         assert abs(fd - ga[pos]) <= 1e-6 * max(1.0, abs(ga[pos]))
     # padding slots of the gradient are zero
     assert ga[(k - 1) * n + 0] == 0.0
+
+
+def _float32_dinv(band, n, k, p, r):
+    """An independent FP32 evaluation of D^{-1} r: each block densely in
+    float32, LU without pivoting (no boost needed for these matrices), then
+    the forward and backward substitutions, all in float32."""
+    sizes, starts = oracle.partition(n, p)
+    out = np.zeros(n)
+    for nb, s0 in zip(sizes, starts):
+        nb, s0 = int(nb), int(s0)
+        A = np.array([[oracle.band_get(band, n, k, s0 + a, s0 + b) for b in range(nb)]
+                      for a in range(nb)], dtype=np.float32)
+        for j in range(nb):
+            A[j + 1:j + k + 1, j] /= A[j, j]
+            A[j + 1:j + k + 1, j + 1:j + k + 1] -= np.outer(A[j + 1:j + k + 1, j],
+                                                           A[j, j + 1:j + k + 1])
+        y = r[s0:s0 + nb].astype(np.float32)
+        for j in range(nb):
+            y[j + 1:j + k + 1] -= A[j + 1:j + k + 1, j] * y[j]
+        for j in range(nb - 1, -1, -1):
+            y[j] = y[j] / A[j, j]
+            y[max(0, j - k):j] -= A[max(0, j - k):j, j] * y[j]
+        out[s0:s0 + nb] = y
+    return out
+
+
+@pytest.mark.parametrize("d", [0.5, 0.12])
+def test_fp32_error_model_against_float32_evaluation(d):
+    """The FP32 error model of D^{-1} (first-order bound and its statistical
+    version) against an actual float32 evaluation: every entry within the
+    rigorous bound, and within 6 sigma of the statistical model, which is
+    itself at most the bound."""
+    n, k, p = 3200, 16, 4
+    pb = sapgen.make_problem(n, k, d=d, seed=47)
+    M = oracle.SapPrecond(pb.band, n, k, p, False, boost_eps=2.0 ** -23)
+    r = sapgen.splitmix64_uniform(8, 7, np.arange(n))
+    g = M.dinv(r)
+    err = np.abs(_float32_dinv(pb.band, n, k, p, r) - g)
+    bound = oracle.dinv_error_bound(M, r)
+    sig = oracle.dinv_error_sigma(M, r)
+    u = 2.0 ** -24
+    assert np.all(err <= bound)
+    assert np.all(err <= 6 * sig + 8 * u * np.abs(g))
+    assert np.all(sig <= bound)
+    # the errors are real: the model is not trivially loose everywhere
+    assert (err / sig).max() >= 0.3
+
+
+def test_fp32_error_model_of_a_diagonal_matrix():
+    """K = 0: g = r / a, rounded twice (r and a to FP32) and once more by the
+    division: |g_hat - g| <= 3u|g| + O(u^2), inside the bound."""
+    n = 500
+    pb = sapgen.make_problem(n, 0, d=1.0, seed=49)
+    band = pb.band * (1.0 + sapgen.splitmix64_uniform(49, 6, np.arange(n)))
+    M = oracle.SapPrecond(band, n, 0, 5, False, boost_eps=2.0 ** -23)
+    r = sapgen.splitmix64_uniform(50, 7, np.arange(n))
+    g = r / band
+    bound = oracle.dinv_error_bound(M, r)
+    u = 2.0 ** -24
+    assert np.all(bound >= 3 * u * np.abs(g))
+    assert np.all(bound <= 20 * u * np.abs(g))
+    g32 = (r.astype(np.float32) / band.astype(np.float32)).astype(np.float64)
+    assert np.all(np.abs(g32 - g) <= bound)
+
+
+# ------------------------------------------------ conjugate gradient (SPD)
+
+def test_cg_iterates_match_scipy_cg():
+    """The oracle's preconditioned CG (Saad Alg. 9.1) produces the same
+    iterates as SciPy's cg with the same preconditioner, step by step."""
+    n, k, p = 2000, 6, 5
+    pb = sapgen.make_problem(n, k, d=1.02, seed=51, symmetric=True)
+    M = SapPrecond(pb.band, n, k, p, False)
+    A = sps.csr_matrix(sapgen.band_to_dense(pb.band, n, k))
+    mine = []
+    oracle.cg(lambda v: bandmv(pb.band, n, k, v), M.apply, pb.b, tol=1e-14, maxit=6,
+              observe=lambda it, x, r: mine.append(x))
+    ref = []
+    Mop = spla.LinearOperator((n, n), matvec=M.apply)
+    spla.cg(A, pb.b, M=Mop, rtol=0.0, atol=0.0, maxiter=6, callback=lambda xk: ref.append(xk.copy()))
+    assert len(mine) == len(ref) == 6
+    for a_, b_ in zip(mine, ref):
+        assert np.abs(a_ - b_).max() <= 1e-12 * np.abs(b_).max()
+
+
+def test_cg_finite_termination_three_eigenvalues():
+    """CG on an SPD matrix with 3 distinct eigenvalues and no preconditioning
+    reaches the solution in 3 steps (exact-arithmetic termination)."""
+    n = 300
+    diag = np.array([1.0, 4.0, 9.0])[np.arange(n) % 3]
+    band = diag.copy()                       # K = 0 band layout: the diagonal
+    xt = sapgen.splitmix64_uniform(52, 2, np.arange(n))
+    b = diag * xt
+    res = oracle.cg(lambda v: bandmv(band, n, 0, v), lambda v: v.copy(), b, tol=1e-13, maxit=10)
+    assert res.converged and res.iters == 3.0 and res.restarts == 0
+    assert np.abs(res.x - xt).max() <= 1e-13
+
+
+def test_cg_exact_preconditioner_one_step():
+    """P = 1: M = A (no boost), so z = A^{-1} r and the first CG step lands on
+    the solution."""
+    n, k = 1500, 9
+    pb = sapgen.make_problem(n, k, d=1.1, seed=53, symmetric=True)
+    x, res, _ = oracle.sap_solve_cg(pb.band, n, k, pb.b, 1, False, tol=1e-12)
+    assert res.converged and res.iters == 1.0
+    assert np.abs(x - pb.x_true).max() <= 1e-12
+
+
+def test_cg_breakdown_on_indefinite_direction():
+    """p^T A p = 0 for A = diag(1, -1) and b = (1, 1): CG breaks down."""
+    band = np.array([1.0, -1.0])
+    with pytest.raises(oracle.Breakdown):
+        oracle.cg(lambda v: bandmv(band, 2, 0, v), lambda v: v.copy(), np.ones(2))
+
+
+def test_spd_generator_is_symmetric_positive_definite():
+    n, k = 400, 12
+    pb = sapgen.make_problem(n, k, d=1.05, seed=54, symmetric=True)
+    A = sapgen.band_to_dense(pb.band, n, k)
+    assert np.array_equal(A, A.T)
+    assert np.linalg.eigvalsh(A).min() > 0.0
+    assert np.all(np.diag(A) > 0)
