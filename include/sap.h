@@ -184,6 +184,27 @@ int sap_solve_adjoint(sap_handle h, const double *g, double *lambda,
 int sap_band_grad(sap_handle h, const double *lambda, const double *x,
                   double *g_band, void *stream);
 
+/* For callers that cannot allocate memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation): sap_factor and
+ * sap_solve of A x = b in one call, with the factors, tips, Krylov vectors
+ * and every other intermediate in a static device array of
+ * SAP_NOALLOC_SCRATCH_BYTES bytes inside the library instead of a caller
+ * workspace.  Each GPU the library runs on holds one such array from the
+ * first call on it until the process ends.  The call creates no handle,
+ * event or stream and calls no allocation routine; it returns once x is
+ * written (it synchronises `stream`).  opt as for sap_create, with
+ * opt->adjoint = 0; a_band (borrowed only during the call), b and x as for
+ * sap_factor and sap_solve.  Options whose workspace does not fit the array
+ * (sap_workspace_bytes + 256 > SAP_NOALLOC_SCRATCH_BYTES) return
+ * SAP_ERR_NOSPACE before any device work.  The statistics carry no device
+ * times (t_*_ms = 0).  All calls on one GPU share its array and it keeps the
+ * last call's contents: calls that overlap on one GPU (other host threads,
+ * other streams) race and must be serialised by the caller. */
+#define SAP_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int sap_solve_noalloc(const sap_options *opt, const double *a_band,
+                      const double *b, double *x, double tol, int32_t maxit,
+                      void *stream, sap_stats *st);
+
 /* Device-side status of the last factorization, synchronising `stream`:
  * SAP_OK or SAP_ERR_SINGULAR; n_boosted (host, nullable) gets the number of
  * boosted pivots. */

@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -1085,6 +1086,41 @@ int factor_impl(sap_handle h, const double *a_band, hipStream_t s)
 
 }  // namespace
 
+// Workspace of sap_solve_noalloc: one static array in every GPU's memory
+// (each device holds its own copy, at its own address, until the process
+// ends).  Host code never passes `scratch` itself to a kernel or a copy: its
+// device address comes from hipGetSymbolAddress, once per device.
+static __device__ __align__(256) unsigned char scratch[SAP_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+constexpr size_t kSlotBytes = 256;   // result slots ahead of the carved workspace
+std::mutex g_scratch_mu;
+unsigned char *g_scratch[kMaxDevices];
+
+// Device address of `scratch` on the current device, looked up on the first
+// call made with that device current.
+int scratch_address(unsigned char **out)
+{
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(SAP_ERR_HIP, "device index out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(SAP_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") +
+                                         hipGetErrorString(e));
+        g_scratch[dev] = static_cast<unsigned char *>(p);
+    }
+    *out = g_scratch[dev];
+    return SAP_OK;
+}
+
+}  // namespace
+
 // ======================================================================= ABI
 
 extern "C" {
@@ -1185,6 +1221,37 @@ int sap_band_grad(sap_handle h, const double *lambda, const double *x, double *g
     HIP_TRY(launch_band_grad(h->opt.n, h->opt.k, lambda, x, g_band,
                              static_cast<hipStream_t>(stream)));
     return SAP_OK;
+}
+
+int sap_solve_noalloc(const sap_options *opt, const double *a_band, const double *b, double *x,
+                      double tol, int32_t maxit, void *stream, sap_stats *st)
+{
+    int rc = validate(opt);
+    if (rc) return rc;
+    if (opt->adjoint) return fail(SAP_ERR_INVALID, "sap_solve_noalloc needs adjoint = 0");
+    if (opt->nrhs > 1) return fail(SAP_ERR_INVALID, "sap_solve_noalloc needs nrhs <= 1");
+    if (!a_band || !b || !x) return fail(SAP_ERR_INVALID, "null pointer");
+    const Layout L = layout_for(*opt);
+    if (L.total > SAP_NOALLOC_SCRATCH_BYTES - kSlotBytes)
+        return fail(SAP_ERR_NOSPACE, "sap_solve_noalloc: these options need " +
+                                         std::to_string(L.total + kSlotBytes) +
+                                         " bytes of scratch; the static scratch holds " +
+                                         std::to_string((size_t)SAP_NOALLOC_SCRATCH_BYTES));
+    unsigned char *scr = nullptr;
+    TRY(scratch_address(&scr));
+    // a handle on the stack over the static scratch: no host or device
+    // allocation, no events (the statistics carry no device times) and no
+    // side stream (the transfer matrices run on `stream`)
+    sap_handle_ hs{};
+    init_handle(&hs, *opt, scr + kSlotBytes, L);
+    hs.d_slots = reinterpret_cast<double *>(scr);
+    hs.h_slots = hs.slot_copy;
+    hs.h_status = hs.status_copy;
+    hs.mapped = false;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    rc = factor_impl(&hs, a_band, s);
+    if (rc) return rc;
+    return krylov(&hs, 0, b, x, tol, maxit, s, st);
 }
 
 int sap_handle_status(sap_handle h, void *stream, int32_t *n_boosted)

@@ -34,7 +34,7 @@ SAP_PREC_FP32 = 1
 EXPORTED = ("sap_workspace_bytes", "sap_create", "sap_factor", "sap_solve",
             "sap_solve_adjoint", "sap_band_grad", "sap_handle_status", "sap_spmv",
             "sap_precond_apply", "sap_get_tips", "sap_profile", "sap_kernel_time",
-            "sap_destroy", "sap_last_error", "sap_solve_cg", "sap_solve_batch",
+            "sap_destroy", "sap_last_error", "sap_solve_noalloc", "sap_solve_cg", "sap_solve_batch",
             "sap_get_factor_rows")
 
 KERNELS = ("norm", "lu", "tips", "sweep", "corr", "spmv", "krylov", "xfer")
@@ -99,6 +99,7 @@ def load_library(path: str = LIB_PATH):
     lib.sap_profile.argtypes = [vp, i32]
     lib.sap_kernel_time.argtypes = [vp, i32, P(dbl), P(i64)]
     lib.sap_destroy.argtypes = [vp]
+    lib.sap_solve_noalloc.argtypes = [P(sap_options), vp, vp, vp, dbl, i32, vp, P(sap_stats)]
     lib.sap_last_error.restype = ctypes.c_char_p
     for name in EXPORTED:
         if name != "sap_last_error":
@@ -297,6 +298,27 @@ class SapSolver:
             self.handle, i, v.ctypes.data_as(ctypes.c_void_p), w.ctypes.data_as(ctypes.c_void_p),
             rb.ctypes.data_as(ctypes.c_void_p), _stream()))
         return v.reshape(self.k, self.k), w.reshape(self.k, self.k), rb.reshape(self.k, self.k)
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20     # SAP_NOALLOC_SCRATCH_BYTES
+
+
+def solve_noalloc(a_band: torch.Tensor, b: torch.Tensor, n: int, k: int, p: int,
+                  mode: str = "coupled", factor_prec: str = "fp64", boost_eps: float = 0.0,
+                  sweep_chunks: int = 0, x: torch.Tensor | None = None, tol: float = 1e-10,
+                  maxit: int = 200):
+    """sap_solve_noalloc: factor and solve in the library's static scratch
+    (no workspace, handle or allocation on the library side).  Returns
+    (x, SapStats); raises SapError on errors other than SAP_NOT_CONVERGED."""
+    opt = make_options(n, k, p, mode, factor_prec, boost_eps, False, sweep_chunks)
+    x = torch.empty_like(b) if x is None else x
+    st = sap_stats()
+    rc = load_library().sap_solve_noalloc(
+        ctypes.byref(opt), _dptr(a_band, (2 * k + 1) * n, "a_band"), _dptr(b, n, "b"),
+        _dptr(x, n, "x"), float(tol), int(maxit), _stream(), ctypes.byref(st))
+    if rc not in (SAP_OK, SAP_NOT_CONVERGED):
+        _check(rc)
+    return x, SapStats(**st.as_dict(), status=rc)
 
 
 class SapSolve(torch.autograd.Function):
