@@ -82,6 +82,147 @@ def traffic_from_profiles(tag: str):
     return ent.get("bytes_per_unit")
 
 
+# kernel name -> (class, source file of that kernel)
+KERNEL_CLASSES = (
+    ("k_lu_wide", "lu", "k_lu_wide.hip"), ("k_lu_mfma", "lu", "k_lu_mfma.hip"),
+    ("k_banded_lu", "lu", "k_factor.hip"), ("k_block_norm", "norm", "k_factor.hip"),
+    ("k_sweep_xfer", "xfer", "k_sweep.hip"), ("k_sweep", "sweep", "k_sweep.hip"),
+    ("k_tips", "tips", "k_tips.hip"), ("k_spmv", "spmv", "k_vec.hip"),
+    ("k_correction", "corr", "k_vec.hip"), ("k_dots", "krylov", "k_vec.hip"),
+    ("k_update", "krylov", "k_vec.hip"),
+)
+
+
+def summarize_counters(fetch_dir, write_dir, workload, prec):
+    """Per-class HBM bytes from two rocprofv3 --pmc runs (FETCH_SIZE, then
+    WRITE_SIZE, KiB per dispatch) of `bench.py --steps 1 --warmup 0 --no-cpu
+    --race-d 0 --no-cold --batch-rhs 0 --precs <prec> --copy-calibration`,
+    each scaled by what the counter reads for the run's 1 GiB device copy.
+    Units: a launch, a factorization for the tips, a whole sweep for the
+    sweeps.  Merges into profiles/traffic_<workload>.json and prints a
+    markdown table."""
+    import csv
+    import glob
+
+    def load(d, counter):
+        per = {}
+        for path in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            with open(path) as f:
+                for row in csv.DictReader(f):
+                    if row.get("Counter_Name") != counter:
+                        continue
+                    key = (row["Kernel_Name"], row.get("Dispatch_Id") or row.get("Correlation_Id"))
+                    per[key] = per.get(key, 0.0) + float(row["Counter_Value"])
+        by_kernel = {}
+        for (name, _), v in per.items():
+            by_kernel.setdefault(name, []).append(v)
+        return by_kernel
+
+    fetch, write = load(fetch_dir, "FETCH_SIZE"), load(write_dir, "WRITE_SIZE")
+
+    def bench_line(d):
+        for path in glob.glob(os.path.join(d, "**", "stdout.txt"), recursive=True):
+            for line in open(path):
+                if line.startswith("{"):
+                    return json.loads(line)
+        raise RuntimeError("no bench JSON line under " + d)
+
+    line = bench_line(fetch_dir)
+    copy_f = [v for nm, vs in fetch.items() if "copyBuffer" in nm for v in vs]
+    copy_w = [v for nm, vs in write.items() if "copyBuffer" in nm for v in vs]
+    cal = line["copy_calibration_bytes"]
+    fcal = cal["read"] / (max(copy_f) * 1024.0)
+    wcal = cal["write"] / (max(copy_w) * 1024.0)
+    cfg = sapgen_workload(workload)
+    coupled = cfg["mode"] == "coupled"
+    st = line["runs"][prec]
+    steps = 2                                   # the timed step and the profiled one
+    sweeps = steps * (int(round(st["iters"] * 4)) + 1) * (4 if coupled else 2)
+    classes = {}
+    for name in sorted(set(fetch) | set(write)):
+        hit = next(((c, src) for pat, c, src in KERNEL_CLASSES if pat in name), None)
+        if not hit:
+            continue
+        c, src = hit
+        ent = classes.setdefault(c, {"dispatches": 0, "read": 0.0, "write": 0.0, "source": src,
+                                     "kernels": []})
+        fr, wr = fetch.get(name, []), write.get(name, [])
+        ent["dispatches"] += max(len(fr), len(wr))
+        ent["read"] += sum(fr) * 1024.0 * fcal
+        ent["write"] += sum(wr) * 1024.0 * wcal
+        ent["kernels"].append((name, max(len(fr), len(wr)), sum(fr) / max(len(fr), 1),
+                               sum(wr) / max(len(wr), 1)))
+    nfac = classes.get("lu", {}).get("dispatches", steps)
+    path = os.path.join(PROFILE_DIR, "traffic_%s.json" % workload)
+    data = json.load(open(path)) if os.path.exists(path) else {}
+    rows = []
+    for c, ent in sorted(classes.items()):
+        units = sweeps if c == "sweep" else (nfac if c == "tips" else ent["dispatches"])
+        tag = "%s_%s_%s" % (c, prec, workload)
+        data[tag] = {"dispatches": ent["dispatches"], "source": ent["source"],
+                     "source_sha256_16": kernel_source_hash(ent["source"]), "units": units,
+                     "bytes_per_unit": (ent["read"] + ent["write"]) / units,
+                     "read_bytes_per_unit": ent["read"] / units,
+                     "write_bytes_per_unit": ent["write"] / units}
+        rows.append("| %s | %s | %d | %.1f | %.1f |" % (c, prec, units, ent["read"] / units / 1e6,
+                                                      ent["write"] / units / 1e6))
+    with open(path, "w") as f:
+        json.dump(data, f, indent=1, sort_keys=True)
+    print("calibration: read x %.3f, write x %.3f (1 GiB copy)" % (fcal, wcal))
+    print("| kernel | dispatches | FETCH_SIZE KiB (avg) | WRITE_SIZE KiB (avg) |")
+    print("|---|---|---|---|")
+    for c, ent in sorted(classes.items()):
+        for name, nd, fa, wa in ent["kernels"]:
+            print("| `%s` | %d | %.0f | %.0f |" % (name[:90], nd, fa, wa))
+    print()
+    print("| class | precision | units | read MB per unit | write MB per unit |")
+    print("|---|---|---|---|---|")
+    print("\n".join(rows))
+
+
+def sapgen_workload(name):
+    import sapgen
+    return dict(sapgen.WORKLOADS[name])
+
+
+def run_cold(args, prec, a, b):
+    """The same steps with the 256 MB last-level cache flushed before each
+    one (a 1 GiB buffer is written, untimed): every step starts with A, the
+    factors and the vectors in HBM only.  Returns (ms per step from events
+    around each step, per-kernel times of the flushed steps)."""
+    import torch
+    from paper_1509_07919_amd import SapSolver
+
+    cfg = args.cfg
+    s = SapSolver(cfg["n"], cfg["k"], cfg["p"], mode=cfg["mode"], factor_prec=prec)
+    x = torch.empty_like(b)
+    flush = torch.empty(1 << 27, dtype=torch.float64, device=a.device)
+    for _ in range(args.warmup):
+        s.factor(a)
+        s.solve(b, x, tol=cfg["tol"], maxit=args.maxit)
+    st_ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    en_ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    for i in range(args.steps):
+        flush.fill_(float(i))
+        st_ev[i].record()
+        s.factor(a)
+        s.solve(b, x, tol=cfg["tol"], maxit=args.maxit)
+        en_ev[i].record()
+    torch.cuda.synchronize()
+    ms = sum(st_ev[i].elapsed_time(en_ev[i]) for i in range(args.steps)) / args.steps
+    s.profile(True)
+    for i in range(args.steps):
+        flush.fill_(float(i))
+        s.factor(a)
+        s.solve(b, x, tol=cfg["tol"], maxit=args.maxit)
+    torch.cuda.synchronize()
+    kt = s.kernel_times()
+    s.profile(False)
+    s.close()
+    del flush
+    return ms, kt
+
+
 def run_gpu(args, prec, pb, a, b):
     import torch
     from paper_1509_07919_amd import SapSolver
@@ -110,6 +251,7 @@ def run_gpu(args, prec, pb, a, b):
     torch.cuda.synchronize()
     kt = s.kernel_times()
     s.profile(False)
+    kt["phases"] = s.tips_phase_times()
     xs = x.cpu().numpy()
     s.close()
     return (t1 - t0) * 1e3 / args.steps, stats, kt, xs
@@ -253,11 +395,16 @@ def main():
                     help="also race FP32 against FP64 factors on the same N, K, P at these "
                          "diagonal dominances (comma list; 0 or empty: skip)")
     ap.add_argument("--race-steps", type=int, default=5)
+    ap.add_argument("--no-cold", action="store_true",
+                    help="skip the steps timed with the last-level cache flushed first")
     ap.add_argument("--batch-rhs", type=int, default=8,
                     help="also time sap_solve_batch with this many right-hand sides on the "
                          "same factorization (0: skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 1 GiB device copy (counter calibration)")
+    ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="build profiles/traffic_<workload>.json from two rocprofv3 --pmc "
+                         "runs (FETCH_SIZE, WRITE_SIZE) of this script with --precs <one>")
     ap.add_argument("--experiment", choices=sorted(EXPERIMENTS),
                     help="instead of the benchmark line, run one of the paper's dense "
                          "sensitivity studies and print one JSON line per configuration")
@@ -268,6 +415,10 @@ def main():
         sys.exit(2)
     if args.experiment:
         run_experiment(args)
+        return
+    if args.summarize_counters:
+        summarize_counters(args.summarize_counters[0], args.summarize_counters[1], args.workload,
+                           args.precs.split(",")[0])
         return
 
     import numpy as np
@@ -305,7 +456,10 @@ def main():
     sweeps = sum((st.n_apply + 1) * (4 if coupled else 2) for st in r["stats"])
     units = {"sweep": sweeps}
     kernels = {}
-    for name, (tms, cnt) in r["kt"].items():
+    for name, val in r["kt"].items():
+        if name == "phases":
+            continue
+        tms, cnt = val
         if cnt == 0:
             continue
         nu = units.get(name, cnt)
@@ -347,6 +501,7 @@ def main():
                 "rel_resid_true": st.rel_resid_true, "converged": bool(st.converged),
                 "t_factor_ms": round(st.t_factor_ms, 4), "t_lu_ms": round(st.t_lu_ms, 4),
                 "t_tips_ms": round(st.t_tips_ms, 4), "t_solve_ms": round(st.t_solve_ms, 4),
+                "tips_phases_ms": {kk: round(v, 4) for kk, v in q["kt"]["phases"].items()},
                 "rel_err_vs_xtrue": err_true}
 
     out = {
@@ -395,6 +550,24 @@ def main():
                 "steps": args.race_steps, "fp64": rw["fp64"], "fp32": rw["fp32"],
                 "fp32_speedup": round(rw["fp64"]["ms"] / rw["fp32"]["ms"], 3)})
             del aw, bw
+    if not args.no_cold:
+        # flushed-cache (cold) figures: the step, and per kernel the sweeps
+        # and SpMV rates, whose operands otherwise partly stay in the 256 MB
+        # last-level cache between launches (A alone is 161.6 MB here)
+        out["cold"] = {}
+        for p_ in runs:
+            cms, ckt = run_cold(args, p_, a, b)
+            sfp = 8 if p_ == "fp64" else 4
+            ent = {"ms_per_step": round(cms, 4)}
+            nsw = sum((st.n_apply + 1) * (4 if coupled else 2) for st in runs[p_]["stats"])
+            for name, nunits, bpu in (("sweep", nsw, sweep_bytes(n, k, sfp, coupled)),
+                                      ("spmv", None, spmv_bytes(n, k))):
+                tms, cnt = ckt[name]
+                if cnt:
+                    nu = nunits if nunits else cnt
+                    ent[name] = {"avg_us": round(1e3 * tms / nu, 2),
+                                 "algorithmic_GBps": round(bpu / (1e-3 * tms / nu) / 1e9, 1)}
+            out["cold"][p_] = ent
     if args.batch_rhs > 0:
         out["multi_rhs"] = [run_batch(args, p_, pb, a, args.batch_rhs) for p_ in runs]
     if args.copy_calibration:

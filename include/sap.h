@@ -141,6 +141,56 @@ int sap_factor(sap_handle h, const double *a_band, void *stream);
 int sap_solve(sap_handle h, const double *b, double *x, double tol,
               int32_t maxit, void *stream, sap_stats *st);
 
+/* ------------------------------------------------------------------------
+ * Sparse front end (Sec. 3.1 "Diagonal Boosting" and "Bandwidth reduction",
+ * Sec. 3.3, Sec. 3.4 T_DB, T_CM, T_Drop, T_Asmbl): reorder a sparse A so
+ * that a dense band of half-bandwidth K carries it, build that band for the
+ * SaP preconditioner, and solve with the full reordered matrix in the
+ * Krylov products.  A_hat = P D_r Q A D_c P^T with Q the row permutation of
+ * diagonal boosting (maximum prod |a_{i sigma_i}| as a minimum-cost perfect
+ * bipartite matching with costs log a_i - log |a_ij|, eq:DBrelated; D_r, D_c
+ * scale A_hat to an I-matrix: |diagonal| = 1, |off-diagonal| <= 1) and P
+ * the Cuthill-McKee ordering of the structure of Q A + (Q A)^T.  Entries
+ * farther than K from the diagonal are left out of the band (drop-off) but
+ * stay in the Krylov product.  Not built: the third-stage reordering of the
+ * diagonal blocks (it needs full spikes). */
+typedef struct sap_sparse_ *sap_sparse;
+
+/* Analyse A given as host CSR (rowptr: N+1 int64, rowptr[0] = 0; colidx:
+ * rowptr[N] int32 column indices; vals: doubles; explicit zeros are not
+ * edges of the matching).  db, cm: nonzero to apply diagonal boosting and
+ * Cuthill-McKee.  drop_frac in [0, 1): K is the least half-bandwidth whose
+ * outside entries carry at most drop_frac of sum |a_hat| (0: every entry in
+ * the band).  The reorderings run on the host; the plan keeps the reordered
+ * structure and work vectors in device memory it allocates.  Returns
+ * SAP_ERR_SINGULAR if A has no perfect matching (structurally singular). */
+int sap_sparse_create(int64_t n, const int64_t *rowptr, const int32_t *colidx,
+                      const double *vals, int32_t db, int32_t cm, double drop_frac,
+                      sap_sparse *out);
+
+/* The plan's K (after drop-off) and the half-bandwidth without drop-off;
+ * the maps (row r of A is row new_row[r] of A_hat; column c is column
+ * new_col[c]) and the scales D_r, D_c (host arrays of N; any pointer may be
+ * NULL). */
+int sap_sparse_info(sap_sparse sp, int32_t *k, int32_t *k_full, int32_t *new_row,
+                    int32_t *new_col, double *row_scale, double *col_scale);
+
+/* On the GPU: the values of A_hat from A's values (device array in the
+ * original CSR order, same structure as at sap_sparse_create) and the band
+ * of A_hat (device, (2K+1)*N doubles, band layout, padding zero) to hand to
+ * sap_factor of a handle with this N and K.  Enqueue-only. */
+int sap_sparse_assemble(sap_sparse sp, const double *vals, double *band, void *stream);
+
+/* Solve A x = b (b, x device N-vectors in A's original order) with
+ * BiCGStab(2) on A_hat y = b_hat, the preconditioner of h (factored on the
+ * band from sap_sparse_assemble) and the sparse product of A_hat; then
+ * x = D_c P^T y.  h must have the plan's N and K.  As sap_solve otherwise
+ * (st->rel_resid_true refers to A_hat y = b_hat). */
+int sap_solve_sparse(sap_handle h, sap_sparse sp, const double *b, double *x, double tol,
+                     int32_t maxit, void *stream, sap_stats *st);
+
+int sap_sparse_destroy(sap_sparse sp);
+
 /* Solve A X = B for m right-hand sides at once (Sec. 4.1.1 discusses the
  * factorization cost that several right-hand sides share), 1 <= m <= nrhs
  * of the handle.  B and X are N x m, column-major (column c at + c*N), and
@@ -236,6 +286,17 @@ int sap_get_tips(sap_handle h, int32_t i, double *v, double *w, double *rbar,
  * a completed sap_factor; synchronises. */
 int sap_get_factor_rows(sap_handle h, int32_t which, int64_t j0, int64_t count,
                         double *out /* host */, void *stream);
+
+/* The paper's split of the SaP-C preprocessing after the block LU (Sec.
+ * 3.4): T_BC (gathering B_i and C_i), T_SPK (the spike tips V_i, W_i) and
+ * T_LUrdcd (Rbar_i and its factorization), in milliseconds, of the last
+ * sap_factor, into ms[0..2] (host).  Where the three run as separate
+ * launches (large K) they are timed with events between them; where one
+ * kernel does all three, its event time is split in proportion to the time
+ * its workgroups spend in each phase (constant-rate device clock).  They are
+ * recorded only while sap_profile is on (SAP_ERR_STATE otherwise).  Zero for
+ * SaP-D.  Synchronises. */
+int sap_tips_phase_times(sap_handle h, double *ms /* host[3] */, void *stream);
 
 /* Per-kernel device timing, for benchmarking.  sap_profile(h, 1) resets the
  * counters and starts bracketing every kernel launch of the handle with a

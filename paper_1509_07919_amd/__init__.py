@@ -3,7 +3,7 @@ systems: hand-written HIP kernels behind a C ABI (include/sap.h), with this
 package as the thin Python binding."""
 
 from .sap import (SAP_COUPLED, SAP_DECOUPLED, SAP_PREC_FP32, SAP_PREC_FP64, SapError,
-                  SapLibraryMissing, SapSolve, SapSolver, SapStats, load_library,
+                  SapLibraryMissing, SapSolve, SapSolver, SapSparse, SapStats, load_library,
                   make_options, sap_solve_autograd, sap_workspace_bytes)
 
 __all__ = ["SapSolver", "SapSolve", "SapStats", "SapError", "SapLibraryMissing",

@@ -400,6 +400,17 @@ __global__ __launch_bounds__(256) void k_tips_lds(TipsArgs<T> a)
     __shared__ T d_sh;
     const int tid = threadIdx.x;
     const int64_t base = s1 - k;                // first row of block i's bottom corner
+    // time this workgroup spends in (a) B/C gather (T_BC), (b) spikes
+    // (T_SPK) and (c, d) Rbar and its inverse (T_LUrdcd), summed over the
+    // workgroups with the constant 100 MHz clock (wall_clock64)
+    unsigned long long tk = (a.ticks && tid == 0) ? wall_clock64() : 0ull;
+    auto lap = [&](int ph) {
+        if (a.ticks && tid == 0) {
+            const unsigned long long u = wall_clock64();
+            atomicAdd(a.ticks + ph, u - tk);
+            tk = u;
+        }
+    };
     const T *cn = a.corner + (int64_t)(i + 1) * kk;
     const int64_t ikk = (int64_t)i * kk;
 
@@ -447,6 +458,7 @@ __global__ __launch_bounds__(256) void k_tips_lds(TipsArgs<T> a)
     __syncthreads();
     for (int c = tid; c < k; c += 256) gi[c] = T(1) / G[c * k + c];
     __syncthreads();
+    lap(0);
 
     // (b) V = U_bb^{-1} (L_bb^{-1} B_i) in X, W = L'_tt^{-1} (U'_tt^{-1} C_{i+1}) in Y
     // a team thread owns column tc and the rows congruent to tr0 modulo
@@ -505,6 +517,7 @@ __global__ __launch_bounds__(256) void k_tips_lds(TipsArgs<T> a)
         a.V[ikk + e] = X[e];
         a.W[ikk + e] = Y[e];
     }
+    lap(1);
 
     // (c) Rbar = I - W V -> F and Rbar (global); item (row pair, 4 columns)
     {
@@ -609,22 +622,38 @@ __global__ __launch_bounds__(256) void k_tips_lds(TipsArgs<T> a)
     }
     __syncthreads();
     for (int r = gr0; gact && r < k; r += grs) a.Rinv[ikk + r * k + gc] = F[r * k + ord_sh[gc]];
+    lap(2);
 }
 
-template <typename T>
-hipError_t launch_tips(const TipsArgs<T> &a, hipStream_t s)
+// the four K x K working matrices and 3K vectors in LDS, plus the static LDS
+// of k_tips_lds (perm_sh, ord_sh, p_sh, d_sh)
+bool tips_in_lds(int k, bool fp32)
 {
+    const size_t ts = fp32 ? 4 : 8;
+    const size_t kk = (size_t)k * k;
+    return (4 * kk + 3 * (size_t)k) * ts + 2 * kMaxK * sizeof(int) + sizeof(int) + ts + 64 <= kMaxLds;
+}
+
+// ev (nullable): events recorded before the first launch, after the B/C
+// gather, after the spikes and after the last launch; in the LDS form the
+// middle two are not recorded (its phases are split by a.ticks instead)
+template <typename T>
+hipError_t launch_tips(const TipsArgs<T> &a, hipStream_t s, hipEvent_t *ev)
+{
+    auto mark = [&](int m) {
+        if (ev && ev[m]) (void)hipEventRecord(ev[m], s);
+    };
     if (a.pt.p < 2) return hipSuccess;
     const size_t kk = (size_t)a.pt.k * a.pt.k;
     const size_t lds = (4 * kk + 3 * (size_t)a.pt.k) * sizeof(T);
-    // plus the static LDS of k_tips_lds (perm_sh, ord_sh, p_sh, d_sh)
-    const size_t lds_static = 2 * kMaxK * sizeof(int) + sizeof(int) + sizeof(T) + 64;
-    if (lds + lds_static <= kMaxLds) {
+    if (tips_in_lds(a.pt.k, sizeof(T) == 4)) {
         auto kern = k_tips_lds<T>;
         hipError_t e = hipFuncSetAttribute((const void *)kern,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
+        mark(0);
         hipLaunchKernelGGL(kern, dim3(a.pt.p - 1), dim3(256), lds, s, a);
+        mark(3);
     } else {
         const int ncg = (a.pt.k + 63) / 64;
         const size_t cols = (size_t)a.pt.k * 66 * sizeof(T);    // columns + 2 factor rows: <= 134640 B
@@ -633,8 +662,11 @@ hipError_t launch_tips(const TipsArgs<T> &a, hipStream_t s)
             hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)cols);
             if (e != hipSuccess) return e;
         }
+        mark(0);
         hipLaunchKernelGGL(k_tips_global_stage<T>, dim3(a.pt.p - 1, 2), dim3(256), 0, s, a);
+        mark(1);
         hipLaunchKernelGGL(k_tips_global_vw<T>, dim3(a.pt.p - 1, 2 * ncg), dim3(64), cols, s, a);
+        mark(2);
         const int nt = (a.pt.k + 63) / 64;
         hipLaunchKernelGGL(k_tips_global_rbar<T>, dim3(a.pt.p - 1, nt * nt), dim3(256), 0, s, a);
         const size_t rb = kk * sizeof(T);
@@ -647,11 +679,13 @@ hipError_t launch_tips(const TipsArgs<T> &a, hipStream_t s)
             hipLaunchKernelGGL((k_tips_global_lu<T, false>), dim3(a.pt.p - 1), dim3(256), 0, s, a);
         }
         hipLaunchKernelGGL(k_tips_global_rinv<T>, dim3(a.pt.p - 1, ncg), dim3(64), cols, s, a);
+        mark(3);
     }
     return hipGetLastError();
 }
 
-template hipError_t launch_tips<float>(const TipsArgs<float> &, hipStream_t);
-template hipError_t launch_tips<double>(const TipsArgs<double> &, hipStream_t);
+
+template hipError_t launch_tips<float>(const TipsArgs<float> &, hipStream_t, hipEvent_t *);
+template hipError_t launch_tips<double>(const TipsArgs<double> &, hipStream_t, hipEvent_t *);
 
 }  // namespace sap

@@ -36,7 +36,7 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-    size_t starts, partial, status, Lc, Uc, Lr, Ur, corner, lwin, B, C, V, W, Rbar, Rlu, Rinv, piv,
+    size_t starts, partial, status, ticks, Lc, Uc, Lr, Ur, corner, lwin, B, C, V, W, Rbar, Rlu, Rinv, piv,
         gT, yT, dtop, dbot, kv, dpart, sc, xLc, xUc, xLr, xUr, xscr, sq, sst, ticket, total;
 };
 
@@ -123,6 +123,7 @@ Layout layout_for(const sap_options &o)
     L.starts = take(sizeof(int64_t) * (p + 1));
     L.partial = take(sizeof(double) * (size_t)p * nchunk);
     L.status = take(64);
+    L.ticks = take(64);          // tips phase clocks (3 x u64)
     const size_t fb = sf * n * coef_pitch(k, (int)sf);   // one factor array
     L.Lc = take(fb);
     L.Uc = take(fb);
@@ -166,6 +167,8 @@ Layout layout_for(const sap_options &o)
 
 }  // namespace
 
+int sap::api_fail(int code, const std::string &msg) { return fail(code, msg); }
+
 struct sap_handle_ {
     sap_options opt;
     bool coupled, fp32;
@@ -186,6 +189,9 @@ struct sap_handle_ {
     const double *a_band;
     bool factored, starts_uploaded;
     hipEvent_t ev[5];        // factor start / after LU / end, solve start / end
+    hipEvent_t tev[4];       // around the tips phases (T_BC, T_SPK, T_LUrdcd)
+    const CsrDev *csr;       // set during sap_solve_sparse: the Krylov product uses it
+    bool phases_valid;       // the last factorization recorded them (profiling on)
     hipStream_t side;        // second stream: transfer matrices beside the tips
     hipEvent_t join;         // the side stream's work joins the main stream
     float t_factor, t_lu, t_tips;
@@ -345,13 +351,22 @@ int precond(sap_handle h, int trans, const double *r, double *z, hipStream_t s, 
                    : precond_t<double>(h, trans, r, z, s, m);
 }
 
+// y = A v (or b - A v) with the matrix of the solve: the band, or the
+// reordered sparse matrix of sap_solve_sparse
+hipError_t spmv_op(sap_handle h, const double *v, const double *b, double *y, int trans, int m,
+                   hipStream_t s)
+{
+    if (h->csr) return launch_csr_spmv(*h->csr, v, b, y, s);
+    return launch_spmv_multi(h->a_band, h->opt.n, h->opt.k, v, b, y, trans, m, s);
+}
+
 // Krylov operator  v -> M^{-1} A v  (or M^{-T} A^T v), m right-hand sides
 int apply_op(sap_handle h, int trans, const double *v, double *out, hipStream_t s, int m = 1)
 {
     double *t = h->kvec(KV_T);
     {
         ProfScope ps(h, SAP_KERNEL_SPMV, s);
-        HIP_TRY(launch_spmv_multi(h->a_band, h->opt.n, h->opt.k, v, nullptr, t, trans, m, s));
+        HIP_TRY(spmv_op(h, v, nullptr, t, trans, m, s));
     }
     return precond(h, trans, t, out, s, m);
 }
@@ -536,7 +551,7 @@ int krylov(sap_handle h, int trans, const double *b, double *x, double tol, int3
         if (spec) {
             {
                 ProfScope ps(h, SAP_KERNEL_SPMV, s);
-                HIP_TRY(launch_spmv(A, n, k, x, b, t, trans, s));    // t = b - A x
+                HIP_TRY(spmv_op(h, x, b, t, trans, 1, s));            // t = b - A x
             }
             TRY(dots(h, OP_SPEC, {{t, t}}, s));
         }
@@ -581,7 +596,7 @@ int krylov(sap_handle h, int trans, const double *b, double *x, double tol, int3
         }
         {
             ProfScope ps(h, SAP_KERNEL_SPMV, s);
-            HIP_TRY(launch_spmv(A, n, k, x, b, t, trans, s));    // t = b - A x
+            HIP_TRY(spmv_op(h, x, b, t, trans, 1, s));            // t = b - A x
         }
         if (pn > thr) {
             // reliable update before the recursive residual reached the
@@ -653,7 +668,7 @@ int krylov(sap_handle h, int trans, const double *b, double *x, double tol, int3
     }
     {
         ProfScope ps(h, SAP_KERNEL_SPMV, s);
-        HIP_TRY(launch_spmv(A, n, k, x, b, t, trans, s));
+        HIP_TRY(spmv_op(h, x, b, t, trans, 1, s));
     }
     TRY(dots(h, OP_NORM, {{t, t}}, s));
     double tn2 = 0;
@@ -916,7 +931,7 @@ int krylov_cg(sap_handle h, const double *b, double *x, double tol, int32_t maxi
     for (int32_t it = 0; it < maxit; ++it) {
         {
             ProfScope ps(h, SAP_KERNEL_SPMV, s);
-            HIP_TRY(launch_spmv(A, n, k, pv, nullptr, q, 0, s));        // q = A p
+            HIP_TRY(spmv_op(h, pv, nullptr, q, 0, 1, s));             // q = A p
         }
         TRY(dots(h, OP_CG_ALPHA, {{pv, q}}, s));
         TRY(update(h, UPD_CG_XR, x, OP_EXIT, 1, s));
@@ -928,7 +943,7 @@ int krylov_cg(sap_handle h, const double *b, double *x, double tol, int32_t maxi
         if (std::sqrt(nrm2) <= tol * bnorm) {
             {
                 ProfScope ps(h, SAP_KERNEL_SPMV, s);
-                HIP_TRY(launch_spmv(A, n, k, x, b, t, 0, s));              // t = b - A x
+                HIP_TRY(spmv_op(h, x, b, t, 0, 1, s));                     // t = b - A x
             }
             TRY(dots(h, OP_NORM, {{t, t}}, s));
             double tn2 = 0, b2 = 0;
@@ -956,7 +971,7 @@ int krylov_cg(sap_handle h, const double *b, double *x, double tol, int32_t maxi
     }
     {
         ProfScope ps(h, SAP_KERNEL_SPMV, s);
-        HIP_TRY(launch_spmv(A, n, k, x, b, t, 0, s));
+        HIP_TRY(spmv_op(h, x, b, t, 0, 1, s));
     }
     TRY(dots(h, OP_NORM, {{t, t}}, s));
     double tn2 = 0;
@@ -984,6 +999,8 @@ int factor_t(sap_handle h, const double *a_band, hipStream_t s)
     lu.status = h->ptr<int>(h->L.status);
     lu.with_ul = h->coupled ? 1 : 0;
     lu.wide = h->L.lwin ? h->ptr<double>(h->L.lwin) : nullptr;
+    if (h->coupled && h->prof && h->tev[0])     // tips phase clocks, zeroed ahead of the LU
+        HIP_TRY(launch_zero(h->ptr<unsigned long long>(h->L.ticks), 3 * sizeof(unsigned long long), s));
     {
         ProfScope ps(h, SAP_KERNEL_LU, s);
         HIP_TRY(launch_banded_lu<T>(lu, s));
@@ -1028,8 +1045,12 @@ int factor_t(sap_handle h, const double *a_band, hipStream_t s)
         ta.Rinv = h->ptr<T>(h->L.Rinv);
         ta.piv = h->ptr<int>(h->L.piv);
         ta.status = lu.status;
+        // phase clocks and events only while profiling (sap_tips_phase_times)
+        const bool phases = h->prof && h->tev[0];
+        ta.ticks = phases ? h->ptr<unsigned long long>(h->L.ticks) : nullptr;
+        h->phases_valid = phases;
         ProfScope ps(h, SAP_KERNEL_TIPS, s);
-        HIP_TRY(launch_tips<T>(ta, s));
+        HIP_TRY(launch_tips<T>(ta, s, phases ? h->tev : nullptr));
     }
     if (side) {
         HIP_TRY(hipEventRecord(h->join, h->side));
@@ -1157,6 +1178,8 @@ int sap_create(const sap_options *opt, void *workspace, size_t ws_bytes, sap_han
         if (h->h_status) (void)hipHostFree(h->h_status);
         for (auto &e : h->ev)
             if (e) (void)hipEventDestroy(e);
+        for (auto &e : h->tev)
+            if (e) (void)hipEventDestroy(e);
         if (h->join) (void)hipEventDestroy(h->join);
         if (h->side) (void)hipStreamDestroy(h->side);
         delete h;
@@ -1170,6 +1193,8 @@ int sap_create(const sap_options *opt, void *workspace, size_t ws_bytes, sap_han
         return cleanup(SAP_ERR_HIP, "hipHostGetDevicePointer failed");
     h->mapped = true;
     for (auto &e : h->ev)
+        if (hipEventCreate(&e) != hipSuccess) return cleanup(SAP_ERR_HIP, "hipEventCreate failed");
+    for (auto &e : h->tev)
         if (hipEventCreate(&e) != hipSuccess) return cleanup(SAP_ERR_HIP, "hipEventCreate failed");
     if (hipEventCreateWithFlags(&h->join, hipEventDisableTiming) != hipSuccess ||
         hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking) != hipSuccess)
@@ -1197,6 +1222,29 @@ int sap_solve_adjoint(sap_handle h, const double *g, double *lambda, double tol,
 {
     if (!h) return fail(SAP_ERR_INVALID, "null handle");
     return krylov(h, 1, g, lambda, tol, maxit, static_cast<hipStream_t>(stream), st);
+}
+
+int sap_solve_sparse(sap_handle h, sap_sparse sp, const double *b, double *x, double tol,
+                     int32_t maxit, void *stream, sap_stats *st)
+{
+    if (!h) return fail(SAP_ERR_INVALID, "null handle");
+    CsrDev m{};
+    double *bhat = nullptr, *yhat = nullptr;
+    const int32_t *new_row = nullptr, *new_col = nullptr;
+    const double *rs = nullptr, *cs = nullptr;
+    if (!sparse_plan_parts(sp, &m, &bhat, &yhat, &new_row, &new_col, &rs, &cs))
+        return fail(SAP_ERR_STATE, "null plan, or sap_sparse_assemble has not been called");
+    if (m.n != h->opt.n || sparse_plan_k(sp) != h->opt.k)
+        return fail(SAP_ERR_INVALID, "the handle's N and K must be the plan's");
+    if (!b || !x) return fail(SAP_ERR_INVALID, "null vector pointer");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    HIP_TRY(launch_map_vec(b, new_row, rs, bhat, m.n, 0, s));      // b_hat = P D_r Q b
+    h->csr = &m;
+    const int rc = krylov(h, 0, bhat, yhat, tol, maxit, s, st);
+    h->csr = nullptr;
+    if (rc < 0) return rc;
+    HIP_TRY(launch_map_vec(yhat, new_col, cs, x, m.n, 1, s));      // x = D_c P^T y_hat
+    return rc;
 }
 
 int sap_solve_batch(sap_handle h, const double *B, double *X, int32_t m, double tol,
@@ -1340,6 +1388,37 @@ int sap_get_factor_rows(sap_handle h, int32_t which, int64_t j0, int64_t count, 
     return SAP_OK;
 }
 
+int sap_tips_phase_times(sap_handle h, double *ms, void *stream)
+{
+    if (!h) return fail(SAP_ERR_INVALID, "null handle");
+    if (!ms) return fail(SAP_ERR_INVALID, "ms is null");
+    if (!h->factored) return fail(SAP_ERR_STATE, "sap_factor has not been called");
+    ms[0] = ms[1] = ms[2] = 0.0;
+    if (!h->coupled) return SAP_OK;
+    if (!h->phases_valid)
+        return fail(SAP_ERR_STATE, "phase times are recorded only while sap_profile is on");
+    HIP_TRY(hipEventSynchronize(h->tev[3]));
+    float span = 0.0f;
+    HIP_TRY(hipEventElapsedTime(&span, h->tev[0], h->tev[3]));
+    if (!tips_in_lds(h->opt.k, h->fp32)) {          // one launch group per phase
+        float t1 = 0.0f, t2 = 0.0f;
+        HIP_TRY(hipEventElapsedTime(&t1, h->tev[0], h->tev[1]));
+        HIP_TRY(hipEventElapsedTime(&t2, h->tev[1], h->tev[2]));
+        ms[0] = t1;
+        ms[1] = t2;
+        ms[2] = span - t1 - t2;
+        return SAP_OK;
+    }
+    // one kernel: its time split by the workgroups' summed phase clocks
+    unsigned long long tk[3] = {0, 0, 0};
+    HIP_TRY(hipMemcpyAsync(tk, h->ptr<unsigned long long>(h->L.ticks), sizeof(tk),
+                           hipMemcpyDeviceToHost, static_cast<hipStream_t>(stream)));
+    HIP_TRY(hipStreamSynchronize(static_cast<hipStream_t>(stream)));
+    const double tot = (double)tk[0] + (double)tk[1] + (double)tk[2];
+    for (int q = 0; q < 3; ++q) ms[q] = tot > 0.0 ? span * (double)tk[q] / tot : 0.0;
+    return SAP_OK;
+}
+
 int sap_profile(sap_handle h, int32_t enable)
 {
     if (!h) return fail(SAP_ERR_INVALID, "null handle");
@@ -1382,6 +1461,8 @@ int sap_destroy(sap_handle h)
         (void)hipHostFree(h->h_status);
     }
     for (auto &e : h->ev)
+        if (e) (void)hipEventDestroy(e);
+    for (auto &e : h->tev)
         if (e) (void)hipEventDestroy(e);
     if (h->side) {
         (void)hipStreamSynchronize(h->side);

@@ -29,6 +29,10 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "sap.h"
+
+#include <string>
+
 namespace sap {
 
 constexpr int kMaxK = 255;
@@ -122,9 +126,13 @@ struct TipsArgs {
     T *B, *C, *V, *W, *Rbar, *Rlu, *Rinv;
     int *piv;
     int *status;
+    unsigned long long *ticks;   // [3] per-phase workgroup time (LDS form), or null
 };
+// ev: 4 events (nullable) around the phases, see k_tips.hip
 template <typename T>
-hipError_t launch_tips(const TipsArgs<T> &a, hipStream_t s);
+hipError_t launch_tips(const TipsArgs<T> &a, hipStream_t s, hipEvent_t *ev = nullptr);
+// whether the tips of this K and precision run as the single LDS kernel
+bool tips_in_lds(int k, bool fp32);
 
 // ------------------------------------------------------------------ sweeps
 // One triangular sweep per diagonal block.  fwd: steps j = 0..nb-1 pushing
@@ -275,6 +283,26 @@ struct UpdArgs {
 hipError_t launch_update(const UpdArgs &a, hipStream_t s);
 
 hipError_t launch_fill(double *v, double val, int64_t n, hipStream_t s);
+
+// ------------------------------------------------------------- sparse A
+// A reordered sparse matrix on the device (CSR), for the Krylov product
+struct CsrDev {
+    int64_t n;
+    const int64_t *rowptr;
+    const int32_t *colidx;
+    const double *vals;
+};
+hipError_t launch_csr_spmv(const CsrDev &m, const double *v, const double *b, double *y,
+                           hipStream_t s);
+hipError_t launch_map_vec(const double *in, const int32_t *map, const double *scale, double *out,
+                          int64_t n, int gather, hipStream_t s);
+// records an error for sap_last_error and returns code (sap_api.hip)
+int api_fail(int code, const std::string &msg);
+// the plan's device pieces (sparse_front.hip); false before sap_sparse_assemble
+bool sparse_plan_parts(sap_sparse p, CsrDev *m, double **bhat, double **yhat,
+                       const int32_t **new_row, const int32_t **new_col, const double **rs,
+                       const double **cs);
+int sparse_plan_k(sap_sparse p);
 hipError_t launch_zero(void *p, size_t bytes, hipStream_t s);   // bytes % 4 == 0
 hipError_t launch_partition_starts(int64_t *starts, int64_t n, int p, hipStream_t s);
 

@@ -35,7 +35,8 @@ EXPORTED = ("sap_workspace_bytes", "sap_create", "sap_factor", "sap_solve",
             "sap_solve_adjoint", "sap_band_grad", "sap_handle_status", "sap_spmv",
             "sap_precond_apply", "sap_get_tips", "sap_profile", "sap_kernel_time",
             "sap_destroy", "sap_last_error", "sap_solve_noalloc", "sap_solve_cg", "sap_solve_batch",
-            "sap_get_factor_rows")
+            "sap_get_factor_rows", "sap_tips_phase_times", "sap_sparse_create",
+            "sap_sparse_info", "sap_sparse_assemble", "sap_solve_sparse", "sap_sparse_destroy")
 
 KERNELS = ("norm", "lu", "tips", "sweep", "corr", "spmv", "krylov", "xfer")
 
@@ -96,6 +97,12 @@ def load_library(path: str = LIB_PATH):
     lib.sap_precond_apply.argtypes = [vp, vp, vp, i32, vp]
     lib.sap_get_tips.argtypes = [vp, i32, vp, vp, vp, vp]
     lib.sap_get_factor_rows.argtypes = [vp, i32, i64, i64, vp, vp]
+    lib.sap_tips_phase_times.argtypes = [vp, vp, vp]
+    lib.sap_sparse_create.argtypes = [i64, vp, vp, vp, i32, i32, dbl, P(vp)]
+    lib.sap_sparse_info.argtypes = [vp, P(i32), P(i32), vp, vp, vp, vp]
+    lib.sap_sparse_assemble.argtypes = [vp, vp, vp, vp]
+    lib.sap_solve_sparse.argtypes = [vp, vp, vp, vp, dbl, i32, vp, P(sap_stats)]
+    lib.sap_sparse_destroy.argtypes = [vp]
     lib.sap_profile.argtypes = [vp, i32]
     lib.sap_kernel_time.argtypes = [vp, i32, P(dbl), P(i64)]
     lib.sap_destroy.argtypes = [vp]
@@ -228,6 +235,19 @@ class SapSolver:
             _check(rc)
         return X, [SapStats(**st.as_dict(), status=rc) for st in sts]
 
+    def solve_sparse(self, sp: "SapSparse", b: torch.Tensor, x: torch.Tensor | None = None,
+                     tol: float = 1e-10, maxit: int = 200, raise_nc: bool = False):
+        """sap_solve_sparse: A x = b through the plan's reordering, with this
+        handle's preconditioner (factored on sp.assemble's band)."""
+        x = torch.empty_like(b) if x is None else x
+        st = sap_stats()
+        rc = load_library().sap_solve_sparse(self.handle, sp.plan, _dptr(b, self.n, "b"),
+                                             _dptr(x, self.n, "x"), float(tol), int(maxit),
+                                             _stream(), ctypes.byref(st))
+        if rc not in (SAP_OK, SAP_NOT_CONVERGED) or (rc == SAP_NOT_CONVERGED and raise_nc):
+            _check(rc)
+        return x, SapStats(**st.as_dict(), status=rc)
+
     def solve_cg(self, b: torch.Tensor, x: torch.Tensor | None = None, tol: float = 1e-10,
                  maxit: int = 500, raise_nc: bool = False):
         """sap_solve_cg: preconditioned conjugate gradient for SPD A."""
@@ -279,6 +299,12 @@ class SapSolver:
             out[name] = (ms.value, cnt.value)
         return out
 
+    def tips_phase_times(self) -> dict:
+        """T_BC, T_SPK, T_LUrdcd (ms) of the last factorization (Sec. 3.4)."""
+        ms = (ctypes.c_double * 3)()
+        _check(load_library().sap_tips_phase_times(self.handle, ms, _stream()))
+        return {"t_bc_ms": ms[0], "t_spk_ms": ms[1], "t_lurdcd_ms": ms[2]}
+
     def factor_rows(self, which: str, j0: int = 0, count: int | None = None):
         """Rows of a factor coefficient array ("Lc", "Uc", "Lr", "Ur") as a
         (count, K+1) float64 array (sap_get_factor_rows)."""
@@ -298,6 +324,58 @@ class SapSolver:
             self.handle, i, v.ctypes.data_as(ctypes.c_void_p), w.ctypes.data_as(ctypes.c_void_p),
             rb.ctypes.data_as(ctypes.c_void_p), _stream()))
         return v.reshape(self.k, self.k), w.reshape(self.k, self.k), rb.reshape(self.k, self.k)
+
+
+class SapSparse:
+    """Sparse front end (sap_sparse_*): host CSR in, reorderings on the host,
+    the band and the reordered values built on the GPU."""
+
+    def __init__(self, n: int, rowptr, colidx, vals, db: bool = True, cm: bool = True,
+                 drop_frac: float = 0.0):
+        import numpy as np
+        lib = load_library()
+        self.n = n
+        self._rowptr = np.ascontiguousarray(rowptr, dtype=np.int64)
+        self._colidx = np.ascontiguousarray(colidx, dtype=np.int32)
+        self._vals = np.ascontiguousarray(vals, dtype=np.float64)
+        h = ctypes.c_void_p(0)
+        _check(lib.sap_sparse_create(n, self._rowptr.ctypes.data_as(ctypes.c_void_p),
+                                     self._colidx.ctypes.data_as(ctypes.c_void_p),
+                                     self._vals.ctypes.data_as(ctypes.c_void_p), int(db), int(cm),
+                                     float(drop_frac), ctypes.byref(h)))
+        self.plan = h
+        self.k = self.info()["k"]
+
+    def info(self) -> dict:
+        import numpy as np
+        k, kf = ctypes.c_int32(0), ctypes.c_int32(0)
+        nr, nc = np.zeros(self.n, dtype=np.int32), np.zeros(self.n, dtype=np.int32)
+        rs, cs = np.zeros(self.n), np.zeros(self.n)
+        vp = ctypes.c_void_p
+        _check(load_library().sap_sparse_info(self.plan, ctypes.byref(k), ctypes.byref(kf),
+                                              nr.ctypes.data_as(vp), nc.ctypes.data_as(vp),
+                                              rs.ctypes.data_as(vp), cs.ctypes.data_as(vp)))
+        return {"k": k.value, "k_full": kf.value, "new_row": nr, "new_col": nc,
+                "row_scale": rs, "col_scale": cs}
+
+    def assemble(self, vals: torch.Tensor, band: torch.Tensor | None = None) -> torch.Tensor:
+        """The band of A_hat (device) from A's values (device, CSR order)."""
+        w = (2 * self.k + 1) * self.n
+        band = torch.empty(w, dtype=torch.float64, device=vals.device) if band is None else band
+        _check(load_library().sap_sparse_assemble(self.plan, _dptr(vals, vals.numel(), "vals"),
+                                                  _dptr(band, w, "band"), _stream()))
+        return band
+
+    def close(self):
+        if getattr(self, "plan", None) and self.plan.value:
+            load_library().sap_sparse_destroy(self.plan)
+            self.plan = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 NOALLOC_SCRATCH_BYTES = 64 << 20     # SAP_NOALLOC_SCRATCH_BYTES

@@ -58,6 +58,7 @@ STREAM_XTRUE = 2
 STREAM_ROWSCALE = 3
 STREAM_XTARGET = 4
 STREAM_PICK = 5
+STREAM_SPARSE = 6        # sparse workloads: pattern, values, permutations
 
 _M64 = np.uint64(0xFFFFFFFFFFFFFFFF)
 _GOLDEN = np.uint64(0x9E3779B97F4A7C15)
@@ -195,6 +196,78 @@ def dense_to_band(a: np.ndarray, k: int, pad: float = 0.0) -> np.ndarray:
         c = cols[max(0, -delta):n - max(0, delta)]
         b2[q, c] = a[c + delta, c]
     return b2.reshape(-1)
+
+
+@dataclass
+class SparseProblem:
+    n: int
+    rowptr: np.ndarray      # int64, n+1
+    colidx: np.ndarray      # int32, nnz (sorted within each row)
+    vals: np.ndarray        # float64, nnz
+    x_true: np.ndarray
+    b: np.ndarray
+    k0: int                 # half-bandwidth of the hidden banded matrix
+
+    def dense(self) -> np.ndarray:
+        a = np.zeros((self.n, self.n))
+        for r in range(self.n):
+            lo, hi = self.rowptr[r], self.rowptr[r + 1]
+            a[r, self.colidx[lo:hi]] = self.vals[lo:hi]
+        return a
+
+
+def _perm(seed: int, salt: int, n: int) -> np.ndarray:
+    """A permutation of 0..n-1: the ranks of n uniform draws (index salt*n+i)."""
+    u = splitmix64_uniform(seed, STREAM_SPARSE, salt * n + np.arange(n, dtype=np.uint64))
+    return np.argsort(u, kind="stable").astype(np.int64)
+
+
+def make_sparse_problem(n: int, k0: int, density: float = 0.3, d: float = 1.5,
+                        seed: int = 0) -> SparseProblem:
+    """A sparse system whose structure hides a banded, diagonally dominant
+    matrix (the kind of input the reordering front end of Sec. 3.1 is for):
+
+    * B: half-bandwidth k0; each off-diagonal slot (r, c), 0 < |r-c| <= k0,
+      is a nonzero with probability `density` (stream 6, index
+      r*(2 k0 + 1) + (c - r + k0), value mapped from [-1, 1)), its value the
+      stream-0 draw of that slot; b_rr = s_r d sum|b_rc| as for the dense
+      workloads (at least d if the row has no off-diagonal);
+    * A = S R B S^T: R a random row permutation (moves the heavy diagonal off
+      the diagonal), S a random symmetric permutation (scatters the band);
+      both from stream 6 (salts 1 and 2);
+    * x_true ~ U[-1, 1) (stream 2), b = A x_true."""
+    w = 2 * k0 + 1
+    rows, cols, vals = [], [], []
+    diag = np.zeros(n)
+    for delta in range(-k0, k0 + 1):
+        if delta == 0:
+            continue
+        c = np.arange(max(0, -delta), n - max(0, delta), dtype=np.int64)
+        r = c + delta
+        slot = r * w + (c - r + k0)
+        keep = splitmix64_uniform(seed, STREAM_SPARSE, (slot + 3 * n).astype(np.uint64)) * 0.5 + 0.5 < density
+        v = splitmix64_uniform(seed, STREAM_OFFDIAG, slot.astype(np.uint64))
+        rows.append(r[keep]); cols.append(c[keep]); vals.append(v[keep])
+        np.add.at(diag, r[keep], np.abs(v[keep]))
+    sign = np.where(splitmix64_uniform(seed, STREAM_SIGN, np.arange(n, dtype=np.uint64)) < 0.0,
+                    -1.0, 1.0)
+    dval = sign * d * np.where(diag > 0, diag, 1.0)
+    rows.append(np.arange(n)); cols.append(np.arange(n)); vals.append(dval)
+    r = np.concatenate(rows); c = np.concatenate(cols); v = np.concatenate(vals)
+    R = _perm(seed, 1, n)          # row r of B becomes row R[r]
+    S = _perm(seed, 2, n)          # index i becomes S[i] (rows and columns)
+    r2 = S[R[r]]
+    c2 = S[c]
+    order = np.lexsort((c2, r2))
+    r2, c2, v = r2[order], c2[order], v[order]
+    rowptr = np.zeros(n + 1, dtype=np.int64)
+    np.add.at(rowptr, r2 + 1, 1)
+    rowptr = np.cumsum(rowptr)
+    x_true = splitmix64_uniform(seed, STREAM_XTRUE, np.arange(n, dtype=np.uint64))
+    b = np.zeros(n)
+    np.add.at(b, r2, v * x_true[c2])
+    return SparseProblem(n=n, rowptr=rowptr, colidx=c2.astype(np.int32), vals=v,
+                         x_true=x_true, b=b, k0=k0)
 
 
 # The five workloads: sizes, dominance, partitions, mode and precisions.

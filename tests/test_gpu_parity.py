@@ -476,3 +476,32 @@ def test_lu_rows_parity(n, k, p, prec):
     for which in ("Lc", "Uc"):
         assert_close(s.factor_rows(which), oracle_factor_rows(M, which), tol, which)
     s.close()
+
+
+@pytest.mark.parametrize("n,k,p,prec", [(20011, 50, 16, "fp64"), (20011, 50, 16, "fp32"),
+                                        (12000, 150, 12, "fp32")])
+def test_tips_phase_times(n, k, p, prec):
+    """The T_BC / T_SPK / T_LUrdcd split of the SaP-C preprocessing (Sec.
+    3.4): three non-negative times that add up to the tips' event time, for
+    the one-kernel form (K = 50) and the per-phase launches (K = 150)."""
+    case("phases", n, k, p, prec)
+    pb = sapgen.make_problem(n, k, seed=60)
+    from paper_1509_07919_amd import SapError
+    s = solver(n, k, p, prec=prec)
+    s.factor(dev(pb.band))
+    with pytest.raises(SapError):                     # recorded only while profiling
+        s.tips_phase_times()
+    s.profile(True)
+    s.factor(dev(pb.band))
+    _, st = s.solve(dev(pb.b), tol=1e-10)
+    s.profile(False)
+    ph = s.tips_phase_times()
+    vals = [ph["t_bc_ms"], ph["t_spk_ms"], ph["t_lurdcd_ms"]]
+    assert all(v >= 0.0 for v in vals) and sum(vals) > 0.0
+    # the phases lie inside the factorization's span
+    assert sum(vals) <= st.t_factor_ms * 1.05 + 1e-3
+    d = solver(n, k, p, mode="decoupled", prec=prec)
+    d.factor(dev(pb.band))
+    assert d.tips_phase_times() == {"t_bc_ms": 0.0, "t_spk_ms": 0.0, "t_lurdcd_ms": 0.0}
+    s.close()
+    d.close()

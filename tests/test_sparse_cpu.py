@@ -1,0 +1,99 @@
+"""Sparse front end on the host (no GPU): the library's diagonal boosting,
+Cuthill-McKee and drop-off against the oracle (oracle/sparse.py), and the
+oracle's matching against brute force."""
+
+import itertools
+
+import numpy as np
+import pytest
+
+import oracle.sparse as osp
+import sapgen
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1509_07919_amd import sap
+    return sap.load_library()
+
+
+def plan(sp, db=True, cm=True, drop=0.0):
+    from paper_1509_07919_amd import SapSparse
+    return SapSparse(sp.n, sp.rowptr, sp.colidx, sp.vals, db=db, cm=cm, drop_frac=drop)
+
+
+@pytest.mark.parametrize("n", [3, 5, 7])
+def test_oracle_matching_is_the_brute_force_optimum(n):
+    """min over all permutations of sum c_{i sigma_i} (eq:DBrelated)."""
+    rng_u = sapgen.splitmix64_uniform(70 + n, 6, np.arange(n * n)).reshape(n, n)
+    A = np.where(np.abs(rng_u) < 0.6, rng_u, 0.0) + np.eye(n)[::-1] * 0.05
+    rows, cols = np.nonzero(A)
+    rowptr = np.concatenate([[0], np.cumsum(np.bincount(rows, minlength=n))])
+    sigma, cost = osp.db_matching(n, rowptr, cols, A[rows, cols])
+    amax = np.abs(A).max(axis=1)
+    best = min(sum(np.log(amax[i]) - np.log(abs(A[i, p[i]])) if A[i, p[i]] != 0 else np.inf
+                   for i in range(n)) for p in itertools.permutations(range(n)))
+    assert abs(cost - best) <= 1e-12
+    assert sorted(sigma) == list(range(n))
+
+
+@pytest.mark.parametrize("n,k0,density,seed", [(500, 4, 0.5, 1), (3000, 10, 0.3, 2),
+                                               (4000, 25, 0.15, 3)])
+def test_db_matching_cost_and_i_matrix(n, k0, density, seed):
+    sp = sapgen.make_sparse_problem(n, k0, density=density, seed=seed)
+    info = plan(sp, db=True, cm=False).info()
+    sigma = info["new_row"]
+    assert sorted(sigma) == list(range(n))
+    cost = osp.matching_cost(n, sp.rowptr, sp.colidx, sp.vals, sigma)
+    _, best = osp.db_matching(n, sp.rowptr, sp.colidx, sp.vals)
+    assert abs(cost - best) <= 1e-9 * max(1.0, abs(best))
+    # D_r A D_c is an I-matrix: |entries| <= 1, = 1 on the matched ones
+    rows = np.repeat(np.arange(n), np.diff(sp.rowptr))
+    s = np.abs(info["row_scale"][rows] * sp.vals * info["col_scale"][sp.colidx])
+    assert s.max() <= 1.0 + 1e-12
+    matched = sigma[rows] == sp.colidx
+    assert np.allclose(s[matched], 1.0, rtol=1e-12, atol=0)
+
+
+@pytest.mark.parametrize("n,k0,density,seed", [(500, 4, 0.5, 1), (3000, 10, 0.3, 2),
+                                               (4000, 25, 0.15, 3)])
+def test_cuthill_mckee_and_drop_equal_the_oracle(n, k0, density, seed):
+    """The same ordering as the oracle's Cuthill-McKee on the boosted
+    structure (deterministic tie-breaks), the same half-bandwidth, and the
+    same drop-off K for several fractions."""
+    sp = sapgen.make_sparse_problem(n, k0, density=density, seed=seed)
+    sigma = plan(sp, db=True, cm=False).info()["new_row"].astype(np.int64)
+    B = osp.permute_csr(n, sp.rowptr, sp.colidx, sp.vals, sigma, np.arange(n))
+    order, kk = osp.cuthill_mckee(n, B.indptr, B.indices)
+    pos = np.empty(n, dtype=np.int64)
+    pos[order] = np.arange(n)
+    full = plan(sp).info()
+    assert np.array_equal(full["new_col"], pos)
+    assert np.array_equal(full["new_row"], pos[sigma])
+    assert full["k_full"] == kk
+    Ah = osp.permute_csr(n, sp.rowptr, sp.colidx, sp.vals, full["new_row"], full["new_col"],
+                         full["row_scale"], full["col_scale"])
+    assert osp.half_bandwidth(n, Ah.indptr, Ah.indices, np.arange(n)) == kk
+    for frac in (1e-3, 2e-2):
+        assert plan(sp, drop=frac).info()["k"] == osp.drop_k(n, Ah.indptr, Ah.indices, Ah.data, frac)
+    assert kk <= 3 * k0                     # the hidden band is recovered
+
+
+def test_without_reordering_is_the_identity():
+    sp = sapgen.make_sparse_problem(800, 5, seed=4)
+    info = plan(sp, db=False, cm=False).info()
+    assert np.array_equal(info["new_row"], np.arange(800))
+    assert np.array_equal(info["new_col"], np.arange(800))
+    assert np.all(info["row_scale"] == 1.0) and np.all(info["col_scale"] == 1.0)
+
+
+def test_structurally_singular_is_reported(lib):
+    from paper_1509_07919_amd import SapError, sap
+    # rows 0 and 1 both only in column 0
+    rowptr = np.array([0, 1, 2, 4], dtype=np.int64)
+    colidx = np.array([0, 0, 1, 2], dtype=np.int32)
+    vals = np.array([1.0, 2.0, 3.0, 4.0])
+    from paper_1509_07919_amd import SapSparse
+    with pytest.raises(SapError) as e:
+        SapSparse(3, rowptr, colidx, vals)
+    assert e.value.code == sap.SAP_ERR_SINGULAR
