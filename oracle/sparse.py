@@ -6,9 +6,13 @@ preconditioner is built on (paper: Li, Serban, Negrut, arXiv:1509.07919):
 * ``db_cost`` / ``db_matching`` -- diagonal boosting (Sec. 3.1, "Diagonal
   Boosting"): a row permutation maximising prod |a_{i sigma_i}|, as the
   minimum-cost perfect bipartite matching with costs
-  c_ij = log a_i - log |a_ij|, a_i = max_j |a_ij| (eq:DBrelated).  The
-  matching itself is a library step (SciPy's min_weight_full_bipartite_
-  matching); it is pinned against brute force on small matrices.
+  c_ij = log a_i - log |a_ij|, a_i = max_j |a_ij| (eq:DBrelated), found
+  by successive shortest augmenting paths (the Hungarian method with
+  Dijkstra's algorithm on reduced costs; Kuhn 1955, Edmonds-Karp 1972),
+  whose dual potentials u, v give the I-matrix scaling
+  exp(u_i)/a_i, exp(v_j).  Pinned against brute force on small matrices
+  and against SciPy's min_weight_full_bipartite_matching (a library
+  routine, fast on some inputs and not on others, so only the former).
 * ``cuthill_mckee`` -- bandwidth reduction (Sec. 3.1, "Bandwidth
   reduction"; Sec. 3.3): Cuthill-McKee on the structure of B + B^T, a
   breadth-first search that visits the neighbours of each node in
@@ -48,15 +52,103 @@ def db_costs(n, rowptr, colidx, vals) -> sps.csr_matrix:
 
 def db_matching(n, rowptr, colidx, vals):
     """sigma[i] = column matched to row i in a minimum-cost perfect matching,
-    and that minimum cost sum_i c_{i sigma_i}."""
+    and that minimum cost sum_i c_{i sigma_i}.  (sigma, cost, u, v) with
+    ``duals=True`` via db_matching_duals."""
+    sigma, cost, _, _ = db_matching_duals(n, rowptr, colidx, vals)
+    return sigma, cost
+
+
+def db_matching_duals(n, rowptr, colidx, vals):
+    """Minimum-cost perfect matching by successive shortest augmenting paths.
+
+    Dual feasibility: reduced costs r_ij = c_ij - u_i - v_j >= 0 on every
+    edge, = 0 on matched edges (then the matching is optimal).  Start:
+    v_j = min_i c_ij, u_i = min_j (c_ij - v_j), and each row takes a free
+    column of zero reduced cost if it has one.  For every row i0 still
+    free: Dijkstra from i0 over alternating paths (row -> column along an
+    edge, length r_ij; column -> its matched row, length 0) until the
+    nearest free column j* is popped, at distance L; augment along the path;
+    every row i reached at distance d_i gets u_i += L - d_i and every column
+    j popped at distance d_j gets v_j -= L - d_j, which keeps r >= 0 and
+    makes the new path's edges tight.  Raises ValueError if A has no
+    perfect matching (structurally singular)."""
+    C = db_costs(n, rowptr, colidx, vals)
+    ptr, col, cost = C.indptr, C.indices, C.data
+    inf = float("inf")
+    v = np.full(n, inf)
+    for i in range(n):
+        for e in range(ptr[i], ptr[i + 1]):
+            v[col[e]] = min(v[col[e]], cost[e])
+    if np.isinf(v).any():
+        raise ValueError("structurally singular: an empty column")
+    u = np.zeros(n)
+    row_of = np.full(n, -1, dtype=np.int64)        # column -> matched row
+    sigma = np.full(n, -1, dtype=np.int64)         # row -> matched column
+    for i in range(n):
+        if ptr[i] == ptr[i + 1]:
+            raise ValueError("structurally singular: an empty row")
+        u[i] = min(cost[e] - v[col[e]] for e in range(ptr[i], ptr[i + 1]))
+        for e in range(ptr[i], ptr[i + 1]):
+            j = col[e]
+            if row_of[j] < 0 and cost[e] - v[j] - u[i] == 0.0:
+                row_of[j], sigma[i] = i, j
+                break
+    for i0 in range(n):
+        if sigma[i0] >= 0:
+            continue
+        dist = {}                  # column -> tentative distance
+        via = {}                   # column -> row it was reached from
+        done = {}                  # column -> final distance
+        rows = {i0: 0.0}           # rows reached -> their distance
+        heap = []
+        i, di = i0, 0.0
+        jstar = -1
+        while True:
+            for e in range(ptr[i], ptr[i + 1]):
+                j = col[e]
+                if j in done:
+                    continue
+                nd = di + (cost[e] - u[i] - v[j])
+                if nd < dist.get(j, inf):
+                    dist[j], via[j] = nd, i
+                    heapq.heappush(heap, (nd, j))
+            while heap and (heap[0][1] in done or heap[0][0] > dist[heap[0][1]]):
+                heapq.heappop(heap)
+            if not heap:
+                raise ValueError("structurally singular: no augmenting path")
+            dj, j = heapq.heappop(heap)
+            done[j] = dj
+            if row_of[j] < 0:
+                jstar, L = j, dj
+                break
+            i, di = row_of[j], dj
+            rows[i] = di
+        for i, di in rows.items():
+            u[i] += L - di
+        for j, dj in done.items():
+            v[j] -= L - dj
+        j = jstar
+        while True:                # flip the path back to i0
+            i = via[j]
+            nxt = sigma[i]
+            sigma[i], row_of[j] = j, i
+            if i == i0:
+                break
+            j = nxt
+    total = float(sum(C[i, sigma[i]] for i in range(n)))
+    return sigma, total, u, v
+
+
+def db_matching_scipy(n, rowptr, colidx, vals):
+    """The same optimum from SciPy's min_weight_full_bipartite_matching
+    (edge weights shifted by +1 so that zero costs stay edges)."""
     C = db_costs(n, rowptr, colidx, vals)
     W = C.copy()
-    W.data = W.data + 1.0            # every edge positive (zero weights would vanish)
+    W.data = W.data + 1.0
     r, c = min_weight_full_bipartite_matching(W)
     sigma = np.empty(n, dtype=np.int64)
     sigma[r] = c
-    cost = float(sum(C[i, sigma[i]] for i in range(n)))
-    return sigma, cost
+    return sigma, float(sum(C[i, sigma[i]] for i in range(n)))
 
 
 def matching_cost(n, rowptr, colidx, vals, sigma) -> float:

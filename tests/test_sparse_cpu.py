@@ -22,7 +22,7 @@ def plan(sp, db=True, cm=True, drop=0.0):
     return SapSparse(sp.n, sp.rowptr, sp.colidx, sp.vals, db=db, cm=cm, drop_frac=drop)
 
 
-@pytest.mark.parametrize("n", [3, 5, 7])
+@pytest.mark.parametrize("n", [3, 5, 7, 8])
 def test_oracle_matching_is_the_brute_force_optimum(n):
     """min over all permutations of sum c_{i sigma_i} (eq:DBrelated)."""
     rng_u = sapgen.splitmix64_uniform(70 + n, 6, np.arange(n * n)).reshape(n, n)
@@ -45,8 +45,12 @@ def test_db_matching_cost_and_i_matrix(n, k0, density, seed):
     sigma = info["new_row"]
     assert sorted(sigma) == list(range(n))
     cost = osp.matching_cost(n, sp.rowptr, sp.colidx, sp.vals, sigma)
-    _, best = osp.db_matching(n, sp.rowptr, sp.colidx, sp.vals)
+    sigma_o, best = osp.db_matching(n, sp.rowptr, sp.colidx, sp.vals)
     assert abs(cost - best) <= 1e-9 * max(1.0, abs(best))
+    # continuous random values: the optimum is unique, so the matchings agree
+    assert np.array_equal(sigma, sigma_o)
+    sigma_s, cost_s = osp.db_matching_scipy(n, sp.rowptr, sp.colidx, sp.vals)
+    assert np.array_equal(sigma_o, sigma_s) and abs(cost_s - best) <= 1e-9 * max(1.0, best)
     # D_r A D_c is an I-matrix: |entries| <= 1, = 1 on the matched ones
     rows = np.repeat(np.arange(n), np.diff(sp.rowptr))
     s = np.abs(info["row_scale"][rows] * sp.vals * info["col_scale"][sp.colidx])
@@ -62,7 +66,7 @@ def test_cuthill_mckee_and_drop_equal_the_oracle(n, k0, density, seed):
     structure (deterministic tie-breaks), the same half-bandwidth, and the
     same drop-off K for several fractions."""
     sp = sapgen.make_sparse_problem(n, k0, density=density, seed=seed)
-    sigma = plan(sp, db=True, cm=False).info()["new_row"].astype(np.int64)
+    sigma = osp.db_matching(n, sp.rowptr, sp.colidx, sp.vals)[0].astype(np.int64)
     B = osp.permute_csr(n, sp.rowptr, sp.colidx, sp.vals, sigma, np.arange(n))
     order, kk = osp.cuthill_mckee(n, B.indptr, B.indices)
     pos = np.empty(n, dtype=np.int64)
@@ -97,3 +101,17 @@ def test_structurally_singular_is_reported(lib):
     with pytest.raises(SapError) as e:
         SapSparse(3, rowptr, colidx, vals)
     assert e.value.code == sap.SAP_ERR_SINGULAR
+
+
+@pytest.mark.parametrize("n,k0,density,seed", [(300, 3, 0.6, 21), (2000, 8, 0.3, 22)])
+def test_oracle_duals_are_feasible_and_tight(n, k0, density, seed):
+    """Reduced costs c_ij - u_i - v_j >= 0 on every edge and 0 on the
+    matched ones (LP duality: the matching is then optimal), so
+    exp(u_i)/a_i |a_ij| exp(v_j) <= 1 with equality on the matching."""
+    sp = sapgen.make_sparse_problem(n, k0, density=density, seed=seed)
+    sigma, cost, u, v = osp.db_matching_duals(n, sp.rowptr, sp.colidx, sp.vals)
+    C = osp.db_costs(n, sp.rowptr, sp.colidx, sp.vals).tocoo()
+    red = C.data - u[C.row] - v[C.col]
+    assert red.min() >= -1e-12
+    assert np.abs(red[sigma[C.row] == C.col]).max() <= 1e-12
+    assert abs(u.sum() + v.sum() - cost) <= 1e-9 * max(1.0, cost)
