@@ -156,9 +156,11 @@ int sap_solve(sap_handle h, const double *b, double *x, double tol,
  * diagonal blocks (it needs full spikes). */
 typedef struct sap_sparse_ *sap_sparse;
 
-/* Analyse A given as host CSR (rowptr: N+1 int64, rowptr[0] = 0; colidx:
- * rowptr[N] int32 column indices; vals: doubles; explicit zeros are not
- * edges of the matching).  db, cm: nonzero to apply diagonal boosting and
+/* Analyse A given as host CSR (rowptr: N+1 int64, rowptr[0] = 0,
+ * non-decreasing; colidx: rowptr[N] int32 column indices in [0, N), each at
+ * most once per row, any order; vals: finite doubles; explicit zeros are
+ * not edges of the matching; 1 <= N < 2^31).  Violations return
+ * SAP_ERR_INVALID.  db, cm: nonzero to apply diagonal boosting and
  * Cuthill-McKee.  drop_frac in [0, 1): K is the least half-bandwidth whose
  * outside entries carry at most drop_frac of sum |a_hat| (0: every entry in
  * the band).  The reorderings run on the host; the plan keeps the reordered

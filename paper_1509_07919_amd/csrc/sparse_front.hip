@@ -28,6 +28,7 @@
 #include "sap_internal.h"
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <limits>
 #include <numeric>
@@ -374,7 +375,8 @@ int sap_sparse_create(int64_t n, const int64_t *rowptr, const int32_t *colidx, c
 {
     if (!out) return sfail(SAP_ERR_INVALID, "output pointer is null");
     *out = nullptr;
-    if (n < 1 || !rowptr || !colidx || !vals) return sfail(SAP_ERR_INVALID, "bad CSR arguments");
+    if (n < 1 || n > INT32_MAX || !rowptr || !colidx || !vals)
+        return sfail(SAP_ERR_INVALID, "bad CSR arguments");
     if (!(drop_frac >= 0.0 && drop_frac < 1.0)) return sfail(SAP_ERR_INVALID, "drop_frac must be in [0, 1)");
     if (rowptr[0] != 0) return sfail(SAP_ERR_INVALID, "rowptr[0] must be 0");
     Csr a;
@@ -387,6 +389,17 @@ int sap_sparse_create(int64_t n, const int64_t *rowptr, const int32_t *colidx, c
     a.val.assign(vals, vals + nnz);
     for (int64_t e = 0; e < nnz; ++e)
         if (a.col[e] < 0 || a.col[e] >= n) return sfail(SAP_ERR_INVALID, "column index out of range");
+    for (int64_t e = 0; e < nnz; ++e)
+        if (!std::isfinite(a.val[e])) return sfail(SAP_ERR_INVALID, "a value is not finite");
+    {
+        // a repeated (row, column) would be summed by the product but not by the band
+        std::vector<int64_t> last(n, -1);
+        for (int64_t i = 0; i < n; ++i)
+            for (int64_t e = a.ptr[i]; e < a.ptr[i + 1]; ++e) {
+                if (last[a.col[e]] == i) return sfail(SAP_ERR_INVALID, "a column repeats within a row");
+                last[a.col[e]] = i;
+            }
+    }
 
     sap_sparse p = new (std::nothrow) sap_sparse_();
     if (!p) return sfail(SAP_ERR_INVALID, "out of host memory");

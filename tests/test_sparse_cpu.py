@@ -115,3 +115,23 @@ def test_oracle_duals_are_feasible_and_tight(n, k0, density, seed):
     assert red.min() >= -1e-12
     assert np.abs(red[sigma[C.row] == C.col]).max() <= 1e-12
     assert abs(u.sum() + v.sum() - cost) <= 1e-9 * max(1.0, cost)
+
+
+def test_invalid_csr_is_refused():
+    """A repeated (row, column), a non-finite value, a column out of range and
+    a decreasing rowptr are refused with SAP_ERR_INVALID."""
+    from paper_1509_07919_amd import SapError, SapSparse, sap
+    good = (np.array([0, 2, 4], dtype=np.int64), np.array([0, 1, 0, 1], dtype=np.int32),
+            np.array([4.0, 1.0, 1.0, 4.0]))
+    SapSparse(2, *good).close()
+    bad = [
+        (good[0], np.array([0, 0, 0, 1], dtype=np.int32), good[2]),          # repeated column
+        (good[0], good[1], np.array([4.0, np.nan, 1.0, 4.0])),               # NaN
+        (good[0], good[1], np.array([4.0, 1.0, np.inf, 4.0])),               # inf
+        (good[0], np.array([0, 2, 0, 1], dtype=np.int32), good[2]),          # out of range
+        (np.array([0, 3, 2], dtype=np.int64), good[1][:2], good[2][:2]),     # decreasing rowptr
+    ]
+    for rp, ci, va in bad:
+        with pytest.raises(SapError) as e:
+            SapSparse(2, rp, ci, va)
+        assert e.value.code == sap.SAP_ERR_INVALID
