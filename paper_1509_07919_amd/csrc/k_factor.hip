@@ -731,14 +731,24 @@ hipError_t launch_banded_lu<double>(const LuArgs<double> &a, hipStream_t s)
     return launch_lu_wide(a, a.wide, s);      // K > 160
 }
 
+// LDS of the blocked kernel (two windows, two stage buffers, the reciprocals)
+static size_t lu_blk_lds(int k, int b, int s, size_t szt)
+{
+    const size_t kb = (size_t)k + b;
+    return (2 * kb * (kb + 1) + 2 * (size_t)(2 * k + 3) * s + 2 * (size_t)b) * szt;
+}
+
 template <>
 hipError_t launch_banded_lu<float>(const LuArgs<float> &a, hipStream_t s)
 {
     const int k = a.pt.k;
     // blocked kernel: panel width 8 (the fastest measured at K = 10..50), or 4,
-    // with K + B <= 64 (one panel row per lane)
+    // with K + B <= 64 (one panel row per lane), then two panel rows per lane
+    // while the double-buffered window fits the LDS (K <= 104)
     if (k + 8 <= 64) return launch_lu_blk<float, 8, 32, 512, 1>(a, s);
     if (k + 4 <= 64) return launch_lu_blk<float, 4, 32, 512, 1>(a, s);
+    if (k + 8 <= 128 && lu_blk_lds(k, 8, 32, sizeof(float)) <= kMaxLds)
+        return launch_lu_blk<float, 8, 32, 512, 2>(a, s);
     if (k < 64 && lu_mfma_supported(k, true)) return launch_lu_mfma<float>(a, s);
     if (k >= 64 && lu_mfma_supported(k, true)) return launch_lu_mfma<float>(a, s);
     if (k < 16) return launch_lu_cfg<float, 16, 16, 256>(a, s);

@@ -123,6 +123,7 @@ WIDE_CASES = [
     (6007, 150, 7, "fp32"), (6400, 160, 8, "fp64"), (6400, 200, 8, "fp32"),
     (6400, 208, 8, "fp32"), (7001, 255, 6, "fp32"), (6400, 161, 8, "fp64"),
     (6400, 200, 8, "fp64"), (6400, 208, 8, "fp64"), (7001, 255, 6, "fp64"),
+    (5003, 80, 5, "fp32"), (6007, 104, 6, "fp32"),
 ]
 
 
@@ -451,10 +452,12 @@ def oracle_factor_rows(M, which):
     return out
 
 
-# every LU kernel: the blocked LDS window (B = 8 and 4), the matrix-core
-# kernel (several window sizes), the register ring (FP64 97..127, FP32 > 208)
+# every LU kernel: the blocked LDS window (B = 8 and 4; FP32 with two rows per
+# lane up to K = 104), the matrix-core kernel (several window sizes), the
+# register ring (FP64 97..127, FP32 > 208)
 LU_ROW_CASES = [
     (3001, 10, 3, "fp64"), (3001, 10, 3, "fp32"), (4001, 58, 4, "fp64"), (4001, 62, 4, "fp32"),
+    (5003, 66, 5, "fp32"), (6007, 104, 6, "fp32"), (5003, 120, 5, "fp32"),
     (4001, 64, 4, "fp64"), (5003, 96, 5, "fp64"), (5003, 100, 5, "fp64"), (6007, 127, 5, "fp64"),
     (6007, 150, 7, "fp32"), (6400, 160, 8, "fp64"), (6400, 208, 8, "fp32"), (7001, 255, 6, "fp32"),
     (6400, 161, 8, "fp64"), (6401, 200, 8, "fp64"), (7001, 255, 6, "fp64"),
