@@ -362,12 +362,14 @@ __global__ __launch_bounds__(64) void k_tips_global_rinv(TipsArgs<T> a)
 
 // ---------------------------------------------------------------------------
 // The same quantities with every K x K working matrix in LDS (4 K^2 + 3 K
-// elements), spread over all 256 threads:
+// elements), spread over all NT threads (512, or 1024 for K >= 64, where no
+// transfer-matrix kernel runs beside this one):
 //   (a) B, C, the two factor corners and 1/diag(L'_tt) are loaded, all loads
 //       of a batch issued before the first store;
 //   (b) V and W by right-looking (column-sweep) substitution, one pivot row
-//       per step and one barrier per step: threads 0..127 work on V, threads
-//       128..255 on W, element (row, column) pairs spread over the team.  The
+//       per step and one barrier per step: the first half of the threads
+//       works on V, the second on W, element (row, column) pairs spread over
+//       the team.  The
 //       scaling by a pivot of the non-unit triangle is applied on the fly to
 //       the pivot row that the step reads, and written back one step later,
 //       when no thread reads that row any more;
@@ -378,8 +380,9 @@ __global__ __launch_bounds__(64) void k_tips_global_rinv(TipsArgs<T> a)
 //       then every other row is eliminated (the item of the pivot's row also
 //       moves the displaced row); the column order is restored when Rinv is
 //       written out.
-template <typename T>
-__global__ __launch_bounds__(256) void k_tips_lds(TipsArgs<T> a)
+// NT threads: two teams of NT / 2 >= K threads
+template <typename T, int NT>
+__global__ __launch_bounds__(NT) void k_tips_lds(TipsArgs<T> a)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int i = blockIdx.x;                   // interface i: blocks i, i+1
@@ -419,8 +422,8 @@ __global__ __launch_bounds__(256) void k_tips_lds(TipsArgs<T> a)
     // diagonal, u on and above it with the reciprocal on the diagonal), the
     // reversed corner of LU(J A_{i+1} J) -> G (U'_tt above the diagonal, L'_tt
     // on and below it)
-    // thread (gc, gr0) covers column gc, rows gr0 + grs * q (grs = floor(256 / K))
-    const int grs = 256 / k;
+    // thread (gc, gr0) covers column gc, rows gr0 + grs * q (grs = floor(NT / K))
+    const int grs = NT / k;
     const int gc = tid % k, gr0 = tid / k;
     const bool gact = gr0 < grs;
     constexpr int QB = 4;
@@ -456,16 +459,16 @@ __global__ __launch_bounds__(256) void k_tips_lds(TipsArgs<T> a)
         }
     }
     __syncthreads();
-    for (int c = tid; c < k; c += 256) gi[c] = T(1) / G[c * k + c];
+    for (int c = tid; c < k; c += NT) gi[c] = T(1) / G[c * k + c];
     __syncthreads();
     lap(0);
 
     // (b) V = U_bb^{-1} (L_bb^{-1} B_i) in X, W = L'_tt^{-1} (U'_tt^{-1} C_{i+1}) in Y
     // a team thread owns column tc and the rows congruent to tr0 modulo
-    // trs = floor(128 / K) (threads past trs*K idle), so no step divides
-    const bool vteam = tid < 128;
-    const int tt = vteam ? tid : tid - 128;
-    const int trs = 128 / k;
+    // trs = floor(NT / 2 / K) (threads past trs*K idle), so no step divides
+    const bool vteam = tid < NT / 2;
+    const int tt = vteam ? tid : tid - NT / 2;
+    const int trs = NT / 2 / k;
     const int tc = tt % k, tr0 = tt / k;
     const bool tact = tr0 < trs;
     // unit triangles: V forward with L_bb (step s: pivot row s), W backward
@@ -513,7 +516,7 @@ __global__ __launch_bounds__(256) void k_tips_lds(TipsArgs<T> a)
         else Y[(k - 1) * k + tc] *= gi[k - 1];
     }
     __syncthreads();
-    for (int e = tid; e < kk; e += 256) {
+    for (int e = tid; e < kk; e += NT) {
         a.V[ikk + e] = X[e];
         a.W[ikk + e] = Y[e];
     }
@@ -522,7 +525,7 @@ __global__ __launch_bounds__(256) void k_tips_lds(TipsArgs<T> a)
     // (c) Rbar = I - W V -> F and Rbar (global); item (row pair, 4 columns)
     {
         const int ng = (k + 3) / 4, nr = (k + 1) / 2;
-        for (int it = tid; it < nr * ng; it += 256) {
+        for (int it = tid; it < nr * ng; it += NT) {
             const int r0 = 2 * (it / ng), c0 = 4 * (it - (it / ng) * ng);
             const int r1 = min(r0 + 1, k - 1);
             T acc0[4] = {T(0), T(0), T(0), T(0)}, acc1[4] = {T(0), T(0), T(0), T(0)};
@@ -583,8 +586,8 @@ __global__ __launch_bounds__(256) void k_tips_lds(TipsArgs<T> a)
         if (tid < k) {
             const int c = tid;
             rowj[c] = (c == j ? T(1) : F[p * k + c]) * d;
-        } else if (tid >= 128 && tid - 128 < k) {
-            const int r = tid - 128;
+        } else if (tid >= NT / 2 && tid - NT / 2 < k) {
+            const int r = tid - NT / 2;
             const int src = r == j ? p : (r == p ? j : r);
             colj[r] = F[src * k + j];
         }
@@ -647,12 +650,15 @@ hipError_t launch_tips(const TipsArgs<T> &a, hipStream_t s, hipEvent_t *ev)
     const size_t kk = (size_t)a.pt.k * a.pt.k;
     const size_t lds = (4 * kk + 3 * (size_t)a.pt.k) * sizeof(T);
     if (tips_in_lds(a.pt.k, sizeof(T) == 4)) {
-        auto kern = k_tips_lds<T>;
+        // below K = 64 the chunk transfer matrices run beside this kernel on
+        // a second stream: fewer threads here leave them CUs
+        const bool wide = a.pt.k >= 64;
+        auto kern = wide ? k_tips_lds<T, 1024> : k_tips_lds<T, 512>;
         hipError_t e = hipFuncSetAttribute((const void *)kern,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
         mark(0);
-        hipLaunchKernelGGL(kern, dim3(a.pt.p - 1), dim3(256), lds, s, a);
+        hipLaunchKernelGGL(kern, dim3(a.pt.p - 1), dim3(wide ? 1024 : 512), lds, s, a);
         mark(3);
     } else {
         const int ncg = (a.pt.k + 63) / 64;
