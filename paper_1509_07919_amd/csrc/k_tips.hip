@@ -63,7 +63,7 @@ __device__ __forceinline__ T rowdot(const T *M, const T *X, int k, int r, int b,
 //                       (the same address in every lane);
 //   k_tips_global_rbar  grid (P-1, tiles^2): Rbar = I - W V in 64 x 64
 //                       tiles staged through LDS, into the Rbar and Rlu slots;
-//   k_tips_global_lu    grid (P-1): the pivoted LU of Rbar, in LDS when K^2
+//   k_tips_global_lu    grid (P-1), 1024 threads: the pivoted LU of Rbar, in LDS when K^2
 //                       elements fit (FP32 K <= 202, FP64 K <= 143), stored
 //                       in the Rlu slot;
 //   k_tips_global_rinv  grid (P-1, column groups), one wave: the Rinv columns
@@ -263,8 +263,10 @@ __global__ __launch_bounds__(256) void k_tips_global_rbar(TipsArgs<T> a)
 
 // INLDS: Rbar is factored in LDS (K^2 elements of dynamic LDS) and written
 // back to the Rlu slot at the end; else in place in the Rlu slot
+constexpr int kTipsLuNT = 1024;     // threads of k_tips_global_lu: a 32 x 32 grid
+
 template <typename T, bool INLDS>
-__global__ __launch_bounds__(256) void k_tips_global_lu(TipsArgs<T> a)
+__global__ __launch_bounds__(kTipsLuNT) void k_tips_global_lu(TipsArgs<T> a)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int i = blockIdx.x;
@@ -277,7 +279,7 @@ __global__ __launch_bounds__(256) void k_tips_global_lu(TipsArgs<T> a)
     __shared__ int pr_sh;
     __shared__ T zero_sh;
     if (INLDS)
-        for (int e = tid; e < kk; e += 256) F[e] = G[e];
+        for (int e = tid; e < kk; e += kTipsLuNT) F[e] = G[e];
     if (tid == 0) zero_sh = T(0);
     block_sync();
     // LU with partial pivoting of Rbar in F (ties to the lowest row); the
@@ -304,7 +306,7 @@ __global__ __launch_bounds__(256) void k_tips_global_lu(TipsArgs<T> a)
         block_sync();
         const int p = pr_sh;
         if (p != j)
-            for (int c = tid; c < k; c += 256) {
+            for (int c = tid; c < k; c += kTipsLuNT) {
                 const T t = F[j * k + c];
                 F[j * k + c] = F[p * k + c];
                 F[p * k + c] = t;
@@ -312,19 +314,19 @@ __global__ __launch_bounds__(256) void k_tips_global_lu(TipsArgs<T> a)
         block_sync();
         const T d = F[j * k + j];
         const T dinv = d != T(0) ? T(1) / d : zero_sh;
-        // trailing update: thread (tid / 16, tid % 16) takes every 16th row
+        // trailing update: thread (tid / 32, tid % 32) takes every 32nd row
         // and column, so no index needs a division
-        for (int r = j + 1 + (tid >> 4); r < k; r += 16) {
+        for (int r = j + 1 + (tid >> 5); r < k; r += 32) {
             const T l = F[r * k + j] * dinv;
-            for (int c = j + 1 + (tid & 15); c < k; c += 16)
+            for (int c = j + 1 + (tid & 31); c < k; c += 32)
                 F[r * k + c] = fma(-l, F[j * k + c], F[r * k + c]);
         }
         block_sync();
-        for (int r = j + 1 + tid; r < k; r += 256) F[r * k + j] *= dinv;
+        for (int r = j + 1 + tid; r < k; r += kTipsLuNT) F[r * k + j] *= dinv;
         block_sync();
     }
     if (INLDS)
-        for (int e = tid; e < kk; e += 256) G[e] = F[e];
+        for (int e = tid; e < kk; e += kTipsLuNT) G[e] = F[e];
 }
 
 // Rinv = Rbar^{-1}: column b solves Rbar y = e_b with the pivoted LU of the
@@ -680,9 +682,9 @@ hipError_t launch_tips(const TipsArgs<T> &a, hipStream_t s, hipEvent_t *ev)
             hipError_t e = hipFuncSetAttribute((const void *)k_tips_global_lu<T, true>,
                                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)rb);
             if (e != hipSuccess) return e;
-            hipLaunchKernelGGL((k_tips_global_lu<T, true>), dim3(a.pt.p - 1), dim3(256), rb, s, a);
+            hipLaunchKernelGGL((k_tips_global_lu<T, true>), dim3(a.pt.p - 1), dim3(kTipsLuNT), rb, s, a);
         } else {
-            hipLaunchKernelGGL((k_tips_global_lu<T, false>), dim3(a.pt.p - 1), dim3(256), 0, s, a);
+            hipLaunchKernelGGL((k_tips_global_lu<T, false>), dim3(a.pt.p - 1), dim3(kTipsLuNT), 0, s, a);
         }
         hipLaunchKernelGGL(k_tips_global_rinv<T>, dim3(a.pt.p - 1, ncg), dim3(64), cols, s, a);
         mark(3);
