@@ -77,9 +77,13 @@ typedef struct sap_options {
     int32_t adjoint;      /* nonzero: also keep the transposed factor copies */
                           /*  needed by sap_solve_adjoint                    */
     int32_t sweep_chunks; /* chains per block in each triangular sweep:     */
-                          /*  0 -> chosen by the library, 1 -> one chain    */
-                          /*  per block, >= 2 -> at most this many (each    */
-                          /*  chunk then holds >= 64 rows); must be >= 0    */
+                          /*  0 -> chosen by the library (chunked for       */
+                          /*  K < 64 only), 1 -> one chain per block,       */
+                          /*  >= 2 -> at most this many (each chunk then    */
+                          /*  holds >= 64 rows) for K < 128, whose chunk    */
+                          /*  transfer matrices sap_factor then forms       */
+                          /*  (N K^2 FP64 FMA per factor array); one chain  */
+                          /*  above; must be >= 0                           */
     int32_t nrhs;         /* right-hand sides sap_solve_batch may take at   */
                           /*  once, 0..64 (0 -> 1); the workspace grows     */
                           /*  with it                                       */

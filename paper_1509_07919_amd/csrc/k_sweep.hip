@@ -68,19 +68,22 @@ constexpr int kSweepWaves = 4;
 // once (multi-RHS sweeps), each transfer matrix read once for all of them;
 // sh[64 j ..] then holds column j's state.  q, st and top are per column
 // (strides p*nch*K, p*nch*K and p*K).
-template <typename T, bool FWD, int NW, bool STORE, int NR = 1>
+template <typename T, bool FWD, int NW, bool STORE, int NR = 1, int H = 1>
 __device__ void chain_states(const SweepArgs<T> &a, int blk, int nchb, int nlink, double *sh,
                              const T *top = nullptr, int col0 = 0, int nc = 1)
 {
-    constexpr int IW = 64 / NW;
+    // H output slots per lane (m = lane + 64 h, K < 64 H); wave w sums the
+    // terms i in [IW w, IW w + IW) of X(c)^T p
+    constexpr int W64 = 64 * H;
+    constexpr int IW = W64 / NW;
     const int k = a.pt.k;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int64_t base = (int64_t)blk * a.nch;
     const int64_t qs = (int64_t)a.pt.p * a.nch * k;     // column stride of q and st
     const int64_t ts = (int64_t)a.pt.p * k;             // column stride of top
     const T *qc = a.q + col0 * qs;
-    double *cur = sh;            // [NR][64] state entering the current chunk
-    double *part = sh + 64 * NR; // [NW][NR][64] partial sums
+    double *cur = sh;             // [NR][W64] state entering the current chunk
+    double *part = sh + W64 * NR; // [NW][NR][W64] partial sums
     const int c0 = FWD ? 0 : nchb - 1;            // chunk whose q seeds the chain
     const int dir = FWD ? 1 : -1;
     // the state entering chunk c0 + dir is q(c0), or with an incoming state
@@ -89,71 +92,85 @@ __device__ void chain_states(const SweepArgs<T> &a, int blk, int nchb, int nlink
     if (top) ++nlink;
     if (tid < 64) {
 #pragma unroll
-        for (int j = 0; j < NR; ++j) {
-            double v = 0.0;
-            if (j < nc && tid < k)
-                v = top ? -(double)top[j * ts + tid] : (double)qc[j * qs + (base + c0) * k + tid];
-            cur[j * 64 + tid] = v;
-            if (STORE && !top && j < nc && tid < k)
-                a.st[(col0 + j) * qs + (base + c0 + dir) * k + tid] = v;
-        }
+        for (int j = 0; j < NR; ++j)
+#pragma unroll
+            for (int h = 0; h < H; ++h) {
+                const int m = 64 * h + tid;
+                double v = 0.0;
+                if (j < nc && m < k)
+                    v = top ? -(double)top[j * ts + m] : (double)qc[j * qs + (base + c0) * k + m];
+                cur[j * W64 + m] = v;
+                if (STORE && !top && j < nc && m < k)
+                    a.st[(col0 + j) * qs + (base + c0 + dir) * k + m] = v;
+            }
     }
     // the transfer matrices of NG links are loaded at once, so their
-    // latencies overlap; the links are then chained one after the other
-    constexpr int NG = NR > 1 ? 2 : ((sizeof(T) == 8 || NW > 4) ? (STORE ? 2 : 3) : 4);
-    auto load_x = [&](int c, double *dst) {
+    // latencies overlap; the links are then chained one after the other (with
+    // two slots per lane, one link at a time and one slot's half of X at a
+    // time, which keeps the registers of the sweep kernels that chain)
+    constexpr int NG = H > 1 ? 1 : (NR > 1 ? 2 : ((sizeof(T) == 8 || NW > 4) ? (STORE ? 2 : 3) : 4));
+    auto load_x = [&](int c, int h, double (&dst)[IW]) {
         const double *x = a.xf + (base + c) * k * k;
 #pragma unroll
         for (int e = 0; e < IW; ++e) {
             const int i = IW * wave + e;
-            dst[e] = (i < k && lane < k) ? x[i * k + lane] : 0.0;
+            dst[e] = (i < k && 64 * h + lane < k) ? x[i * k + 64 * h + lane] : 0.0;
         }
     };
     __syncthreads();
     for (int g = 0; g < nlink; g += NG) {
-        double xg[NG][IW], qg[NG][NR];
+        double xg[NG][IW], qg[NG][NR][H];
 #pragma unroll
         for (int j = 0; j < NG; ++j) {
             const int c = first + dir * (g + j);
             if (g + j < nlink) {
-                load_x(c, xg[j]);
+                if (H == 1) load_x(c, 0, xg[j]);
 #pragma unroll
                 for (int r = 0; r < NR; ++r)
-                    qg[j][r] = (wave == 0 && lane < k && r < nc)
-                                   ? (double)qc[r * qs + (base + c) * k + lane] : 0.0;
+#pragma unroll
+                    for (int h = 0; h < H; ++h)
+                        qg[j][r][h] = (wave == 0 && 64 * h + lane < k && r < nc)
+                                          ? (double)qc[r * qs + (base + c) * k + 64 * h + lane] : 0.0;
             }
         }
 #pragma unroll
         for (int j = 0; j < NG; ++j) {
             if (g + j < nlink) {
                 const int c = first + dir * (g + j);         // chunk of this link
+#pragma unroll 1
+                for (int h = 0; h < H; ++h) {
+                    if (H > 1) load_x(c, h, xg[j]);
 #pragma unroll
-                for (int r = 0; r < NR; ++r) {
-                    const double *cr = cur + r * 64 + IW * wave;
-                    double s0 = 0.0, s1 = 0.0;
+                    for (int r = 0; r < NR; ++r) {
+                        const double *cr = cur + r * W64 + IW * wave;
+                        double s0 = 0.0, s1 = 0.0;
 #pragma unroll
-                    for (int e = 0; e < IW; e += 2) {
-                        s0 = fma(xg[j][e], cr[e], s0);
-                        s1 = fma(xg[j][e + 1], cr[e + 1], s1);
+                        for (int e = 0; e < IW; e += 2) {
+                            s0 = fma(xg[j][e], cr[e], s0);
+                            s1 = fma(xg[j][e + 1], cr[e + 1], s1);
+                        }
+                        part[(wave * NR + r) * W64 + 64 * h + lane] = s0 + s1;
                     }
-                    part[(wave * NR + r) * 64 + lane] = s0 + s1;
                 }
                 __syncthreads();
                 if (wave == 0) {
 #pragma unroll
-                    for (int r = 0; r < NR; ++r) {
-                        double ps[NW];
+                    for (int r = 0; r < NR; ++r)
 #pragma unroll
-                        for (int w = 0; w < NW; ++w) ps[w] = part[(w * NR + r) * 64 + lane];
+                        for (int h = 0; h < H; ++h) {
+                            const int m = 64 * h + lane;
+                            double ps[NW];
 #pragma unroll
-                        for (int h = NW / 2; h >= 1; h /= 2)
+                            for (int w = 0; w < NW; ++w) ps[w] = part[(w * NR + r) * W64 + m];
 #pragma unroll
-                            for (int w = 0; w < h; ++w) ps[w] += ps[w + h];
-                        const double v = qg[j][r] + ps[0];
-                        cur[r * 64 + lane] = lane < k ? v : 0.0;
-                        if (STORE && lane < k && r < nc)
-                            a.st[(col0 + r) * qs + (base + c + dir) * k + lane] = v;
-                    }
+                            for (int hh = NW / 2; hh >= 1; hh /= 2)
+#pragma unroll
+                                for (int w = 0; w < hh; ++w) ps[w] += ps[w + hh];
+                            const double v = qg[j][r][h] + ps[0];
+                            cur[r * W64 + m] = m < k ? v : 0.0;
+                            if (STORE && m < k && r < nc)
+                                a.st[(col0 + r) * qs + (base + c + dir) * k + m] = v;
+                        }
                 }
                 __syncthreads();
             }
@@ -163,7 +180,7 @@ __device__ void chain_states(const SweepArgs<T> &a, int blk, int nchb, int nlink
 
 // End of a zero-state workgroup: the last of a block's workgroups to arrive
 // (atomic ticket) chains the block's chunk states.
-template <typename T, bool FWD, int NW>
+template <typename T, bool FWD, int NW, int H = 1>
 __device__ void chain_if_last(const SweepArgs<T> &a, int blk, int nchb, double *scratch)
 {
     __shared__ int last_sh;
@@ -176,7 +193,7 @@ __device__ void chain_if_last(const SweepArgs<T> &a, int blk, int nchb, double *
     __syncthreads();
     if (!last_sh) return;
     __threadfence();                            // see every chunk's q
-    if (nchb >= 2) chain_states<T, FWD, NW, true>(a, blk, nchb, nchb - 2, scratch);
+    if (nchb >= 2) chain_states<T, FWD, NW, true, 1, H>(a, blk, nchb, nchb - 2, scratch);
     if (threadIdx.x == 0) a.ticket[blk] = 0u;   // ready for the next sweep
 }
 
@@ -185,10 +202,11 @@ __device__ void chain_if_last(const SweepArgs<T> &a, int blk, int nchb, double *
 // of S prescaled inputs v*d.
 constexpr int kSweepRows = 32;
 template <typename T>
-static size_t sweep_lds_bytes(int cp, int nbuf)
+static size_t sweep_lds_bytes(int cp, int nbuf, int h = 1)
 {
     const size_t b = ((size_t)nbuf * kSweepRows * cp + (size_t)nbuf * kSweepRows) * sizeof(T);
-    const size_t chain = (size_t)64 * (kSweepWaves + 1) * sizeof(double);   // chain_states scratch
+    // chain_states scratch: h slots of 64 per lane
+    const size_t chain = (size_t)64 * h * (kSweepWaves + 1) * sizeof(double);
     return b > chain ? b : chain;
 }
 
@@ -412,8 +430,8 @@ __global__ __launch_bounds__(64 * kSweepWaves, kSweepWaves / 2) void k_sweep(Swe
             }
         }
     }
-    if (PH != SWEEP_ZERO_STATE) return;
-    chain_if_last<T, FWD, kSweepWaves>(a, blk, nchb, reinterpret_cast<double *>(stage));
+    if constexpr (PH == SWEEP_ZERO_STATE && KR <= 3)   // chunked up to K = 127
+        chain_if_last<T, FWD, kSweepWaves, KR - 1>(a, blk, nchb, reinterpret_cast<double *>(stage));
 }
 
 // ------------------------------------------------ circular form, K <= 56
@@ -719,9 +737,10 @@ static hipError_t launch_sweep_ph(const SweepArgs<T> &a, hipStream_t s)
     // chunk in flight) that keeps two workgroups per CU when the grid has
     // more than one workgroup per CU
     const size_t cap = grid > 256 ? kMaxLds / 2 : kMaxLds;
+    const int h = KR - 1 < 1 ? 1 : KR - 1;
     int nbuf = kSweepWaves;
-    while (nbuf > 2 && sweep_lds_bytes<T>(cp, nbuf) > cap) --nbuf;
-    const size_t lds = sweep_lds_bytes<T>(cp, nbuf);
+    while (nbuf > 2 && sweep_lds_bytes<T>(cp, nbuf, h) > cap) --nbuf;
+    const size_t lds = sweep_lds_bytes<T>(cp, nbuf, h);
     if (lds > kMaxLds) return hipErrorInvalidValue;
     auto kern = k_sweep<T, KR, FWD, DIAG, PH>;
     hipError_t e = hipFuncSetAttribute((const void *)kern,
@@ -734,7 +753,7 @@ static hipError_t launch_sweep_ph(const SweepArgs<T> &a, hipStream_t s)
 template <typename T, int KR, bool FWD, bool DIAG>
 static hipError_t launch_sweep_cfg(const SweepArgs<T> &a, hipStream_t s)
 {
-    if constexpr (KR == 2) {                   // chained states need K < 64
+    if constexpr (KR <= 3) {                   // chained states up to K = 127
         if (a.phase == SWEEP_ZERO_STATE)
             return launch_sweep_ph<T, KR, FWD, DIAG, SWEEP_ZERO_STATE>(a, s);
         if (a.phase == SWEEP_FROM_STATE)
@@ -920,6 +939,99 @@ __global__ __launch_bounds__(256) void k_sweep_xfer(XferArgs<T> a)
     if (tid < nblk) block_store(out, tid, acc);
 }
 
+// Transfer matrices for 64 <= K < 128: one workgroup of two waves per chunk
+// that hands a state on; wave h runs the basis states i = 64 h + lane over the
+// whole chunk, so no partial transfers are multiplied (the product form above
+// would need 2 K^2 FP64 entries of LDS).  A lane keeps the pending sums of the
+// next 128 steps in registers.  Each wave copies its coming coefficient rows
+// (coefficient m in lane m mod 64 of register m / 64, eight rows ahead) into a
+// ring of its own in LDS and reads them back at one address for all lanes.
+template <typename T>
+__global__ __launch_bounds__(128) void k_sweep_xfer_wide(XferArgs<T> a)
+{
+    constexpr int KM = 128;
+    constexpr int D = 8;
+    using DT = double;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int k = a.pt.k;
+    const int CP = coef_pitch(k, (int)sizeof(T));   // row pitch in HBM
+    const int arr = blockIdx.y;
+    const T *F = a.F[arr];
+    const bool fwd = a.fwd[arr] != 0, diag = a.diag[arr] != 0;
+    const int blk = (int)(blockIdx.x % a.pt.p), ch = (int)(blockIdx.x / a.pt.p);
+    const int64_t s0 = a.pt.starts[blk];
+    const int64_t nb = a.pt.starts[blk + 1] - s0;
+    const int nchb = (int)((nb + a.clen - 1) / a.clen);
+    if (!(ch < nchb && (fwd ? ch + 1 < nchb : ch > 0))) return;
+    const int64_t r0 = (int64_t)ch * a.clen, r1 = min(r0 + a.clen, nb);
+    const int64_t nst = r1 - r0;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+    const int i = 64 * wave + lane;                 // basis state of this lane
+    DT *ring = reinterpret_cast<DT *>(smem_raw) + (size_t)wave * 2 * D * KM;   // [2][D][KM]
+
+    DT p[KM];
+#pragma unroll
+    for (int m = 0; m < KM; ++m) p[m] = (m == i) ? 1.0 : 0.0;
+    T fr[D][2], fn[D][2];
+    auto load = [&](int64_t t0, T (&dst)[D][2]) {
+#pragma unroll
+        for (int e = 0; e < D; ++e) {
+            const int64_t t = t0 + e;
+            const int64_t row = fwd ? r0 + t : r1 - 1 - t;
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const int m = 64 * q + lane;
+                dst[e][q] = (t < nst && m <= k) ? F[(s0 + row) * CP + m] : T(0);
+            }
+        }
+    };
+    load(0, fr);
+    int g = 0;
+    for (int64_t t0 = 0; t0 < nst; t0 += D, ++g) {
+        DT *buf = ring + (g & 1) * D * KM;
+#pragma unroll
+        for (int e = 0; e < D; ++e)
+#pragma unroll
+            for (int q = 0; q < 2; ++q) buf[e * KM + 64 * q + lane] = (DT)fr[e][q];
+        load(t0 + D, fn);
+#pragma unroll
+        for (int e = 0; e < D; ++e) {
+            if (t0 + e < nst) {
+                const DT *row = buf + e * KM;
+                const DT d = diag ? row[0] : 1.0;
+                const DT x = -p[0] * d;
+#pragma unroll
+                for (int m = 1; m < KM; ++m) p[m - 1] = fma(row[m], x, p[m]);
+                p[KM - 1] = 0.0;
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < D; ++e) {
+            fr[e][0] = fn[e][0];
+            fr[e][1] = fn[e][1];
+        }
+    }
+    if (i < k) {
+        DT *out = a.xf[arr] + ((int64_t)blk * a.nch + ch) * k * k + (int64_t)i * k;
+#pragma unroll
+        for (int m = 0; m < KM; ++m)
+            if (m < k) out[m] = p[m];
+    }
+}
+
+template <typename T>
+static hipError_t launch_xfer_wide(const XferArgs<T> &a, hipStream_t s)
+{
+    const size_t lds = 2 * 2 * 8 * 128 * sizeof(double);   // each wave's [2][8][128] ring
+    auto kern = k_sweep_xfer_wide<T>;
+    hipError_t e = hipFuncSetAttribute((const void *)kern,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kern, dim3(a.pt.p * a.nch, a.narr), dim3(128), lds, s, a);
+    return hipGetLastError();
+}
+
 template <typename T, int KM>
 static hipError_t launch_xfer_km(const XferArgs<T> &a, hipStream_t s)
 {
@@ -933,7 +1045,7 @@ static hipError_t launch_xfer_km(const XferArgs<T> &a, hipStream_t s)
     return hipGetLastError();
 }
 
-bool sweep_chunking_supported(int k, bool) { return k >= 1 && k < 64; }
+bool sweep_chunking_supported(int k, bool) { return k >= 1 && k < 128; }
 bool sweep_top_state_supported(int k) { return k >= 1 && k <= kCircMaxK; }
 
 template <typename T>
@@ -942,6 +1054,7 @@ hipError_t launch_sweep_xfer(const XferArgs<T> &a, hipStream_t s)
     const int k = a.pt.k;
     if (!sweep_chunking_supported(k, sizeof(T) == 4) || a.nch < 2 || a.narr < 1 || a.narr > 4)
         return hipErrorInvalidValue;
+    if (k >= 64) return launch_xfer_wide<T>(a, s);
     // KM >= K + 1 slots: the K pending sums plus the zero that enters
     if (k < 8) return launch_xfer_km<T, 8>(a, s);
     if (k < 16) return launch_xfer_km<T, 16>(a, s);

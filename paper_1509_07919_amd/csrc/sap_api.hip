@@ -68,6 +68,11 @@ Chunking chunking_for(const sap_options &o)
     const bool fp32 = o.factor_prec == SAP_PREC_FP32;
     Chunking c{1, (int)maxnb, true};
     if (o.sweep_chunks == 1 || !sweep_chunking_supported(o.k, fp32)) return c;
+    // automatic: chunked only below K = 64; the transfer matrices of wider
+    // bands cost more at factor time (N K^2 FP64 FMA per array, 2 ms at
+    // N=200k, K=100) than one solve's sweeps save, so there they are built
+    // only when asked for
+    if (o.sweep_chunks == 0 && o.k >= 64) return c;
     int64_t want = o.sweep_chunks >= 2 ? o.sweep_chunks : 512 / o.p;
     if (want < 2) return c;
     int64_t clen = (maxnb + want - 1) / want;
@@ -156,7 +161,8 @@ Layout layout_for(const sap_options &o)
         L.xUc = take(xb);
         L.xLr = o.adjoint ? take(xb) : 0;
         L.xUr = o.adjoint ? take(xb) : 0;
-        L.xscr = take(2 * xb * (o.adjoint ? 4 : 2));     // k_sweep_xfer partials
+        // k_sweep_xfer partials (the kernel for K >= 64 multiplies none)
+        L.xscr = k < 64 ? take(2 * xb * (o.adjoint ? 4 : 2)) : 0;
         L.sq = take(2 * sf * (size_t)p * ck.nch * k * m);     // first and second sweep of a D^{-1}
         L.sst = take(sizeof(double) * (size_t)p * ck.nch * k);
         L.ticket = take(sizeof(unsigned) * (size_t)p);

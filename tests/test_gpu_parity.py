@@ -148,13 +148,17 @@ def test_wide_band_precond(n, k, p, prec):
 
 
 # chunked sweeps: (n, k, p, mode, sweep_chunks); blocks of unequal size, chunk
-# counts that leave a short last chunk, and K up to the largest chained one.
+# counts that leave a short last chunk, and K up to the largest chained one
+# (127).
 # (4500, 40, 4): 64-row chunks leave a 37-row last chunk, shorter than K, so
 # the second D^{-1} of SaP-C cannot reuse the first one's zero-state pass.
 CHUNK_CASES = [
     (1000, 1, 2, "decoupled", 3), (3001, 5, 7, "coupled", 2), (5003, 31, 9, "coupled", 7),
     (20011, 50, 16, "coupled", 0), (20011, 50, 16, "coupled", 19), (8191, 63, 4, "coupled", 5),
     (12000, 40, 3, "decoupled", 50), (4500, 40, 4, "coupled", 0),
+    # the ring kernels with two state slots per lane (64 <= K < 128)
+    (8191, 64, 4, "coupled", 5), (10007, 100, 5, "coupled", 6), (9001, 127, 4, "decoupled", 3),
+    (12000, 80, 6, "coupled", 7),
 ]
 
 
