@@ -135,3 +135,67 @@ def test_invalid_csr_is_refused():
         with pytest.raises(SapError) as e:
             SapSparse(2, rp, ci, va)
         assert e.value.code == sap.SAP_ERR_INVALID
+
+
+def _csr_from_dense(A):
+    n = A.shape[0]
+    rows, cols = np.nonzero(A)
+    rowptr = np.concatenate([[0], np.cumsum(np.bincount(rows, minlength=n))]).astype(np.int64)
+    return n, rowptr, cols.astype(np.int32), A[rows, cols].astype(np.float64)
+
+
+def _check_against_oracle(A):
+    from paper_1509_07919_amd import SapSparse
+    n, rowptr, colidx, vals = _csr_from_dense(A)
+    sigma_o, cost_o = osp.db_matching(n, rowptr, colidx, vals)
+    info = SapSparse(n, rowptr, colidx, vals, db=True, cm=False).info()
+    sigma = info["new_row"].astype(np.int64)
+    assert abs(osp.matching_cost(n, rowptr, colidx, vals, sigma) - cost_o) <= 1e-12 * max(1.0, cost_o)
+    s = np.abs(info["row_scale"][:, None] * A * info["col_scale"][None, :])
+    assert s.max() <= 1.0 + 1e-12
+    assert np.allclose(s[np.arange(n), sigma], 1.0, rtol=1e-12, atol=0)
+    return sigma, sigma_o
+
+
+def test_matching_edge_cases():
+    """N = 1; a permutation matrix (the only perfect matching); a cyclic
+    structure whose heaviest entries all sit in one column, so the initial
+    greedy match leaves rows for long augmenting paths; a block of equal
+    entries (many optimal matchings: costs and scaling compared, not the
+    permutation)."""
+    sigma, _ = _check_against_oracle(np.array([[3.0]]))
+    assert list(sigma) == [0]
+    P = np.zeros((6, 6))
+    perm = [3, 0, 5, 1, 4, 2]
+    P[np.arange(6), perm] = [2.0, -1.0, 0.5, 4.0, -3.0, 1.0]
+    sigma, sigma_o = _check_against_oracle(P)
+    assert list(sigma) == perm and list(sigma_o) == perm
+    n = 9
+    C = np.zeros((n, n))
+    for i in range(n):
+        C[i, 0] = 10.0 + i          # every row's heaviest entry in column 0
+        C[i, (i + 1) % n] = 1.0 + 0.1 * i
+        C[i, i] = 0.5 + 0.01 * i
+    sigma, sigma_o = _check_against_oracle(C)
+    assert np.array_equal(sigma, sigma_o)
+    E = np.ones((5, 5))
+    _check_against_oracle(E)
+
+
+def test_cuthill_mckee_disconnected_and_diagonal():
+    """A diagonal matrix (half-bandwidth 0, identity order) and a structure of
+    three disconnected paths: the library's order equals the oracle's."""
+    from paper_1509_07919_amd import SapSparse
+    n, rowptr, colidx, vals = _csr_from_dense(np.diag(np.arange(1.0, 8.0)))
+    info = SapSparse(n, rowptr, colidx, vals, db=False, cm=True).info()
+    assert info["k_full"] == 0 and info["k"] == 0
+    A = np.eye(12) * 4.0
+    for a, b in ((0, 7), (7, 3), (3, 10), (1, 5), (5, 11), (2, 9), (9, 4), (4, 6), (6, 8)):
+        A[a, b] = A[b, a] = 1.0
+    n, rowptr, colidx, vals = _csr_from_dense(A)
+    info = SapSparse(n, rowptr, colidx, vals, db=False, cm=True).info()
+    order, kk = osp.cuthill_mckee(n, rowptr, colidx)
+    pos = np.empty(n, dtype=np.int64)
+    pos[order] = np.arange(n)
+    assert np.array_equal(info["new_col"], pos)
+    assert info["k_full"] == kk == 1
