@@ -120,8 +120,10 @@ def _picks(n, k, count, seed):
 def test_adjoint_gradient_finite_differences():
     """N=100k, K=32, P=32, FP32 preconditioner: L = 0.5||x - x_target||^2.
     dL/db and dL/dA (band) from the adjoint solve agree with the oracle's
-    gradients from direct solves, and with central differences (h = 1e-6) on
-    20 band entries and 20 entries of b."""
+    gradients from direct solves, and with central differences (h = 1e-6) of
+    L evaluated by the oracle's direct banded LU (independent of the GPU
+    solver) on 20 band entries and 20 entries of b.  The differences lose
+    about eps*L/h ~ 5e-6 to cancellation (L ~ 5e4), hence 1e-4."""
     from paper_1509_07919_amd import sap_solve_autograd
     name = "sapc_n100k_k32_adjoint"
     print("CASE adjoint fd", name, flush=True)
@@ -139,33 +141,28 @@ def test_adjoint_gradient_finite_differences():
     assert rel(gb, gb_o) <= 1e-8
     assert rel(ga, ga_o) <= 1e-8
 
-    fd_solver = solver(cfg)
-
-    def lossf(band_t, rhs_t):
-        fd_solver.factor(band_t)
-        y, st = fd_solver.solve(rhs_t, tol=1e-13, maxit=500)
-        assert st.converged
-        return 0.5 * float(((y - dev(xt)) ** 2).sum())
+    def loss(y):
+        return 0.5 * float(((y - xt) ** 2).sum())
 
     h = 1e-6
     bi, slots = _picks(n, k, 20, 7)
     assert len(bi) == 20 and len(slots) == 20
-    band0, b0 = dev(pb.band), dev(pb.b)
+    lu0 = oracle.DirectLU(pb.band, n, k)
     for j in bi:
-        bp, bm = b0.clone(), b0.clone()
+        bp, bm = pb.b.copy(), pb.b.copy()
         bp[j] += h
         bm[j] -= h
-        fd = (lossf(band0, bp) - lossf(band0, bm)) / (2 * h)
+        fd = (loss(lu0.solve(bp)) - loss(lu0.solve(bm))) / (2 * h)
         assert abs(fd - gb[j]) <= 1e-4 * max(1.0, abs(gb[j]))
     for (r, c) in slots:
         pos = (k + r - c) * n + c
-        ap, am = band0.clone(), band0.clone()
+        ap, am = pb.band.copy(), pb.band.copy()
         ap[pos] += h
         am[pos] -= h
-        fd = (lossf(ap, b0) - lossf(am, b0)) / (2 * h)
+        fd = (loss(oracle.solve_direct(ap, n, k, pb.b)) -
+              loss(oracle.solve_direct(am, n, k, pb.b))) / (2 * h)
         assert abs(fd - ga[pos]) <= 1e-4 * max(1.0, abs(ga[pos]))
     s.close()
-    fd_solver.close()
 
 
 def test_weak_dominance_adjoint_wrt_b():
