@@ -122,8 +122,11 @@ def test_adjoint_gradient_finite_differences():
     dL/db and dL/dA (band) from the adjoint solve agree with the oracle's
     gradients from direct solves, and with central differences (h = 1e-6) of
     L evaluated by the oracle's direct banded LU (independent of the GPU
-    solver) on 20 band entries and 20 entries of b.  The differences lose
-    about eps*L/h ~ 5e-6 to cancellation (L ~ 5e4), hence 1e-4."""
+    solver) on 20 band entries and 20 entries of b.  The difference of the
+    two losses is formed exactly as 0.5 (x+ - x-).(x+ + x- - 2 x_target),
+    not as L(x+) - L(x-), which would lose eps*L/h ~ 5e-6 to cancellation
+    (L ~ 5e4); what is left is the O(h^2) truncation and the rounding of
+    x+ - x- (a few 1e-9 relative), hence 1e-6."""
     from paper_1509_07919_amd import sap_solve_autograd
     name = "sapc_n100k_k32_adjoint"
     print("CASE adjoint fd", name, flush=True)
@@ -141,8 +144,9 @@ def test_adjoint_gradient_finite_differences():
     assert rel(gb, gb_o) <= 1e-8
     assert rel(ga, ga_o) <= 1e-8
 
-    def loss(y):
-        return 0.5 * float(((y - xt) ** 2).sum())
+    def dloss(yp, ym):
+        """L(yp) - L(ym) without forming either loss."""
+        return 0.5 * float(np.dot(yp - ym, yp + ym - 2.0 * xt))
 
     h = 1e-6
     bi, slots = _picks(n, k, 20, 7)
@@ -152,16 +156,16 @@ def test_adjoint_gradient_finite_differences():
         bp, bm = pb.b.copy(), pb.b.copy()
         bp[j] += h
         bm[j] -= h
-        fd = (loss(lu0.solve(bp)) - loss(lu0.solve(bm))) / (2 * h)
-        assert abs(fd - gb[j]) <= 1e-4 * max(1.0, abs(gb[j]))
+        fd = dloss(lu0.solve(bp), lu0.solve(bm)) / (2 * h)
+        assert abs(fd - gb[j]) <= 1e-6 * max(1.0, abs(gb[j]))
     for (r, c) in slots:
         pos = (k + r - c) * n + c
         ap, am = pb.band.copy(), pb.band.copy()
         ap[pos] += h
         am[pos] -= h
-        fd = (loss(oracle.solve_direct(ap, n, k, pb.b)) -
-              loss(oracle.solve_direct(am, n, k, pb.b))) / (2 * h)
-        assert abs(fd - ga[pos]) <= 1e-4 * max(1.0, abs(ga[pos]))
+        fd = dloss(oracle.solve_direct(ap, n, k, pb.b),
+                   oracle.solve_direct(am, n, k, pb.b)) / (2 * h)
+        assert abs(fd - ga[pos]) <= 1e-6 * max(1.0, abs(ga[pos]))
     s.close()
 
 
