@@ -492,6 +492,11 @@ LU_ROW_CASES = [
     (4001, 64, 4, "fp64"), (5003, 96, 5, "fp64"), (5003, 100, 5, "fp64"), (6007, 127, 5, "fp64"),
     (6007, 150, 7, "fp32"), (6400, 160, 8, "fp64"), (6400, 208, 8, "fp32"), (7001, 255, 6, "fp32"),
     (6400, 161, 8, "fp64"), (6401, 200, 8, "fp64"), (7001, 255, 6, "fp64"),
+    # the blocked kernel across K = 1..56 (panel widths 8 and 4): blocks whose
+    # length is not a multiple of the panel width, blocks shorter than the window
+    (1001, 1, 3, "fp64"), (2003, 3, 5, "fp32"), (3001, 13, 4, "fp64"), (4099, 33, 6, "fp32"),
+    (5003, 50, 5, "fp64"), (5003, 50, 5, "fp32"), (6007, 56, 7, "fp64"), (6007, 56, 7, "fp32"),
+    (203, 30, 4, "fp64"), (157, 45, 3, "fp32"),
 ]
 
 
