@@ -380,6 +380,27 @@ def cpu_baseline(cfg, pb, reps):
     return statistics.median(times), x, res
 
 
+def cpu_lapack_context(cfg, pb, reps):
+    """Context only: LAPACK's banded LU with partial pivoting (dgbsv through
+    scipy.linalg.solve_banded) on the same system, with the host BLAS's own
+    thread count; median of `reps` solves and the relative error against
+    x_true.  The band layout is LAPACK's band storage with kl = ku = K
+    (entry a(i, j) at row K + i - j of column j), so the array is passed as is."""
+    import numpy as np
+    import scipy.linalg as sla
+    from threadpoolctl import threadpool_info
+    n, k = cfg["n"], cfg["k"]
+    ab = pb.band.reshape(2 * k + 1, n)
+    times, x = [], None
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        x = sla.solve_banded((k, k), ab, pb.b, check_finite=False)
+        times.append((time.perf_counter() - t0) * 1e3)
+    threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
+    err = float(np.linalg.norm(x - pb.x_true) / np.linalg.norm(pb.x_true))
+    return statistics.median(times), threads, err
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -589,6 +610,12 @@ def main():
         for p_ in runs:
             out["runs"][p_]["rel_err_vs_oracle"] = float(
                 np.linalg.norm(runs[p_]["x"] - xo) / np.linalg.norm(xo))
+        lms, lthr, lerr = cpu_lapack_context(cfg, pb, args.cpu_reps)
+        out["cpu_context"] = {
+            "value": round(lms, 2), "unit": "ms", "kind": "lapack_dgbsv",
+            "threads": lthr, "rel_err_vs_xtrue": lerr,
+            "sample": "full workload, median of %d scipy.linalg.solve_banded solves "
+                      "(banded LU with partial pivoting)" % args.cpu_reps}
     print(json.dumps(out), flush=True)
 
 
