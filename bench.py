@@ -257,6 +257,84 @@ def run_gpu(args, prec, pb, a, b):
     return (t1 - t0) * 1e3 / args.steps, stats, kt, xs
 
 
+def run_backward(args, prec, pb, a, b):
+    """The differentiation step: factor and forward solve, then the backward
+    pass of L = 0.5 ||x - x_target||^2 (x_target ~ N(0, 1)): the adjoint solve
+    A^T lambda = x - x_target on the same factors (dL/db = lambda) and the band
+    gradient dL/dA = band(-lambda x^T).  Events on the launch stream time the
+    forward part and the backward part of each step, and the band gradient
+    alone; a second round with per-launch timing gives the backward pass's
+    kernels."""
+    import torch
+
+    import sapgen
+    from paper_1509_07919_amd import SapSolver
+
+    cfg = args.cfg
+    n, k = cfg["n"], cfg["k"]
+    s = SapSolver(n, k, cfg["p"], mode=cfg["mode"], factor_prec=prec, adjoint=True)
+    xt = torch.from_numpy(sapgen.normal_draws(args.seed, sapgen.STREAM_XTARGET, n)).to(a.device)
+    x, g, lam = torch.empty_like(b), torch.empty_like(b), torch.empty_like(b)
+    gband = torch.empty((2 * k + 1) * n, dtype=torch.float64, device=a.device)
+
+    def one(ev=None):
+        if ev:
+            ev[0].record()
+        s.factor(a)
+        _, st = s.solve(b, x, tol=cfg["tol"], maxit=args.maxit)
+        if ev:
+            ev[1].record()
+        torch.sub(x, xt, out=g)
+        _, sta = s.solve_adjoint(g, lam, tol=cfg["tol"], maxit=args.maxit)
+        if ev:
+            ev[2].record()
+        s.band_grad(lam, x, gband)
+        if ev:
+            ev[3].record()
+        return st, sta
+
+    for _ in range(args.warmup):
+        one()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
+    stats = [one(ev) for ev in evs]
+    torch.cuda.synchronize()
+    fwd = sum(e[0].elapsed_time(e[1]) for e in evs) / args.steps
+    bwd = sum(e[1].elapsed_time(e[3]) for e in evs) / args.steps
+    # the band gradient alone: 10 launches queued behind a spin on the GPU, so
+    # that they run back to back (one launch is shorter than the host's
+    # launch latency that follows the adjoint solve's final synchronization)
+    reps = 10
+    ga, gb = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda._sleep(5_000_000)
+    ga.record()
+    for _ in range(reps):
+        s.band_grad(lam, x, gband)
+    gb.record()
+    torch.cuda.synchronize()
+    grad = ga.elapsed_time(gb) / reps
+    s.profile(True)
+    for _ in range(args.steps):
+        torch.sub(x, xt, out=g)
+        s.solve_adjoint(g, lam, tol=cfg["tol"], maxit=args.maxit)
+    torch.cuda.synchronize()
+    kt = s.kernel_times()
+    s.profile(False)
+    s.close()
+    st, sta = stats[-1]
+    grad_bytes = 8.0 * (2 * k + 1) * n + 16.0 * n          # writes the band, reads lambda and x
+    return {
+        "forward_ms": round(fwd, 4), "backward_ms": round(bwd, 4),
+        "adjoint_iters": sta.iters, "adjoint_restarts": sta.restarts,
+        "adjoint_rel_resid_true": sta.rel_resid_true, "adjoint_converged": bool(sta.converged),
+        "forward_iters": st.iters,
+        "band_grad": {"avg_us": round(grad * 1e3, 2), "bytes_per_unit": grad_bytes,
+                      "algorithmic_GBps": grad_bytes / (grad * 1e-3) / 1e9,
+                      "frac_of_hbm_peak": grad_bytes / (grad * 1e-3) / 1e9 / HBM_PEAK_GBS},
+        "adjoint_kernels": {c: {"ms_per_step": ms_ / args.steps, "launches_per_step": cnt / args.steps}
+                            for c, (ms_, cnt) in kt.items() if cnt},
+    }
+
+
 # The paper's dense banded studies (Sec. 4.1.1-4.1.3), on synthetic matrices
 # generated as for the benchmark (sapgen): time to solution of SaP-C and SaP-D
 # with an FP32 preconditioner and FP64 BiCGStab(2), as the paper runs them.
@@ -421,6 +499,9 @@ def main():
     ap.add_argument("--batch-rhs", type=int, default=8,
                     help="also time sap_solve_batch with this many right-hand sides on the "
                          "same factorization (0: skip)")
+    ap.add_argument("--backward", choices=("auto", "on", "off"), default="auto",
+                    help="also time the backward pass (adjoint solve and band gradient); "
+                         "auto: for the workloads whose configuration includes it")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 1 GiB device copy (counter calibration)")
     ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -591,6 +672,10 @@ def main():
             out["cold"][p_] = ent
     if args.batch_rhs > 0:
         out["multi_rhs"] = [run_batch(args, p_, pb, a, args.batch_rhs) for p_ in runs]
+    backward = args.backward == "on" or (args.backward == "auto" and args.workload in
+                                         ("sapc_n100k_k32_adjoint", "sapc_n200k_k100_weak"))
+    if backward:
+        out["backward"] = {p_: run_backward(args, p_, pb, a, b) for p_ in runs}
     if args.copy_calibration:
         src_t = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
         dst_t = torch.empty_like(src_t)

@@ -122,26 +122,29 @@ hipError_t launch_spmv_multi(const double *band, int64_t n, int k, const double 
     return hipGetLastError();
 }
 
+// g = band(-lambda x^T): diagonal q of the band (row = column + q - K) is
+// one row of the grid, its columns spread over blockIdx.x, so no thread
+// divides an index; lambda and x (N doubles each) are re-read from cache by
+// every diagonal.
 __global__ __launch_bounds__(256) void k_band_grad(int64_t n, int k,
                                                    const double *__restrict__ lam,
                                                    const double *__restrict__ x,
                                                    double *__restrict__ g)
 {
-    const int64_t total = (int64_t)(2 * k + 1) * n;
-    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total;
-         e += (int64_t)gridDim.x * 256) {
-        const int64_t q = e / n, c = e - q * n;
-        const int64_t r = c + q - k;
-        g[e] = (r >= 0 && r < n) ? -lam[r] * x[c] : 0.0;
+    const int64_t d = (int64_t)blockIdx.y - k;
+    double *gq = g + (int64_t)blockIdx.y * n;
+    for (int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x; c < n; c += (int64_t)gridDim.x * 256) {
+        const int64_t r = c + d;
+        gq[c] = (r >= 0 && r < n) ? -lam[r] * x[c] : 0.0;
     }
 }
 
 hipError_t launch_band_grad(int64_t n, int k, const double *lam, const double *x, double *g,
                             hipStream_t s)
 {
-    const int64_t total = (int64_t)(2 * k + 1) * n;
-    const int64_t nblk = min((total + 255) / 256, (int64_t)65536);
-    hipLaunchKernelGGL(k_band_grad, dim3((unsigned)nblk), dim3(256), 0, s, n, k, lam, x, g);
+    const int64_t nblk = min((n + 255) / 256, (int64_t)4096);
+    hipLaunchKernelGGL(k_band_grad, dim3((unsigned)nblk, (unsigned)(2 * k + 1)), dim3(256), 0, s,
+                       n, k, lam, x, g);
     return hipGetLastError();
 }
 
