@@ -182,7 +182,22 @@ def summarize_counters(fetch_dir, write_dir, workload, prec):
 
 def sapgen_workload(name):
     import sapgen
-    return dict(sapgen.WORKLOADS[name])
+    return dict(sapgen.WORKLOADS.get(name) or sapgen.SPD_WORKLOADS[name])
+
+
+def outer_solve(args, s, b, x):
+    """One solve with the outer method of the run: BiCGStab(2) or, for the
+    symmetric positive definite workloads, CG."""
+    cfg = args.cfg
+    if args.solver == "cg":
+        return s.solve_cg(b, x, tol=cfg["tol"], maxit=args.maxit)
+    return s.solve(b, x, tol=cfg["tol"], maxit=args.maxit)
+
+
+def applications(args, st):
+    """Preconditioner applications of one solve (BiCGStab(2) applies it
+    once more than its counted operator applications, to b)."""
+    return st.n_apply + (0 if args.solver == "cg" else 1)
 
 
 def run_cold(args, prec, a, b):
@@ -199,14 +214,14 @@ def run_cold(args, prec, a, b):
     flush = torch.empty(1 << 27, dtype=torch.float64, device=a.device)
     for _ in range(args.warmup):
         s.factor(a)
-        s.solve(b, x, tol=cfg["tol"], maxit=args.maxit)
+        outer_solve(args, s, b, x)
     st_ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
     en_ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
     for i in range(args.steps):
         flush.fill_(float(i))
         st_ev[i].record()
         s.factor(a)
-        s.solve(b, x, tol=cfg["tol"], maxit=args.maxit)
+        outer_solve(args, s, b, x)
         en_ev[i].record()
     torch.cuda.synchronize()
     ms = sum(st_ev[i].elapsed_time(en_ev[i]) for i in range(args.steps)) / args.steps
@@ -214,7 +229,7 @@ def run_cold(args, prec, a, b):
     for i in range(args.steps):
         flush.fill_(float(i))
         s.factor(a)
-        s.solve(b, x, tol=cfg["tol"], maxit=args.maxit)
+        outer_solve(args, s, b, x)
     torch.cuda.synchronize()
     kt = s.kernel_times()
     s.profile(False)
@@ -232,7 +247,7 @@ def run_gpu(args, prec, pb, a, b):
     x = torch.empty_like(b)
     for _ in range(args.warmup):
         s.factor(a)
-        s.solve(b, x, tol=cfg["tol"], maxit=args.maxit)
+        outer_solve(args, s, b, x)
     # the timed steps run without per-launch events; the per-kernel device
     # times come from as many steps again with events around every launch
     stats = []
@@ -240,14 +255,14 @@ def run_gpu(args, prec, pb, a, b):
     t0 = time.perf_counter()
     for _ in range(args.steps):
         s.factor(a)
-        _, st = s.solve(b, x, tol=cfg["tol"], maxit=args.maxit)
+        _, st = outer_solve(args, s, b, x)
         stats.append(st)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     s.profile(True)
     for _ in range(args.steps):
         s.factor(a)
-        s.solve(b, x, tol=cfg["tol"], maxit=args.maxit)
+        outer_solve(args, s, b, x)
     torch.cuda.synchronize()
     kt = s.kernel_times()
     s.profile(False)
@@ -442,9 +457,10 @@ def cpu_model() -> str:
     return "unknown"
 
 
-def cpu_baseline(cfg, pb, reps):
-    """The CPU oracle (plain FP64 SaP-C + BiCGStab(2)) on the same workload,
-    single thread, median of `reps` full solves."""
+def cpu_baseline(cfg, pb, reps, solver="bicgstab2"):
+    """The CPU oracle (plain FP64 SaP + BiCGStab(2), or CG for the SPD
+    workloads) on the same workload, single thread, median of `reps` full
+    solves."""
     from threadpoolctl import threadpool_limits
 
     import oracle
@@ -452,8 +468,9 @@ def cpu_baseline(cfg, pb, reps):
     with threadpool_limits(1):
         for _ in range(reps):
             t0 = time.perf_counter()
-            x, res, _ = oracle.sap_solve(pb.band, cfg["n"], cfg["k"], pb.b, cfg["p"],
-                                         cfg["mode"] == "coupled", tol=cfg["tol"])
+            fn = oracle.sap_solve_cg if solver == "cg" else oracle.sap_solve
+            x, res, _ = fn(pb.band, cfg["n"], cfg["k"], pb.b, cfg["p"],
+                           cfg["mode"] == "coupled", tol=cfg["tol"])
             times.append((time.perf_counter() - t0) * 1e3)
     return statistics.median(times), x, res
 
@@ -499,6 +516,9 @@ def main():
     ap.add_argument("--batch-rhs", type=int, default=8,
                     help="also time sap_solve_batch with this many right-hand sides on the "
                          "same factorization (0: skip)")
+    ap.add_argument("--solver", choices=("auto", "bicgstab2", "cg"), default="auto",
+                    help="outer Krylov method; auto: CG for the symmetric positive definite "
+                         "workloads, BiCGStab(2) otherwise")
     ap.add_argument("--backward", choices=("auto", "on", "off"), default="auto",
                     help="also time the backward pass (adjoint solve and band gradient); "
                          "auto: for the workloads whose configuration includes it")
@@ -527,11 +547,15 @@ def main():
     import torch
 
     import sapgen
-    cfg = dict(sapgen.WORKLOADS[args.workload])
+    cfg = sapgen_workload(args.workload)
     args.cfg = cfg
+    spd = args.workload in sapgen.SPD_WORKLOADS
+    if args.solver == "auto":
+        args.solver = "cg" if spd else "bicgstab2"
     n, k = cfg["n"], cfg["k"]
     pb = sapgen.make_problem(n, k, d=cfg["d"], seed=args.seed,
-                             row_scale_decades=cfg["row_scale_decades"])
+                             row_scale_decades=cfg["row_scale_decades"],
+                             symmetric=cfg.get("symmetric", False))
     dev = torch.device("cuda:0")
     a = torch.from_numpy(pb.band).to(dev)
     b = torch.from_numpy(pb.b).to(dev)
@@ -555,7 +579,7 @@ def main():
     # (chunked form: zero-state pass, then the pass from the chained states);
     # its unit is the whole sweep.  Sweeps per step: 2 (SaP-D) or 4 (SaP-C)
     # per preconditioner application, n_apply + 1 applications per solve.
-    sweeps = sum((st.n_apply + 1) * (4 if coupled else 2) for st in r["stats"])
+    sweeps = sum(applications(args, st) * (4 if coupled else 2) for st in r["stats"])
     units = {"sweep": sweeps}
     kernels = {}
     for name, val in r["kt"].items():
@@ -613,7 +637,7 @@ def main():
         "dtype": "f64" if head == "fp64" else "f32-factor/f64-krylov", "data": "synthetic",
         "config": {"workload": args.workload, "n": n, "k": k, "p": cfg["p"],
                    "mode": cfg["mode"], "d": cfg["d"], "tol": cfg["tol"], "seed": args.seed,
-                   "factor_prec": head},
+                   "factor_prec": head, "solver": args.solver},
         "roofline": roof,
         "runs": {p_: summary(p_) for p_ in runs},
         "kernels": kernels,
@@ -625,6 +649,8 @@ def main():
                        "fp32_factor_ms": round(runs["fp32"]["ms"], 4),
                        "fp32_speedup": round(runs["fp64"]["ms"] / runs["fp32"]["ms"], 3)}
     race_ds = [float(v) for v in str(args.race_d).split(",") if v.strip() and float(v) > 0]
+    if spd or args.solver == "cg":
+        race_ds = []                # the weak-dominance race is a BiCGStab(2) study
     if race_ds and "fp64" in runs and "fp32" in runs:
         # the same race where the FP64 preconditioner is no longer exact after
         # one application, so both precisions iterate
@@ -661,7 +687,7 @@ def main():
             cms, ckt = run_cold(args, p_, a, b)
             sfp = 8 if p_ == "fp64" else 4
             ent = {"ms_per_step": round(cms, 4)}
-            nsw = sum((st.n_apply + 1) * (4 if coupled else 2) for st in runs[p_]["stats"])
+            nsw = sum(applications(args, st) * (4 if coupled else 2) for st in runs[p_]["stats"])
             for name, nunits, bpu in (("sweep", nsw, sweep_bytes(n, k, sfp, coupled)),
                                       ("spmv", None, spmv_bytes(n, k))):
                 tms, cnt = ckt[name]
@@ -670,7 +696,7 @@ def main():
                     ent[name] = {"avg_us": round(1e3 * tms / nu, 2),
                                  "algorithmic_GBps": round(bpu / (1e-3 * tms / nu) / 1e9, 1)}
             out["cold"][p_] = ent
-    if args.batch_rhs > 0:
+    if args.batch_rhs > 0 and args.solver != "cg":
         out["multi_rhs"] = [run_batch(args, p_, pb, a, args.batch_rhs) for p_ in runs]
     backward = args.backward == "on" or (args.backward == "auto" and args.workload in
                                          ("sapc_n100k_k32_adjoint", "sapc_n200k_k100_weak"))
@@ -684,13 +710,13 @@ def main():
         out["copy_calibration_bytes"] = {"read": src_t.numel() * 8, "write": dst_t.numel() * 8}
         del src_t, dst_t
     if not args.no_cpu:
-        cms, xo, res = cpu_baseline(cfg, pb, args.cpu_reps)
+        cms, xo, res = cpu_baseline(cfg, pb, args.cpu_reps, args.solver)
         out["cpu_baseline"] = {
             "value": round(cms, 2), "unit": "ms", "cores": 1, "kind": "oracle",
             "sample": "full workload, median of %d oracle solves (FP64 SaP-%s, P=%d, "
-                      "BiCGStab(2) to %g), 1 thread" % (args.cpu_reps,
-                                                        "C" if coupled else "D",
-                                                        cfg["p"], cfg["tol"]),
+                      "%s to %g), 1 thread" % (args.cpu_reps, "C" if coupled else "D", cfg["p"],
+                                               "CG" if args.solver == "cg" else "BiCGStab(2)",
+                                               cfg["tol"]),
             "host_cpus": os.cpu_count(), "cpu_model": cpu_model()}
         for p_ in runs:
             out["runs"][p_]["rel_err_vs_oracle"] = float(
