@@ -350,6 +350,69 @@ def run_backward(args, prec, pb, a, b):
     }
 
 
+def run_sparse(args):
+    """The sparse front end on a synthetic sparse system (sapgen's hidden band
+    of half-bandwidth K0, scattered by random permutations): the host analysis
+    split into the time buckets T_DB (matching and scaling), T_CM
+    (Cuthill-McKee) and T_Drop (reordered structure and drop-off), then per
+    step on the GPU T_Asmbl (values and band of A_hat), sap_factor and
+    sap_solve_sparse, timed with events.  Prints one JSON line."""
+    import numpy as np
+    import torch
+
+    import sapgen
+    from paper_1509_07919_amd import SapSolver, SapSparse
+
+    n, k0, dens = (float(v) for v in args.sparse.split(","))
+    n, k0 = int(n), int(k0)
+    sp = sapgen.make_sparse_problem(n, k0, density=dens, seed=args.seed)
+    t0 = time.perf_counter()
+    plan = SapSparse(n, sp.rowptr, sp.colidx, sp.vals, db=True, cm=True,
+                     drop_frac=args.sparse_drop)
+    t_create = (time.perf_counter() - t0) * 1e3
+    info, times = plan.info(), plan.times()
+    k = info["k"]
+    dev = torch.device("cuda:0")
+    vals = torch.from_numpy(sp.vals).to(dev)
+    b = torch.from_numpy(sp.b).to(dev)
+    x = torch.empty_like(b)
+    band = plan.assemble(vals)
+    line = {"sparse": {"n": n, "k0": k0, "density": dens, "nnz": int(sp.rowptr[-1]),
+                       "drop_frac": args.sparse_drop, "k": k, "k_full": info["k_full"],
+                       "p": args.sparse_p, "mode": "coupled", "tol": 1e-10, "seed": args.seed},
+            "analysis_ms": {"total": round(t_create, 2),
+                            **{kk: round(v, 2) for kk, v in times.items()}},
+            "runs": {}}
+    for prec in args.precs.split(","):
+        s = SapSolver(n, k, args.sparse_p, mode="coupled", factor_prec=prec)
+        for _ in range(args.warmup):
+            plan.assemble(vals, band)
+            s.factor(band)
+            s.solve_sparse(plan, b, x, tol=1e-10, maxit=args.maxit)
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+        sts = []
+        for ev in evs:
+            ev[0].record()
+            plan.assemble(vals, band)
+            ev[1].record()
+            s.factor(band)
+            _, st = s.solve_sparse(plan, b, x, tol=1e-10, maxit=args.maxit)
+            ev[2].record()
+            sts.append(st)
+        torch.cuda.synchronize()
+        st = sts[-1]
+        xs = x.cpu().numpy()
+        line["runs"][prec] = {
+            "ms": round(sum(e[0].elapsed_time(e[2]) for e in evs) / args.steps, 4),
+            "t_asmbl_ms": round(sum(e[0].elapsed_time(e[1]) for e in evs) / args.steps, 4),
+            "t_factor_ms": round(st.t_factor_ms, 4), "t_solve_ms": round(st.t_solve_ms, 4),
+            "iters": st.iters, "restarts": st.restarts, "converged": bool(st.converged),
+            "rel_err_vs_xtrue": float(np.linalg.norm(xs - sp.x_true) / np.linalg.norm(sp.x_true))}
+        s.close()
+    plan.close()
+    print(json.dumps(line), flush=True)
+
+
 # The paper's dense banded studies (Sec. 4.1.1-4.1.3), on synthetic matrices
 # generated as for the benchmark (sapgen): time to solution of SaP-C and SaP-D
 # with an FP32 preconditioner and FP64 BiCGStab(2), as the paper runs them.
@@ -527,6 +590,12 @@ def main():
     ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="build profiles/traffic_<workload>.json from two rocprofv3 --pmc "
                          "runs (FETCH_SIZE, WRITE_SIZE) of this script with --precs <one>")
+    ap.add_argument("--sparse", metavar="N,K0,DENSITY",
+                    help="instead of the benchmark line, time the sparse front end on a "
+                         "synthetic sparse system (e.g. 200000,50,0.2)")
+    ap.add_argument("--sparse-drop", type=float, default=0.0,
+                    help="drop-off fraction for --sparse")
+    ap.add_argument("--sparse-p", type=int, default=64, help="partitions for --sparse")
     ap.add_argument("--experiment", choices=sorted(EXPERIMENTS),
                     help="instead of the benchmark line, run one of the paper's dense "
                          "sensitivity studies and print one JSON line per configuration")
@@ -537,6 +606,9 @@ def main():
         sys.exit(2)
     if args.experiment:
         run_experiment(args)
+        return
+    if args.sparse:
+        run_sparse(args)
         return
     if args.summarize_counters:
         summarize_counters(args.summarize_counters[0], args.summarize_counters[1], args.workload,

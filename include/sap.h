@@ -181,6 +181,12 @@ int sap_sparse_create(int64_t n, const int64_t *rowptr, const int32_t *colidx,
 int sap_sparse_info(sap_sparse sp, int32_t *k, int32_t *k_full, int32_t *new_row,
                     int32_t *new_col, double *row_scale, double *col_scale);
 
+/* Host time of the three analysis stages of sap_sparse_create, the sparse
+ * front end's share of the time buckets of Sec. 3.4: the matching with its
+ * scaling (T_DB), Cuthill-McKee (T_CM), and forming the reordered structure
+ * with the drop-off K (T_Drop), in ms.  Any pointer may be NULL. */
+int sap_sparse_times(sap_sparse sp, double *t_db_ms, double *t_cm_ms, double *t_drop_ms);
+
 /* On the GPU: the values of A_hat from A's values (device array in the
  * original CSR order, same structure as at sap_sparse_create) and the band
  * of A_hat (device, (2K+1)*N doubles, band layout, padding zero) to hand to

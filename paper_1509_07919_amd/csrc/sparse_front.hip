@@ -28,6 +28,7 @@
 #include "sap_internal.h"
 
 #include <algorithm>
+#include <chrono>
 #include <climits>
 #include <cmath>
 #include <limits>
@@ -210,21 +211,42 @@ bool db_match(const Csr &c, std::vector<int64_t> &sigma, std::vector<double> &u,
     return true;
 }
 
-// Neighbour lists of the structure of B + B^T without self loops, sorted.
-std::vector<std::vector<int64_t>> sym_adjacency(const Csr &b)
+// Neighbour lists of the structure of B + B^T without self loops, sorted and
+// without repeats, as one CSR array (counted, filled, then each list sorted).
+struct Adjacency {
+    std::vector<int64_t> ptr, idx;
+    int64_t degree(int64_t i) const { return ptr[i + 1] - ptr[i]; }
+};
+
+Adjacency sym_adjacency(const Csr &b)
 {
     const int64_t n = b.n;
-    std::vector<std::vector<int64_t>> adj(n);
+    std::vector<int64_t> cnt(n + 1, 0);
     for (int64_t i = 0; i < n; ++i)
         for (int64_t e = b.ptr[i]; e < b.ptr[i + 1]; ++e) {
             const int64_t j = b.col[e];
             if (j == i) continue;
-            adj[i].push_back(j);
-            adj[j].push_back(i);
+            ++cnt[i + 1];
+            ++cnt[j + 1];
         }
-    for (auto &a : adj) {
-        std::sort(a.begin(), a.end());
-        a.erase(std::unique(a.begin(), a.end()), a.end());
+    for (int64_t i = 0; i < n; ++i) cnt[i + 1] += cnt[i];
+    std::vector<int64_t> raw(cnt[n]), cur(cnt.begin(), cnt.end() - 1);
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t e = b.ptr[i]; e < b.ptr[i + 1]; ++e) {
+            const int64_t j = b.col[e];
+            if (j == i) continue;
+            raw[cur[i]++] = j;
+            raw[cur[j]++] = i;
+        }
+    Adjacency adj;
+    adj.ptr.assign(n + 1, 0);
+    adj.idx.reserve(raw.size());
+    for (int64_t i = 0; i < n; ++i) {
+        auto first = raw.begin() + cnt[i], end = raw.begin() + cnt[i + 1];
+        std::sort(first, end);
+        end = std::unique(first, end);
+        adj.idx.insert(adj.idx.end(), first, end);
+        adj.ptr[i + 1] = (int64_t)adj.idx.size();
     }
     return adj;
 }
@@ -241,10 +263,10 @@ int64_t half_bandwidth(const Csr &b, const std::vector<int64_t> &new_of_old)
 // One Cuthill-McKee ordering (old index by new position) started at s, then
 // the other components from their least (degree, index) node; `last`
 // receives the last BFS level of s's component.
-void cm_from(const std::vector<std::vector<int64_t>> &adj, const std::vector<int64_t> &deg,
+void cm_from(const Adjacency &adj, const std::vector<int64_t> &deg,
              int64_t s, std::vector<int64_t> &order, std::vector<int64_t> &last)
 {
-    const int64_t n = (int64_t)adj.size();
+    const int64_t n = (int64_t)deg.size();
     std::vector<char> seen(n, 0);
     std::vector<int64_t> dist(n, -1);
     order.clear();
@@ -258,8 +280,8 @@ void cm_from(const std::vector<std::vector<int64_t>> &adj, const std::vector<int
         for (size_t h = base; h < order.size(); ++h) {
             const int64_t x = order[h];
             nb.clear();
-            for (int64_t w : adj[x])
-                if (!seen[w]) nb.push_back(w);
+            for (int64_t e = adj.ptr[x]; e < adj.ptr[x + 1]; ++e)
+                if (!seen[adj.idx[e]]) nb.push_back(adj.idx[e]);
             std::sort(nb.begin(), nb.end(), less);
             for (int64_t w : nb) {
                 seen[w] = 1;
@@ -289,7 +311,7 @@ std::vector<int64_t> cuthill_mckee(const Csr &b, int tries)
     const int64_t n = b.n;
     const auto adj = sym_adjacency(b);
     std::vector<int64_t> deg(n);
-    for (int64_t i = 0; i < n; ++i) deg[i] = (int64_t)adj[i].size();
+    for (int64_t i = 0; i < n; ++i) deg[i] = adj.degree(i);
     auto less = [&](int64_t a, int64_t c) { return deg[a] != deg[c] ? deg[a] < deg[c] : a < c; };
     int64_t start = 0;
     for (int64_t v = 1; v < n; ++v)
@@ -338,6 +360,8 @@ struct SparsePlan {
     double *d_row_scale = nullptr, *d_col_scale = nullptr;
     double *bhat = nullptr, *yhat = nullptr;
     bool assembled = false;
+    // host time of the analysis stages (Sec. 3.4 buckets T_DB, T_CM, T_Drop)
+    double t_db_ms = 0.0, t_cm_ms = 0.0, t_drop_ms = 0.0;
 };
 
 }  // namespace sap
@@ -405,6 +429,11 @@ int sap_sparse_create(int64_t n, const int64_t *rowptr, const int32_t *colidx, c
     if (!p) return sfail(SAP_ERR_INVALID, "out of host memory");
     p->n = n;
     p->nnz = nnz;
+    using clk = std::chrono::steady_clock;
+    auto ms_since = [](clk::time_point t0) {
+        return std::chrono::duration<double, std::milli>(clk::now() - t0).count();
+    };
+    auto t0 = clk::now();
     // DB: costs c_ij = log a_i - log|a_ij| (explicit zeros are not edges)
     std::vector<int64_t> sigma(n);
     std::vector<double> rs(n, 1.0), cs(n, 1.0);
@@ -435,6 +464,8 @@ int sap_sparse_create(int64_t n, const int64_t *rowptr, const int32_t *colidx, c
     } else {
         std::iota(sigma.begin(), sigma.end(), 0);
     }
+    p->t_db_ms = ms_since(t0);
+    t0 = clk::now();
     // B = Q A: row i of A becomes row sigma[i]
     Csr b;
     b.n = n;
@@ -461,18 +492,30 @@ int sap_sparse_create(int64_t n, const int64_t *rowptr, const int32_t *colidx, c
         p->new_row[i] = (int32_t)pos[sigma[i]];
         p->new_col[i] = (int32_t)pos[i];
     }
+    p->t_cm_ms = ms_since(t0);
+    t0 = clk::now();
     p->row_scale = rs;
     p->col_scale = cs;
     // the reordered structure, entries sorted by (row, column) of A_hat
+    // (rows of A_hat by counting, then each row's few entries by column; the
+    // keys are unique since no column repeats within a row)
     std::vector<int64_t> ent(nnz), erow(nnz);
     for (int64_t i = 0; i < n; ++i)
         for (int64_t e = a.ptr[i]; e < a.ptr[i + 1]; ++e) erow[e] = i;
-    std::iota(ent.begin(), ent.end(), 0);
-    std::sort(ent.begin(), ent.end(), [&](int64_t x, int64_t y) {
-        const int32_t rx = p->new_row[erow[x]], ry = p->new_row[erow[y]];
-        if (rx != ry) return rx < ry;
-        return p->new_col[a.col[x]] < p->new_col[a.col[y]];
-    });
+    {
+        std::vector<int64_t> cur(n + 1, 0);
+        for (int64_t i = 0; i < n; ++i) cur[p->new_row[i] + 1] = a.ptr[i + 1] - a.ptr[i];
+        for (int64_t r = 0; r < n; ++r) cur[r + 1] += cur[r];
+        for (int64_t e = 0; e < nnz; ++e) ent[cur[p->new_row[erow[e]]]++] = e;
+        int64_t lo = 0;
+        for (int64_t r = 0; r < n; ++r) {
+            const int64_t hi = cur[r];          // end of row r after the fill
+            std::sort(ent.begin() + lo, ent.begin() + hi, [&](int64_t x, int64_t y) {
+                return p->new_col[a.col[x]] < p->new_col[a.col[y]];
+            });
+            lo = hi;
+        }
+    }
     std::vector<int64_t> hptr(n + 1, 0);
     std::vector<int32_t> hcol(nnz);
     std::vector<double> hscale(nnz);
@@ -506,6 +549,7 @@ int sap_sparse_create(int64_t n, const int64_t *rowptr, const int32_t *colidx, c
     p->h_colidx = std::move(hcol);
     p->h_src = std::move(ent);
     p->h_escale = std::move(hscale);
+    p->t_drop_ms = ms_since(t0);
     *out = p;
     return SAP_OK;
 }
@@ -546,6 +590,15 @@ int sap_sparse_info(sap_sparse p, int32_t *k, int32_t *k_full, int32_t *new_row,
     if (new_col) std::copy(p->new_col.begin(), p->new_col.end(), new_col);
     if (row_scale) std::copy(p->row_scale.begin(), p->row_scale.end(), row_scale);
     if (col_scale) std::copy(p->col_scale.begin(), p->col_scale.end(), col_scale);
+    return SAP_OK;
+}
+
+int sap_sparse_times(sap_sparse p, double *t_db_ms, double *t_cm_ms, double *t_drop_ms)
+{
+    if (!p) return sfail(SAP_ERR_INVALID, "null plan");
+    if (t_db_ms) *t_db_ms = p->t_db_ms;
+    if (t_cm_ms) *t_cm_ms = p->t_cm_ms;
+    if (t_drop_ms) *t_drop_ms = p->t_drop_ms;
     return SAP_OK;
 }
 

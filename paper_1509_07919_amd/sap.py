@@ -36,7 +36,8 @@ EXPORTED = ("sap_workspace_bytes", "sap_create", "sap_factor", "sap_solve",
             "sap_precond_apply", "sap_get_tips", "sap_profile", "sap_kernel_time",
             "sap_destroy", "sap_last_error", "sap_solve_noalloc", "sap_solve_cg", "sap_solve_batch",
             "sap_get_factor_rows", "sap_tips_phase_times", "sap_sparse_create",
-            "sap_sparse_info", "sap_sparse_assemble", "sap_solve_sparse", "sap_sparse_destroy")
+            "sap_sparse_info", "sap_sparse_times", "sap_sparse_assemble", "sap_solve_sparse",
+            "sap_sparse_destroy")
 
 KERNELS = ("norm", "lu", "tips", "sweep", "corr", "spmv", "krylov", "xfer")
 
@@ -99,6 +100,7 @@ def load_library(path: str = LIB_PATH):
     lib.sap_get_factor_rows.argtypes = [vp, i32, i64, i64, vp, vp]
     lib.sap_tips_phase_times.argtypes = [vp, vp, vp]
     lib.sap_sparse_create.argtypes = [i64, vp, vp, vp, i32, i32, dbl, P(vp)]
+    lib.sap_sparse_times.argtypes = [vp, P(dbl), P(dbl), P(dbl)]
     lib.sap_sparse_info.argtypes = [vp, P(i32), P(i32), vp, vp, vp, vp]
     lib.sap_sparse_assemble.argtypes = [vp, vp, vp, vp]
     lib.sap_solve_sparse.argtypes = [vp, vp, vp, vp, dbl, i32, vp, P(sap_stats)]
@@ -357,6 +359,13 @@ class SapSparse:
                                               rs.ctypes.data_as(vp), cs.ctypes.data_as(vp)))
         return {"k": k.value, "k_full": kf.value, "new_row": nr, "new_col": nc,
                 "row_scale": rs, "col_scale": cs}
+
+    def times(self) -> dict:
+        """Host ms of the analysis stages: matching and scaling, Cuthill-McKee,
+        the reordered structure with the drop-off."""
+        t = [ctypes.c_double(0) for _ in range(3)]
+        _check(load_library().sap_sparse_times(self.plan, *[ctypes.byref(v) for v in t]))
+        return {"t_db_ms": t[0].value, "t_cm_ms": t[1].value, "t_drop_ms": t[2].value}
 
     def assemble(self, vals: torch.Tensor, band: torch.Tensor | None = None) -> torch.Tensor:
         """The band of A_hat (device) from A's values (device, CSR order)."""
