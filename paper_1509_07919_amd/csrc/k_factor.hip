@@ -680,13 +680,15 @@ __global__ __launch_bounds__(NT) void k_banded_lu_blk(LuArgs<T> a)
     if (tid == 0 && zero_piv) a.status[1] = 1;
 }
 
+constexpr size_t kLuBlkStaticLds = 64;   // bytes of static LDS in k_banded_lu_blk (tau_sh), rounded up
+
 template <typename T, int B, int S, int NT, int RPL>
 static hipError_t launch_lu_blk(const LuArgs<T> &a, hipStream_t s)
 {
     const int k = a.pt.k, KB = k + B;
     const size_t lds = (2 * (size_t)KB * (KB + 1) + 2 * (size_t)(2 * k + 3) * S +
                         2 * (size_t)B) * sizeof(T);
-    if (lds > kMaxLds) return hipErrorInvalidValue;
+    if (lds + kLuBlkStaticLds > kMaxLds) return hipErrorInvalidValue;
     auto kern = k_banded_lu_blk<T, B, S, NT, RPL>;
     hipError_t e = hipFuncSetAttribute((const void *)kern,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -710,14 +712,26 @@ static hipError_t launch_lu_cfg(const LuArgs<T> &a, hipStream_t s)
     return hipGetLastError();
 }
 
+// LDS of the blocked kernel (two windows, two stage buffers, the reciprocals);
+// the static tau_sh takes some of the CU's LDS beside it
+static size_t lu_blk_lds(int k, int b, int s, size_t szt)
+{
+    const size_t kb = (size_t)k + b;
+    return (2 * kb * (kb + 1) + 2 * (size_t)(2 * k + 3) * s + 2 * (size_t)b) * szt +
+           kLuBlkStaticLds;
+}
+
 template <>
 hipError_t launch_banded_lu<double>(const LuArgs<double> &a, hipStream_t s)
 {
     const int k = a.pt.k;
     // blocked kernel: panel width 8 (the fastest measured at K = 10..50), or 4,
-    // with K + B <= 64 (one panel row per lane)
+    // with K + B <= 64 (one panel row per lane), then two panel rows per lane
+    // while the window fits the LDS with stage chunks of 16 (K <= 78)
     if (k + 8 <= 64) return launch_lu_blk<double, 8, 32, 512, 1>(a, s);
     if (k + 4 <= 64) return launch_lu_blk<double, 4, 32, 512, 1>(a, s);
+    if (k + 8 <= 128 && lu_blk_lds(k, 8, 16, sizeof(double)) <= kMaxLds)
+        return launch_lu_blk<double, 8, 16, 512, 2>(a, s);
     if (k < 64 && lu_mfma_supported(k, false)) return launch_lu_mfma<double>(a, s);
     // matrix-core kernel where its register window fits without spilling
     // (K <= 96), the register ring up to K = 127, then the matrix-core kernel
@@ -729,13 +743,6 @@ hipError_t launch_banded_lu<double>(const LuArgs<double> &a, hipStream_t s)
     if (k < 64) return launch_lu_cfg<double, 64, 32, 256>(a, s);
     if (k < 128) return launch_lu_cfg<double, 128, 16, 1024>(a, s);
     return launch_lu_wide(a, a.wide, s);      // K > 160
-}
-
-// LDS of the blocked kernel (two windows, two stage buffers, the reciprocals)
-static size_t lu_blk_lds(int k, int b, int s, size_t szt)
-{
-    const size_t kb = (size_t)k + b;
-    return (2 * kb * (kb + 1) + 2 * (size_t)(2 * k + 3) * s + 2 * (size_t)b) * szt;
 }
 
 template <>

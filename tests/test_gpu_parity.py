@@ -124,6 +124,7 @@ WIDE_CASES = [
     (6400, 208, 8, "fp32"), (7001, 255, 6, "fp32"), (6400, 161, 8, "fp64"),
     (6400, 200, 8, "fp64"), (6400, 208, 8, "fp64"), (7001, 255, 6, "fp64"),
     (5003, 80, 5, "fp32"), (6007, 104, 6, "fp32"),
+    (5003, 61, 5, "fp64"), (5003, 73, 5, "fp64"), (6007, 78, 6, "fp64"), (6007, 79, 6, "fp64"),
 ]
 
 
@@ -497,6 +498,8 @@ LU_ROW_CASES = [
     (1001, 1, 3, "fp64"), (2003, 3, 5, "fp32"), (3001, 13, 4, "fp64"), (4099, 33, 6, "fp32"),
     (5003, 50, 5, "fp64"), (5003, 50, 5, "fp32"), (6007, 56, 7, "fp64"), (6007, 56, 7, "fp32"),
     (203, 30, 4, "fp64"), (157, 45, 3, "fp32"),
+    # FP64 with two panel rows per lane (K = 61..78, while the window fits the LDS)
+    (5003, 61, 5, "fp64"), (5003, 73, 5, "fp64"), (6007, 78, 6, "fp64"),
 ]
 
 
