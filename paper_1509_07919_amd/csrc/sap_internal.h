@@ -287,7 +287,7 @@ hipError_t launch_fill(double *v, double val, int64_t n, hipStream_t s);
 // ------------------------------------------------------------- sparse A
 // A reordered sparse matrix on the device (CSR), for the Krylov product
 struct CsrDev {
-    int64_t n;
+    int64_t n, nnz;
     const int64_t *rowptr;
     const int32_t *colidx;
     const double *vals;

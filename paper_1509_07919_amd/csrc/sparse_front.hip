@@ -61,15 +61,25 @@ __global__ void k_band_from_csr(const int64_t *__restrict__ rowptr, const int32_
         }
 }
 
-// y = A v, or y = b - A v; one row per thread (a few entries per row)
-__global__ void k_csr_spmv(const int64_t *__restrict__ rowptr, const int32_t *__restrict__ colidx,
-                           const double *__restrict__ a, int64_t n, const double *__restrict__ v,
-                           const double *__restrict__ b, double *__restrict__ y)
+// y = A v, or y = b - A v: L consecutive lanes per row stride through its
+// entries together (loads of neighbouring lanes are neighbouring entries),
+// then their partial sums are added across the L lanes
+template <int L>
+__global__ __launch_bounds__(256) void k_csr_spmv(const int64_t *__restrict__ rowptr,
+                                                  const int32_t *__restrict__ colidx,
+                                                  const double *__restrict__ a, int64_t n,
+                                                  const double *__restrict__ v,
+                                                  const double *__restrict__ b,
+                                                  double *__restrict__ y)
 {
-    for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < n; r += (int64_t)gridDim.x * 256) {
+    const int sub = (int)threadIdx.x & (L - 1);
+    const int64_t step = (int64_t)gridDim.x * (256 / L);
+    for (int64_t r = ((int64_t)blockIdx.x * 256 + threadIdx.x) / L; r < n; r += step) {
         double s = 0.0;
-        for (int64_t e = rowptr[r]; e < rowptr[r + 1]; ++e) s = fma(a[e], v[colidx[e]], s);
-        y[r] = b ? b[r] - s : s;
+        for (int64_t e = rowptr[r] + sub; e < rowptr[r + 1]; e += L) s = fma(a[e], v[colidx[e]], s);
+#pragma unroll
+        for (int o = L / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, L);
+        if (sub == 0) y[r] = b ? b[r] - s : s;
     }
 }
 
@@ -91,12 +101,26 @@ static unsigned grid_for(int64_t n)
     return (unsigned)std::min<int64_t>(std::max<int64_t>(g, 1), 4096);
 }
 
+template <int L>
+static hipError_t launch_csr_spmv_l(const CsrDev &m, const double *v, const double *b, double *y,
+                                   hipStream_t s)
+{
+    hipLaunchKernelGGL(k_csr_spmv<L>, dim3(grid_for(m.n * L)), dim3(256), 0, s, m.rowptr, m.colidx,
+                       m.vals, m.n, v, b, y);
+    return hipGetLastError();
+}
+
+// lanes per row: the power of two at or below the mean row length, 1..32
 hipError_t launch_csr_spmv(const CsrDev &m, const double *v, const double *b, double *y,
                            hipStream_t s)
 {
-    hipLaunchKernelGGL(k_csr_spmv, dim3(grid_for(m.n)), dim3(256), 0, s, m.rowptr, m.colidx, m.vals,
-                       m.n, v, b, y);
-    return hipGetLastError();
+    const int64_t mean = m.nnz / std::max<int64_t>(m.n, 1);
+    if (mean >= 32) return launch_csr_spmv_l<32>(m, v, b, y, s);
+    if (mean >= 16) return launch_csr_spmv_l<16>(m, v, b, y, s);
+    if (mean >= 8) return launch_csr_spmv_l<8>(m, v, b, y, s);
+    if (mean >= 4) return launch_csr_spmv_l<4>(m, v, b, y, s);
+    if (mean >= 2) return launch_csr_spmv_l<2>(m, v, b, y, s);
+    return launch_csr_spmv_l<1>(m, v, b, y, s);
 }
 
 // ------------------------------------------------------------ host stages
@@ -636,6 +660,7 @@ bool sparse_plan_parts(sap_sparse p, CsrDev *m, double **bhat, double **yhat,
 {
     if (!p || !p->assembled) return false;
     m->n = p->n;
+    m->nnz = p->nnz;
     m->rowptr = p->rowptr;
     m->colidx = p->colidx;
     m->vals = p->vals;
