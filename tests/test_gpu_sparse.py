@@ -76,6 +76,9 @@ CASES = [
     (30000, 20, 0.2, 7, 8, "decoupled", "fp64", 0.02),
     (40000, 12, 0.25, 9, 16, "coupled", "fp64", 0.005),
     (777, 3, 0.5, 8, 3, "coupled", "fp64", 0.0),
+    # CSR products with 32 lanes a row (mean row length 41) and one (1.8)
+    (20000, 40, 0.5, 13, 8, "coupled", "fp64", 0.0),
+    (30000, 4, 0.1, 13, 8, "coupled", "fp64", 0.0),
 ]
 
 

@@ -83,6 +83,24 @@ def test_cuthill_mckee_and_drop_equal_the_oracle(n, k0, density, seed):
     assert kk <= 3 * k0                     # the hidden band is recovered
 
 
+def test_analysis_stage_times():
+    """sap_sparse_times: three non-negative host times, whose sum is within
+    the wall time of sap_sparse_create; without reordering the matching and
+    Cuthill-McKee stages do nothing measurable next to the full analysis."""
+    import time
+    sp = sapgen.make_sparse_problem(20000, 10, density=0.3, seed=15)
+    t0 = time.perf_counter()
+    pl = plan(sp)
+    wall = (time.perf_counter() - t0) * 1e3
+    t = pl.times()
+    assert set(t) == {"t_db_ms", "t_cm_ms", "t_drop_ms"}
+    assert all(v >= 0.0 for v in t.values())
+    assert sum(t.values()) <= wall * 1.05 + 1.0
+    assert t["t_db_ms"] > 0.0 and t["t_cm_ms"] > 0.0
+    t_id = plan(sp, db=False, cm=False).times()
+    assert t_id["t_db_ms"] + t_id["t_cm_ms"] < t["t_db_ms"] + t["t_cm_ms"]
+
+
 def test_without_reordering_is_the_identity():
     sp = sapgen.make_sparse_problem(800, 5, seed=4)
     info = plan(sp, db=False, cm=False).info()
