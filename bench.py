@@ -189,7 +189,7 @@ def outer_solve(args, s, b, x):
     """One solve with the outer method of the run: BiCGStab(2) or, for the
     symmetric positive definite workloads, CG."""
     cfg = args.cfg
-    if args.solver == "cg":
+    if getattr(args, "solver", "bicgstab2") == "cg":
         return s.solve_cg(b, x, tol=cfg["tol"], maxit=args.maxit)
     return s.solve(b, x, tol=cfg["tol"], maxit=args.maxit)
 
@@ -197,7 +197,7 @@ def outer_solve(args, s, b, x):
 def applications(args, st):
     """Preconditioner applications of one solve (BiCGStab(2) applies it
     once more than its counted operator applications, to b)."""
-    return st.n_apply + (0 if args.solver == "cg" else 1)
+    return st.n_apply + (0 if getattr(args, "solver", "bicgstab2") == "cg" else 1)
 
 
 def run_cold(args, prec, a, b):
