@@ -133,16 +133,22 @@ __global__ __launch_bounds__(256) void k_band_grad(int64_t n, int k,
 {
     const int64_t d = (int64_t)blockIdx.y - k;
     double *gq = g + (int64_t)blockIdx.y * n;
-    for (int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x; c < n; c += (int64_t)gridDim.x * 256) {
-        const int64_t r = c + d;
-        gq[c] = (r >= 0 && r < n) ? -lam[r] * x[c] : 0.0;
+    // four columns per thread, 256 apart (each store instruction of a wave
+    // still covers 64 consecutive slots)
+    for (int64_t c0 = (int64_t)blockIdx.x * 1024 + threadIdx.x; c0 < n; c0 += (int64_t)gridDim.x * 1024) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t c = c0 + 256 * u;
+            const int64_t r = c + d;
+            if (c < n) gq[c] = (r >= 0 && r < n) ? -lam[r] * x[c] : 0.0;
+        }
     }
 }
 
 hipError_t launch_band_grad(int64_t n, int k, const double *lam, const double *x, double *g,
                             hipStream_t s)
 {
-    const int64_t nblk = min((n + 255) / 256, (int64_t)4096);
+    const int64_t nblk = min((n + 1023) / 1024, (int64_t)4096);
     hipLaunchKernelGGL(k_band_grad, dim3((unsigned)nblk, (unsigned)(2 * k + 1)), dim3(256), 0, s,
                        n, k, lam, x, g);
     return hipGetLastError();
