@@ -1,3 +1,4 @@
+#include <utility>
 // Forward elimination / back substitution with the block factors (the
 // block-diagonal solves D g = b of eq:diag-sys, and the purification solves
 // of Sec. 2.1), arXiv:1509.07919 Sec. 3.1: each is a chain of N_i dependent
@@ -804,6 +805,41 @@ hipError_t launch_sweep<double>(const SweepArgs<double> &a0, hipStream_t s)
     return launch_sweep_kr<double, 5>(a, s);
 }
 
+// Coefficient M of a row held as lane M mod 16 of register M / 16 in every
+// row of sixteen lanes, broadcast to all lanes (DPP row_newbcast).
+template <int M, int NR>
+__device__ __forceinline__ double row_bcast(const double (&c)[NR])
+{
+    return __builtin_amdgcn_mov_dpp(c[M >> 4], 0x150 + (M & 15), 0xf, 0xf, true);
+}
+
+// acc + (lane N of the row of sixteen lanes of c) * x, the broadcast folded
+// into the FMA (DPP row_newbcast on its first operand).  A DPP read of a VGPR
+// needs two wait states after a VALU write of it, which the compiler does not
+// track through inline assembly: WAIT inserts them, and xfer_step asks for it
+// at the first read of each register of c in a step (c is not written within
+// a step).
+template <int N, bool WAIT>
+__device__ __forceinline__ double fma_row_bcast(double acc, double c, double x)
+{
+    if (WAIT)
+        asm("s_nop 1\n\tv_fmac_f64_dpp %0, %1, %2 row_newbcast:%3 row_mask:0xf bank_mask:0xf"
+            : "=v"(acc) : "v"(c), "v"(x), "n"(N), "0"(acc));
+    else
+        asm("v_fmac_f64_dpp %0, %1, %2 row_newbcast:%3 row_mask:0xf bank_mask:0xf"
+            : "=v"(acc) : "v"(c), "v"(x), "n"(N), "0"(acc));
+    return acc;
+}
+
+// One step of the transfer recurrence on the pending sums p: p[m-1] = p[m] + c_m x
+template <int KM, int NR, int... Ms>
+__device__ __forceinline__ void xfer_step(double (&p)[KM], const double (&c)[NR], double x,
+                                          std::integer_sequence<int, Ms...>)
+{
+    ((p[Ms] = fma_row_bcast<(Ms + 1) & 15, Ms == 0 || ((Ms + 1) & 15) == 0>(p[Ms + 1], c[(Ms + 1) >> 4], x),
+      ((Ms & 3) == 3 ? __builtin_amdgcn_sched_barrier(0) : (void)0)), ...);
+}
+
 // ------------------------------------------------------ transfer matrices
 // One workgroup of four waves per chunk that hands a state on (blockIdx.y
 // selects the coefficient array).  Wave w takes the w-th quarter of the
@@ -811,15 +847,15 @@ hipError_t launch_sweep<double>(const SweepArgs<double> &a0, hipStream_t s)
 // state e_i (pending sum 1 for the i-th step), so its K pending sums at the
 // end form row i of the quarter's transfer X_w.  p[m] holds the pending sum
 // of the m-th step after the current one: one step is x = -p[0]*d,
-// p[m-1] = p[m] + F[j][m]*x.  Coefficient rows are loaded one per lane
-// (coefficient m in lane m), eight rows ahead, and broadcast with
-// v_readlane.  The chunk's transfer is the product X_0 X_1 X_2 X_3 (a state
+// p[m-1] = p[m] + F[j][m]*x.  Coefficient rows are loaded four rows ahead,
+// coefficient m into lane m mod 16 of each row of sixteen lanes, and each FMA
+// takes its coefficient through a DPP row broadcast.  The chunk's transfer is the product X_0 X_1 X_2 X_3 (a state
 // s maps to s X), formed through two LDS slots.  All of it is FP64 for either
 // factor precision (FP32 coefficients are widened exactly): see chain_states.
 template <typename T, int KM>
 __global__ __launch_bounds__(256) void k_sweep_xfer(XferArgs<T> a)
 {
-    static_assert(KM <= 64, "coefficients are spread one per lane");
+    static_assert(KM <= 64, "four registers of sixteen coefficients");
     using DT = double;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     DT *Xs = reinterpret_cast<DT *>(smem_raw);   // [2][K][K]
@@ -843,32 +879,55 @@ __global__ __launch_bounds__(256) void k_sweep_xfer(XferArgs<T> a)
     DT p[KM];
 #pragma unroll
     for (int m = 0; m < KM; ++m) p[m] = (m == lane) ? 1.0 : 0.0;
-    constexpr int D = 8;
-    T fr[D], fn[D];
-    auto load = [&](int64_t t0, T *dst) {
+    // coefficient m of a row sits in lane m mod 16 of every row of sixteen
+    // lanes (register m / 16, widened to FP64 at the end of an iteration) and
+    // reaches all lanes through a row broadcast (DPP row_newbcast) folded into
+    // the FMA's operand
+    constexpr int NR = (KM + 15) / 16;
+    constexpr int D = 4;
+    DT fr[D][NR];
+    T fn[D][NR];
+    // raw loads with no branch and no use before the end of an iteration, so
+    // their wait sits there: the row is clamped into the chunk (rows past the
+    // wave's last step are loaded but never used) and slots past K read slot
+    // K + 1, which holds zero
+    auto load = [&](int64_t t0, T (&dst)[D][NR]) {
 #pragma unroll
         for (int e = 0; e < D; ++e) {
             const int64_t t = t0 + e;
-            const int64_t row = fwd ? r0 + t : r1 - 1 - t;
-            dst[e] = (t < t_hi && lane <= k) ? F[(s0 + row) * CP + lane] : T(0);
+            const int64_t row = min(max(fwd ? r0 + t : r1 - 1 - t, r0), r1 - 1);
+#pragma unroll
+            for (int r = 0; r < NR; ++r)
+                dst[e][r] = F[(s0 + row) * CP + min((lane & 15) + 16 * r, k + 1)];
         }
     };
-    load(t_lo, fr);
-    for (int64_t t0 = t_lo; t0 < t_hi; t0 += D) {
+    auto widen = [&]() {
+#pragma unroll
+        for (int e = 0; e < D; ++e)
+#pragma unroll
+            for (int r = 0; r < NR; ++r) fr[e][r] = (DT)fn[e][r];
+    };
+    auto step = [&](const DT (&c)[NR]) {
+        const DT d0 = row_bcast<0>(c);            // unconditional: no branch in a step
+        const DT d = diag ? d0 : 1.0;
+        const DT x = -p[0] * d;
+        xfer_step(p, c, x, std::make_integer_sequence<int, KM - 1>{});
+        p[KM - 1] = 0.0;
+        __builtin_amdgcn_sched_barrier(0);
+    };
+    // D steps an iteration (the shift of p is register renaming), then the rest
+    load(t_lo, fn);
+    widen();
+    int64_t t0 = t_lo;
+    for (; t0 + D <= t_hi; t0 += D) {
         load(t0 + D, fn);
 #pragma unroll
-        for (int e = 0; e < D; ++e) {
-            if (t0 + e < t_hi) {
-                const DT d = diag ? (DT)lane_bcast(fr[e], 0) : 1.0;
-                const DT x = -p[0] * d;
-#pragma unroll
-                for (int m = 1; m < KM; ++m) p[m - 1] = fma((DT)lane_bcast(fr[e], m), x, p[m]);
-                p[KM - 1] = 0.0;
-            }
-        }
-#pragma unroll
-        for (int e = 0; e < D; ++e) fr[e] = fn[e];
+        for (int e = 0; e < D; ++e) step(fr[e]);
+        widen();
     }
+#pragma unroll
+    for (int e = 0; e < D - 1; ++e)
+        if (t0 + e < t_hi) step(fr[e]);
     // X = ((X_0 X_1) X_2) X_3 through two K x K slots of LDS (A: the running
     // product, B: the next factor), so the kernel needs 2 K^2 elements of
     // LDS and three workgroups fit on a CU beside the tips kernel; each
