@@ -382,6 +382,9 @@ __device__ void scalar_op(int op, const double *d, double *sc, double *host)
     case OP_SPEC:
         if (host) host[H_SPEC] = d[0];
         break;
+    case OP_BNORM:
+        if (host) host[H_BNORM] = d[0];
+        break;
     case OP_EXIT:
     case OP_NORM:
         sc[S_NRM2] = d[0]; publish = true;

@@ -488,17 +488,12 @@ int krylov(sap_handle h, int trans, const double *b, double *x, double tol, int3
     const int k = h->opt.k;
     double nrm2 = 0, brk = 0;
 
-    // the factorization's status and ||b|| in one host round trip (the
-    // reduction kernel copies the status words to the host slots)
-    TRY(dots(h, OP_NORM, {{b, b}}, s, h->ptr<int>(h->L.status)));
-    TRY(sync_read(h, s, &nrm2, &brk));
-    loc.n_boosted = (int32_t)h->h_slots[H_NBOOST];
-    if (const int32_t singular = (int32_t)h->h_slots[H_SING]) {
-        if (st) *st = loc;
-        return fail(SAP_ERR_SINGULAR, singular == 1 ? "zero pivot in a diagonal block (boosting disabled)"
-                                                    : "singular reduced matrix Rbar");
-    }
-    const double bnorm = std::sqrt(nrm2);
+    // The factorization's status and ||b|| go to host slots now and are read
+    // at the first exit test, with its round trip: a singular factorization
+    // or b = 0 then ends the solve there (the first quarter step has run on
+    // them, and x is reset for b = 0).
+    TRY(dots(h, OP_BNORM, {{b, b}}, s, h->ptr<int>(h->L.status)));
+    double bnorm = -1.0;           // read at the first exit test
     HIP_TRY(launch_fill(x, 0.0, n, s));
     auto finish = [&](int code, const char *msg) {
         if (h->ev[4]) {
@@ -518,11 +513,6 @@ int krylov(sap_handle h, int trans, const double *b, double *x, double tol, int3
         if (code == SAP_NOT_CONVERGED) g_err = msg;
         return code;
     };
-    if (bnorm == 0.0) {
-        loc.converged = 1;
-        return finish(SAP_OK, "");
-    }
-
     // r0 = M^{-1} b, rt = r0, u0 = 0, scalars reset; the norm of r0 is read
     // at the first exit test (host slot H_NRM0), saving a round trip
     TRY(precond(h, trans, b, r0, s));
@@ -543,6 +533,8 @@ int krylov(sap_handle h, int trans, const double *b, double *x, double tol, int3
     double pn_last = 0.0, pn_last2 = 0.0;
     int pn_hist = 0;
     // exit test: returns 1 = converged, 2 = restarted, 0 = continue, < 0 error
+    // (described by `why`)
+    const char *why = "breakdown in BiCGStab(2)";
     auto exit_test = [&]() -> int {
         // When this test may converge or restart (the first after a
         // (re)start, or when the last two tests extrapolate below the
@@ -562,6 +554,21 @@ int krylov(sap_handle h, int trans, const double *b, double *x, double tol, int3
             TRY(dots(h, OP_SPEC, {{t, t}}, s));
         }
         TRY(sync_read(h, s, &nrm2, &brk));
+        if (bnorm < 0.0) {
+            loc.n_boosted = (int32_t)h->h_slots[H_NBOOST];
+            if (const int32_t singular = (int32_t)h->h_slots[H_SING]) {
+                napply = 0;
+                why = singular == 1 ? "zero pivot in a diagonal block (boosting disabled)"
+                                    : "singular reduced matrix Rbar";
+                return SAP_ERR_SINGULAR;
+            }
+            bnorm = std::sqrt(h->h_slots[H_BNORM]);
+            if (bnorm == 0.0) {                                  // x = 0, no step counted
+                HIP_TRY(launch_fill(x, 0.0, n, s));
+                napply = 0;
+                return 1;
+            }
+        }
         if (tn_pending) {
             tn_restart = std::sqrt(h->h_slots[H_TRUE]);
             loc.rel_resid_true = tn_restart / bnorm;
@@ -642,7 +649,7 @@ int krylov(sap_handle h, int trans, const double *b, double *x, double tol, int3
         TRY(update(h, UPD_J0, x, OP_EXIT, 1, s));
         loc.n_apply = napply;
         e = exit_test(); loc.n_apply = napply;
-        if (e < 0) return finish(e, "breakdown in BiCGStab(2)");
+        if (e < 0) return finish(e, why);
         if (e == 1) { code = SAP_OK; break; }
         if (e == 2) continue;
         TRY(apply_op(h, trans, r0, r1, s)); ++napply;
@@ -654,7 +661,7 @@ int krylov(sap_handle h, int trans, const double *b, double *x, double tol, int3
         TRY(update(h, UPD_J1, x, OP_EXIT, 1, s));
         loc.n_apply = napply;
         e = exit_test(); loc.n_apply = napply;
-        if (e < 0) return finish(e, "breakdown in BiCGStab(2)");
+        if (e < 0) return finish(e, why);
         if (e == 1) { code = SAP_OK; break; }
         if (e == 2) continue;
         TRY(apply_op(h, trans, r1, r2, s)); ++napply;
@@ -664,7 +671,7 @@ int krylov(sap_handle h, int trans, const double *b, double *x, double tol, int3
         TRY(update(h, UPD_FINAL, x, OP_FINAL, 2, s));
         loc.n_apply = napply;
         e = exit_test(); loc.n_apply = napply;
-        if (e < 0) return finish(e, "breakdown in BiCGStab(2)");
+        if (e < 0) return finish(e, why);
         if (e == 1) { code = SAP_OK; break; }
     }
     loc.n_apply = napply;
@@ -894,15 +901,10 @@ int krylov_cg(sap_handle h, const double *b, double *x, double tol, int32_t maxi
     const double *A = h->a_band;
     const int k = h->opt.k;
     double nrm2 = 0, brk = 0;
-    TRY(dots(h, OP_NORM, {{b, b}}, s, h->ptr<int>(h->L.status)));
-    TRY(sync_read(h, s, &nrm2, &brk));
-    loc.n_boosted = (int32_t)h->h_slots[H_NBOOST];
-    if (const int32_t singular = (int32_t)h->h_slots[H_SING]) {
-        if (st) *st = loc;
-        return fail(SAP_ERR_SINGULAR, singular == 1 ? "zero pivot in a diagonal block (boosting disabled)"
-                                                    : "singular reduced matrix Rbar");
-    }
-    const double bnorm = std::sqrt(nrm2);
+    // the factorization's status and ||b|| are read with the first step's
+    // round trip (a singular factorization or b = 0 ends the solve there)
+    TRY(dots(h, OP_BNORM, {{b, b}}, s, h->ptr<int>(h->L.status)));
+    double bnorm = -1.0;
     HIP_TRY(launch_fill(x, 0.0, n, s));
     int napply = 0, steps = 0;
     auto finish = [&](int code, const char *msg) {
@@ -924,10 +926,6 @@ int krylov_cg(sap_handle h, const double *b, double *x, double tol, int32_t maxi
         if (code == SAP_NOT_CONVERGED) g_err = msg;
         return code;
     };
-    if (bnorm == 0.0) {
-        loc.converged = 1;
-        return finish(SAP_OK, "");
-    }
     // r = b, z = M^{-1} r, p = z, rho = (r, z)
     HIP_TRY(hipMemcpyAsync(r, b, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
     TRY(precond(h, 0, r, z, s));
@@ -943,6 +941,22 @@ int krylov_cg(sap_handle h, const double *b, double *x, double tol, int32_t maxi
         TRY(update(h, UPD_CG_XR, x, OP_EXIT, 1, s));
         ++steps;
         TRY(sync_read(h, s, &nrm2, &brk));
+        if (bnorm < 0.0) {
+            loc.n_boosted = (int32_t)h->h_slots[H_NBOOST];
+            if (const int32_t singular = (int32_t)h->h_slots[H_SING]) {
+                napply = steps = 0;
+                return finish(SAP_ERR_SINGULAR, singular == 1
+                                                    ? "zero pivot in a diagonal block (boosting disabled)"
+                                                    : "singular reduced matrix Rbar");
+            }
+            bnorm = std::sqrt(h->h_slots[H_BNORM]);
+            if (bnorm == 0.0) {                                  // x = 0, no step counted
+                HIP_TRY(launch_fill(x, 0.0, n, s));
+                napply = steps = 0;
+                code = SAP_OK;
+                break;
+            }
+        }
         if (brk != 0.0 || !std::isfinite(nrm2))
             return finish(SAP_ERR_BREAKDOWN, "breakdown in CG (A or M not positive definite)");
         loc.rel_resid_precond = std::sqrt(nrm2) / bnorm;

@@ -60,6 +60,7 @@ enum KrylovOp : int {
     OP_NORM,       // d0=(v,v): publish only
     OP_TRUE,       // d0=(t,t): the true residual at a restart, to host slot H_TRUE
     OP_SPEC,       // d0=(t,t): the true residual ahead of an exit test, to H_SPEC
+    OP_BNORM,      // d0=(b,b): the right-hand side's squared norm, to H_BNORM
     // preconditioned conjugate gradient (SPD A)
     OP_CG_INIT,    // d0=(r,z) d1=(r,r): rho = (r,z), publish ||r||^2
     OP_CG_ALPHA,   // d0=(p,Ap): alpha = rho / (p,Ap), breakdown unless > 0
@@ -76,9 +77,10 @@ enum ScalarSlot : int {
 // H_NRM0: squared norm of the (re)started preconditioned residual (OP_INIT);
 // H_TRUE: squared norm of the true residual a restart started from (OP_TRUE);
 // H_NBOOST, H_SING: the factorization's status words (DotArgs::status);
-// H_SPEC: squared norm of the true residual enqueued ahead of an exit test
+// H_SPEC: squared norm of the true residual enqueued ahead of an exit test;
+// H_BNORM: squared norm of the right-hand side (OP_BNORM)
 enum HostSlot : int { H_NRM2 = 0, H_BREAK = 1, H_NRM0 = 2, H_TRUE = 3, H_NBOOST = 4, H_SING = 5,
-                      H_SPEC = 6, kHostSlots = 8 };
+                      H_SPEC = 6, H_BNORM = 7, kHostSlots = 8 };
 
 struct Partition {
     const int64_t *starts;   // P+1 block boundaries (device)

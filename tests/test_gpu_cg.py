@@ -109,3 +109,35 @@ def test_cg_breakdown_on_indefinite_matrix():
         s.solve_cg(dev(np.ones(2)), tol=1e-10, maxit=5)
     assert e.value.code == sap.SAP_ERR_BREAKDOWN
     s.close()
+
+
+def test_zero_rhs_and_singular_factor_end_at_first_test():
+    """The factorization's status and ||b|| are read at the first exit test:
+    b = 0 still returns x = 0 exactly with no step counted, and a zero pivot
+    with boosting disabled still returns SAP_ERR_SINGULAR, from CG, BiCGStab(2)
+    and the adjoint solve; a refactored handle solves again."""
+    from paper_1509_07919_amd import SapError, sap
+    n, k, p = 3000, 4, 6
+    print("CASE zero-rhs/singular", n, k, p, flush=True)
+    pb = sapgen.make_problem(n, k, d=1.1, seed=57, symmetric=True)
+    s = solver(n, k, p, mode="decoupled", factor_prec="fp64", adjoint=True, boost_eps=-1.0)
+    s.factor(dev(pb.band))
+    zero = torch.zeros(n, dtype=torch.float64, device=DEV)
+    for fn in (s.solve_cg, s.solve, s.solve_adjoint):
+        x, st = fn(zero)
+        assert st.converged and st.iters == 0.0 and np.abs(host(x)).max() == 0.0
+    band = pb.band.copy()
+    band[k * n + 0] = 0.0                        # zero first pivot of block 0
+    s.factor(dev(band))
+    for fn in (s.solve_cg, s.solve, s.solve_adjoint):
+        with pytest.raises(SapError) as e:
+            fn(dev(pb.b))
+        assert e.value.code == sap.SAP_ERR_SINGULAR
+    s.factor(dev(pb.band))
+    x, st = s.solve_cg(dev(pb.b), tol=1e-10)
+    assert st.converged
+    close(host(x), pb.x_true, 1e-8)
+    x, st = s.solve(dev(pb.b), tol=1e-10)
+    assert st.converged
+    close(host(x), pb.x_true, 1e-8)
+    s.close()
