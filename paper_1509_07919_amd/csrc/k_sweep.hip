@@ -847,7 +847,7 @@ __device__ __forceinline__ void xfer_step(double (&p)[KM], const double (&c)[NR]
 // state e_i (pending sum 1 for the i-th step), so its K pending sums at the
 // end form row i of the quarter's transfer X_w.  p[m] holds the pending sum
 // of the m-th step after the current one: one step is x = -p[0]*d,
-// p[m-1] = p[m] + F[j][m]*x.  Coefficient rows are loaded four rows ahead,
+// p[m-1] = p[m] + F[j][m]*x.  Coefficient rows are loaded two rows ahead,
 // coefficient m into lane m mod 16 of each row of sixteen lanes, and each FMA
 // takes its coefficient through a DPP row broadcast.  The chunk's transfer is the product X_0 X_1 X_2 X_3 (a state
 // s maps to s X), formed through two LDS slots.  All of it is FP64 for either
@@ -884,7 +884,7 @@ __global__ __launch_bounds__(256) void k_sweep_xfer(XferArgs<T> a)
     // reaches all lanes through a row broadcast (DPP row_newbcast) folded into
     // the FMA's operand
     constexpr int NR = (KM + 15) / 16;
-    constexpr int D = 4;
+    constexpr int D = 2;                 // two rows ahead: three waves a SIMD at K = 50
     DT fr[D][NR];
     T fn[D][NR];
     // raw loads with no branch and no use before the end of an iteration, so
