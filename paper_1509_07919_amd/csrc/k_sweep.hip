@@ -849,9 +849,10 @@ __device__ __forceinline__ void xfer_step(double (&p)[KM], const double (&c)[NR]
 // of the m-th step after the current one: one step is x = -p[0]*d,
 // p[m-1] = p[m] + F[j][m]*x.  Coefficient rows are loaded two rows ahead,
 // coefficient m into lane m mod 16 of each row of sixteen lanes, and each FMA
-// takes its coefficient through a DPP row broadcast.  The chunk's transfer is the product X_0 X_1 X_2 X_3 (a state
-// s maps to s X), formed through two LDS slots.  All of it is FP64 for either
-// factor precision (FP32 coefficients are widened exactly): see chain_states.
+// takes its coefficient through a DPP row broadcast.  The chunk's transfer is
+// the product X_0 X_1 X_2 X_3 (a state s maps to s X), formed through two LDS
+// slots.  All of it is FP64 for either factor precision (FP32 coefficients
+// are widened exactly): see chain_states.
 template <typename T, int KM>
 __global__ __launch_bounds__(256) void k_sweep_xfer(XferArgs<T> a)
 {
