@@ -139,8 +139,11 @@ int sap_factor(sap_handle h, const double *a_band, void *stream);
  * relative residual ||b - A x||/||b|| <= tol, otherwise the iteration
  * restarts from the current x with the recomputed residual.  maxit bounds
  * the BiCGStab(2) iterations.  b and x: N doubles each, must not overlap.
- * b = 0 gives x = 0 at once.  Returns SAP_OK, SAP_NOT_CONVERGED (x = last
- * iterate), SAP_ERR_BREAKDOWN, SAP_ERR_SINGULAR or SAP_ERR_STATE.
+ * b = 0 gives x = 0 with no iteration counted.  The factorization's status
+ * and ||b|| are read at the first exit test (one host round trip fewer), so
+ * b = 0 and SAP_ERR_SINGULAR come back after one quarter step of work.
+ * Returns SAP_OK, SAP_NOT_CONVERGED (x = last iterate), SAP_ERR_BREAKDOWN,
+ * SAP_ERR_SINGULAR or SAP_ERR_STATE.
  * `st` (host, nullable) receives the statistics. */
 int sap_solve(sap_handle h, const double *b, double *x, double tol,
               int32_t maxit, void *stream, sap_stats *st);
